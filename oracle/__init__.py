@@ -1,0 +1,248 @@
+"""FP64 CPU oracle for the sLLG Heun step (test infrastructure only).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py`` may import this package.  It shares no code with the GPU
+library ``paper_2502_02236_amd``; it loads its own C file ``asd_oracle.c``
+(plain loops, FP64, ``-ffp-contract=off``) through ctypes.
+
+Paper: Gija et al., arXiv 2502.02236 -- Eq. 1 (sLLG), Sec. II thermal field,
+Eq. 2 (exchange), Eq. 3 (anisotropy), Sec. III (spot, write field, Voronoi
+track), Appendix A (L1_0 Fe sublattice), Eq. 6 (moment sums).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "asd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SC, L10 = 0, 1
+SPOT_NONE, SPOT_MOVING, SPOT_LOCKED = 0, 1, 2
+KB = 1.380649e-23
+
+
+def build(force: bool = True) -> str:
+    """Compile asd_oracle.c with gcc (-O2 -ffp-contract=off) into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+P = C.POINTER
+i32p, i64p, u32p, u8p, i8p, f64p = (P(C.c_int32), P(C.c_int64), P(C.c_uint32), P(C.c_uint8),
+                                    P(C.c_int8), P(C.c_double))
+
+
+class OrcSystem(C.Structure):
+    _fields_ = [
+        ("n_sites", C.c_int64), ("row_ptr", i64p), ("col", i32p), ("shell", i8p),
+        ("label", i32p), ("active", u8p), ("px", f64p), ("py", f64p), ("ctr0", u32p),
+        ("sys_id", C.c_uint32), ("hx", C.c_double), ("origin", C.c_int64),
+        ("n_shells", C.c_int), ("J", C.c_double * 4), ("mu_s", C.c_double),
+        ("alpha", C.c_double), ("gamma", C.c_double), ("dt", C.c_double), ("ku", C.c_double),
+        ("ku_grain", f64p), ("B", C.c_double * 3), ("n_bits", C.c_int), ("bits", u8p),
+        ("steps_per_bit", C.c_int64), ("spot_mode", C.c_int), ("T_amb", C.c_double),
+        ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+        ("v", C.c_double), ("seed", C.c_uint64), ("rounds", C.c_int),
+    ]
+
+
+def _declare(L):
+    L.orc_philox_batch.argtypes = [C.c_int, C.c_uint64, u32p, u32p, C.c_int64]
+    L.orc_ln_batch.argtypes = [f64p, f64p, C.c_int64]
+    L.orc_exp_batch.argtypes = [f64p, f64p, C.c_int64]
+    L.orc_sincos2pi_batch.argtypes = [f64p, f64p, f64p, C.c_int64]
+    L.orc_gauss3_batch.argtypes = [C.c_int, C.c_uint64, u32p, u32p, C.c_uint32, C.c_uint32,
+                                   f64p, C.c_int64]
+    L.orc_lattice_sites.argtypes = [C.c_int] * 4
+    L.orc_lattice_sites.restype = C.c_int64
+    L.orc_build_neighbours.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, C.c_double,
+                                       C.c_double, C.c_int, f64p, i64p, i32p, i8p]
+    L.orc_build_neighbours.restype = C.c_int64
+    L.orc_site_positions.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, f64p, f64p]
+    L.orc_voronoi_labels.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, C.c_int, i32p,
+                                     C.c_int, C.c_int64, i32p]
+    L.orc_heun_steps.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int64, C.c_int64]
+    L.orc_heun_steps.restype = C.c_int
+    L.orc_magnetisation.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int, f64p, f64p]
+    L.orc_energy.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int64, f64p]
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+# ---------------------------------------------------------------- noise
+def philox(ctr, seed: int, rounds: int = 10) -> np.ndarray:
+    """Philox4x32-R of each counter row (uint32[n,4]); key = (lo32 seed, hi32 seed)."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(rounds, seed, _ptr(ctr, u32p), _ptr(out, u32p), len(ctr))
+    return out
+
+
+def ln(u) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty_like(u)
+    lib().orc_ln_batch(_ptr(u, f64p), _ptr(out, f64p), u.size)
+    return out
+
+
+def exp(x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_exp_batch(_ptr(x, f64p), _ptr(out, f64p), x.size)
+    return out
+
+
+def sincos2pi(u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    s, c = np.empty_like(u), np.empty_like(u)
+    lib().orc_sincos2pi_batch(_ptr(u, f64p), _ptr(s, f64p), _ptr(c, f64p), u.size)
+    return s, c
+
+
+def gauss3(sites, steps, sys_id: int, seed: int, stage: int = 0, rounds: int = 10) -> np.ndarray:
+    sites = np.ascontiguousarray(sites, dtype=np.uint32).ravel()
+    steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.uint32), sites.shape))
+    g = np.empty((sites.size, 3), dtype=np.float64)
+    lib().orc_gauss3_batch(rounds, seed, _ptr(sites, u32p), _ptr(steps, u32p), sys_id, stage,
+                           _ptr(g, f64p), sites.size)
+    return g
+
+
+# ---------------------------------------------------------------- lattice
+def lattice_sites(kind: int, nx: int, ny: int, nz: int) -> int:
+    return int(lib().orc_lattice_sites(kind, nx, ny, nz))
+
+
+def neighbours(kind, nx, ny, nz, periodic, a, c, radii):
+    """Brute-force neighbour shells: (row_ptr int64[n+1], col int32, shell int8)."""
+    per = np.ascontiguousarray(periodic, dtype=np.int32)
+    rad = np.ascontiguousarray(radii, dtype=np.float64)
+    n = lattice_sites(kind, nx, ny, nz)
+    row = np.empty(n + 1, dtype=np.int64)
+    tot = lib().orc_build_neighbours(kind, nx, ny, nz, _ptr(per, i32p), a, c, len(rad),
+                                     _ptr(rad, f64p), _ptr(row, i64p), None, None)
+    col = np.empty(max(tot, 1), dtype=np.int32)
+    sh = np.empty(max(tot, 1), dtype=np.int8)
+    lib().orc_build_neighbours(kind, nx, ny, nz, _ptr(per, i32p), a, c, len(rad),
+                               _ptr(rad, f64p), _ptr(row, i64p), _ptr(col, i32p), _ptr(sh, i8p))
+    return row, col[:tot], sh[:tot]
+
+
+def site_positions(kind, nx, ny, nz, a):
+    n = lattice_sites(kind, nx, ny, nz)
+    px, py = np.empty(n), np.empty(n)
+    lib().orc_site_positions(kind, nx, ny, nz, a, _ptr(px, f64p), _ptr(py, f64p))
+    return px, py
+
+
+def voronoi_labels(kind, nx, ny, nz, periodic_xy, Q, seeds_xy, w_units) -> np.ndarray:
+    seeds = np.ascontiguousarray(seeds_xy, dtype=np.int32).reshape(-1, 2)
+    per = np.ascontiguousarray(periodic_xy, dtype=np.int32)
+    lab = np.empty(lattice_sites(kind, nx, ny, nz), dtype=np.int32)
+    lib().orc_voronoi_labels(kind, nx, ny, nz, _ptr(per, i32p), Q, _ptr(seeds, i32p), len(seeds),
+                             int(w_units), _ptr(lab, i32p))
+    return lab
+
+
+# ---------------------------------------------------------------- dynamics
+class System:
+    """One lattice evolved by the oracle's Heun sLLG.
+
+    Arrays are kept alive on the instance; ``S`` is float64[3, n_sites].
+    """
+
+    def __init__(self, *, row_ptr, col, shell, label, px, py, ctr0, n_shells, J, mu_s, alpha,
+                 gamma, dt, ku, ku_grain=None, B=(0.0, 0.0, 0.0), bits=None, steps_per_bit=0,
+                 spot_mode=SPOT_NONE, T_amb=0.0, T_peak=0.0, fwhm=0.0, x0=0.0, y0=0.0, v=0.0,
+                 seed=1, rounds=10, sys_id=0, active=None, hx=0.0, origin=0):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.shell = np.ascontiguousarray(shell, dtype=np.int8)
+        self.label = np.ascontiguousarray(label, dtype=np.int32)
+        self.px = np.ascontiguousarray(px, dtype=np.float64)
+        self.py = np.ascontiguousarray(py, dtype=np.float64)
+        self.ctr0 = np.ascontiguousarray(ctr0, dtype=np.uint32)
+        self.ku_grain = None if ku_grain is None else np.ascontiguousarray(ku_grain, np.float64)
+        self.bits = None if bits is None else np.ascontiguousarray(bits, dtype=np.uint8)
+        self.active = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+        n = len(self.label)
+        s = OrcSystem()
+        s.n_sites = n
+        s.row_ptr, s.col, s.shell = _ptr(self.row_ptr, i64p), _ptr(self.col, i32p), _ptr(self.shell, i8p)
+        s.label = _ptr(self.label, i32p)
+        s.active = _ptr(self.active, u8p)
+        s.px, s.py = _ptr(self.px, f64p), _ptr(self.py, f64p)
+        s.ctr0 = _ptr(self.ctr0, u32p)
+        s.sys_id = sys_id
+        s.hx, s.origin = hx, origin
+        s.n_shells = n_shells
+        for k in range(4):
+            s.J[k] = J[k] if k < len(J) else 0.0
+        s.mu_s, s.alpha, s.gamma, s.dt, s.ku = mu_s, alpha, gamma, dt, ku
+        s.ku_grain = _ptr(self.ku_grain, f64p)
+        for k in range(3):
+            s.B[k] = B[k]
+        s.n_bits = 0 if self.bits is None else len(self.bits)
+        s.bits = _ptr(self.bits, u8p)
+        s.steps_per_bit = steps_per_bit
+        s.spot_mode = spot_mode
+        s.T_amb, s.T_peak, s.fwhm, s.x0, s.y0, s.v = T_amb, T_peak, fwhm, x0, y0, v
+        s.seed, s.rounds = seed, rounds
+        self._s = s
+
+    def set_active(self, active, origin=None):
+        self.active = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+        self._s.active = _ptr(self.active, u8p)
+        if origin is not None:
+            self._s.origin = origin
+
+    def heun(self, S, step0: int, nsteps: int) -> np.ndarray:
+        S = np.array(S, dtype=np.float64, copy=True).reshape(3, -1)
+        Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+        rc = lib().orc_heun_steps(C.byref(self._s), _ptr(Sx, f64p), _ptr(Sy, f64p),
+                                  _ptr(Sz, f64p), step0, nsteps)
+        if rc != 0:
+            raise MemoryError("oracle step allocation failed")
+        return np.stack([Sx, Sy, Sz])
+
+    def magnetisation(self, S, n_grains: int):
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(3, -1)
+        Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+        pg = np.zeros((max(n_grains, 1), 4))
+        tot = np.zeros(4)
+        lib().orc_magnetisation(C.byref(self._s), _ptr(Sx, f64p), _ptr(Sy, f64p), _ptr(Sz, f64p),
+                                n_grains, _ptr(pg, f64p), _ptr(tot, f64p))
+        return pg[:n_grains], tot
+
+    def energy(self, S, step: int) -> np.ndarray:
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(3, -1)
+        Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+        out = np.zeros(4)
+        lib().orc_energy(C.byref(self._s), _ptr(Sx, f64p), _ptr(Sy, f64p), _ptr(Sz, f64p), step,
+                         _ptr(out, f64p))
+        return out

@@ -1,0 +1,637 @@
+/*
+ * asd_oracle.c -- plain, slow, FP64 CPU oracle for the stochastic
+ * Landau-Lifshitz-Gilbert (sLLG) Heun step of atomistic spin dynamics.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file.  It shares no code,
+ * header, table or constant generator with the GPU library; the two agree
+ * only because both follow the same written definitions.
+ *
+ * What it follows (Gija et al., "Multiscale micromagnetic / atomistic
+ * modeling of heat assisted magnetic recording", arXiv 2502.02236):
+ *   - Eq. 1   sLLG equation (Gilbert form), integrated here in the
+ *             algebraically equivalent explicit Landau-Lifshitz form with
+ *             prefactor gamma/(1+alpha^2), by Heun's predictor-corrector
+ *             with renormalisation of every stage (the paper names no
+ *             atomistic integrator; Heun is this project's reading).
+ *   - Sec. II thermal field: Gaussian, zero mean, standard deviation
+ *             sqrt(2 alpha kB T / (gamma mu_s dt)) (tesla form of the
+ *             paper's A/m expression), drawn fresh every time step and
+ *             shared by the predictor and the corrector.
+ *   - Eq. 2   exchange field (1/mu_s) sum_j J_ij S_j over neighbour shells
+ *             (SC: 6 nearest neighbours; L1_0 Fe sublattice: shells).
+ *   - Eq. 3   uniaxial anisotropy field (2 k_u/mu_s)(S.z) z.
+ *   - Sec. II/III Zeeman write field with bit-timed polarity and a
+ *             Gaussian laser-spot temperature profile (Fig. 2).
+ *   - Sec. II Voronoi construction of exchange-decoupled grains.
+ *   - Eq. 6   moment sums (used here as per-grain magnetisation sums).
+ *
+ * Floating point: FP64, compiled with -ffp-contract=off.  The
+ * transcendentals the noise and the temperature need (ln, sin/cos of
+ * 2*pi*u, exp) are this file's own fixed-order series built from + - * /
+ * only, so that the result is a function of the definitions alone and not
+ * of a vendor math library.  Random numbers: Philox4x32 with R rounds as
+ * defined by Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "asd_oracle.h"
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-R (Salmon et al. 2011, Sec. 4.3 / Table 2).             */
+/* One round: the two 32x32->64 products of the S-box, xor with the  */
+/* key and the other two words, then the key is bumped by the Weyl   */
+/* constants.  The first round uses the key as given.                */
+/* ------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32(int rounds, uint32_t k0, uint32_t k1, const uint32_t ctr[4],
+                    uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    for (int r = 0; r < rounds; ++r) {
+        if (r > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+void orc_philox_batch(int rounds, uint64_t seed, const uint32_t *ctr, uint32_t *out,
+                      int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        orc_philox4x32(rounds, (uint32_t)seed, (uint32_t)(seed >> 32), ctr + 4 * i,
+                       out + 4 * i);
+}
+
+/* ------------------------------------------------------------------ */
+/* Portable FP64 transcendentals (own definitions, fixed order).      */
+/* ------------------------------------------------------------------ */
+static const double LN2_HI = 6.93147180369123816490e-01; /* 22 trailing zero bits */
+static const double LN2_LO = 1.90821492927058770002e-10;
+static const double SQRT_HALF = 0.70710678118654752440;
+static const double PIO2 = 1.57079632679489661923;
+static const double INV_LN2 = 1.44269504088896340736;
+
+/* ln(u) for u > 0 finite: u = m 2^e with m in [sqrt(1/2), sqrt(2)),
+ * ln m = 2 atanh(z), z = (m-1)/(m+1), atanh series through z^21. */
+double orc_ln(double u)
+{
+    int e;
+    double m = frexp(u, &e); /* exact: m in [0.5, 1) */
+    if (m < SQRT_HALF) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double z = (m - 1.0) / (m + 1.0);
+    double z2 = z * z;
+    double p = 1.0 / 21.0;
+    p = 1.0 / 19.0 + z2 * p;
+    p = 1.0 / 17.0 + z2 * p;
+    p = 1.0 / 15.0 + z2 * p;
+    p = 1.0 / 13.0 + z2 * p;
+    p = 1.0 / 11.0 + z2 * p;
+    p = 1.0 / 9.0 + z2 * p;
+    p = 1.0 / 7.0 + z2 * p;
+    p = 1.0 / 5.0 + z2 * p;
+    p = 1.0 / 3.0 + z2 * p;
+    p = 1.0 + z2 * p;
+    double lnm = (2.0 * z) * p;
+    double de = (double)e;
+    return de * LN2_HI + (de * LN2_LO + lnm);
+}
+
+/* sin(2 pi u), cos(2 pi u) for u in [0, 1): exact quadrant split of 4u,
+ * then Taylor polynomials on th = (4u - q) pi/2 in [-pi/4, pi/4]:
+ * sin th = th - th^3 P(th^2), P through the th^21 term;
+ * cos th = 1 - th^2 C(th^2), C through the th^20 term. */
+void orc_sincos2pi(double u, double *s_out, double *c_out)
+{
+    double t = 4.0 * u;
+    double q = floor(t + 0.5);
+    double x = t - q;
+    double th = x * PIO2;
+    double th2 = th * th;
+    double ps = -1.0 / 51090942171709440000.0;
+    ps = 1.0 / 121645100408832000.0 + th2 * ps;
+    ps = -1.0 / 355687428096000.0 + th2 * ps;
+    ps = 1.0 / 1307674368000.0 + th2 * ps;
+    ps = -1.0 / 6227020800.0 + th2 * ps;
+    ps = 1.0 / 39916800.0 + th2 * ps;
+    ps = -1.0 / 362880.0 + th2 * ps;
+    ps = 1.0 / 5040.0 + th2 * ps;
+    ps = -1.0 / 120.0 + th2 * ps;
+    ps = 1.0 / 6.0 + th2 * ps;
+    double s = th - (th * th2) * ps;
+    double pc = -1.0 / 2432902008176640000.0;
+    pc = 1.0 / 6402373705728000.0 + th2 * pc;
+    pc = -1.0 / 20922789888000.0 + th2 * pc;
+    pc = 1.0 / 87178291200.0 + th2 * pc;
+    pc = -1.0 / 479001600.0 + th2 * pc;
+    pc = 1.0 / 3628800.0 + th2 * pc;
+    pc = -1.0 / 40320.0 + th2 * pc;
+    pc = 1.0 / 720.0 + th2 * pc;
+    pc = -1.0 / 24.0 + th2 * pc;
+    pc = 0.5 + th2 * pc;
+    double c = 1.0 - th2 * pc;
+    int quad = ((int)q) & 3;
+    switch (quad) {
+    case 0: *s_out = s; *c_out = c; break;
+    case 1: *s_out = c; *c_out = -s; break;
+    case 2: *s_out = -s; *c_out = -c; break;
+    default: *s_out = -c; *c_out = s; break;
+    }
+}
+
+/* exp(x) for finite x <= 0: x = k ln2 + r with k = floor(x/ln2 + 1/2),
+ * r reduced with the split ln2, Taylor polynomial through r^13, then an
+ * exact scaling by 2^k.  Below -700 the result is 0. */
+double orc_exp(double x)
+{
+    if (x < -700.0)
+        return 0.0;
+    double k = floor(x * INV_LN2 + 0.5);
+    double r = (x - k * LN2_HI) - k * LN2_LO;
+    double p = 1.0 / 6227020800.0;
+    p = 1.0 / 479001600.0 + r * p;
+    p = 1.0 / 39916800.0 + r * p;
+    p = 1.0 / 3628800.0 + r * p;
+    p = 1.0 / 362880.0 + r * p;
+    p = 1.0 / 40320.0 + r * p;
+    p = 1.0 / 5040.0 + r * p;
+    p = 1.0 / 720.0 + r * p;
+    p = 1.0 / 120.0 + r * p;
+    p = 1.0 / 24.0 + r * p;
+    p = 1.0 / 6.0 + r * p;
+    p = 0.5 + r * p;
+    p = 1.0 + r * p;
+    p = 1.0 + r * p;
+    return ldexp(p, (int)k);
+}
+
+/* ------------------------------------------------------------------ */
+/* Gaussian triple for one site and step (Box-Muller on Philox words) */
+/* counter = (site, step, system, stage), key = (lo32 seed, hi32 seed) */
+/* u_r = (w + 1/2) 2^-32 in (0,1), u_t = w 2^-32 in [0,1)             */
+/* (gx, gy) = r (cos, sin)(2 pi u_t) from (w0, w1); gz = r cos(...) of */
+/* (w2, w3); the fourth Gaussian is not used.                          */
+/* ------------------------------------------------------------------ */
+static const double TWO_M32 = 2.3283064365386962890625e-10; /* 2^-32 */
+
+static void box_muller(uint32_t wr, uint32_t wt, double *g_cos, double *g_sin)
+{
+    double ur = ((double)wr + 0.5) * TWO_M32;
+    double ut = (double)wt * TWO_M32;
+    double r = sqrt(-2.0 * orc_ln(ur));
+    double s, c;
+    orc_sincos2pi(ut, &s, &c);
+    *g_cos = r * c;
+    *g_sin = r * s;
+}
+
+void orc_gauss3(int rounds, uint64_t seed, uint32_t site, uint32_t step, uint32_t sys,
+                uint32_t stage, double g[3])
+{
+    uint32_t ctr[4] = {site, step, sys, stage};
+    uint32_t w[4];
+    orc_philox4x32(rounds, (uint32_t)seed, (uint32_t)(seed >> 32), ctr, w);
+    double gx, gy, gz, unused;
+    box_muller(w[0], w[1], &gx, &gy);
+    box_muller(w[2], w[3], &gz, &unused);
+    g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+void orc_ln_batch(const double *u, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_ln(u[i]);
+}
+void orc_exp_batch(const double *x, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_exp(x[i]);
+}
+void orc_sincos2pi_batch(const double *u, double *s, double *c, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) orc_sincos2pi(u[i], s + i, c + i);
+}
+void orc_gauss3_batch(int rounds, uint64_t seed, const uint32_t *site, const uint32_t *step,
+                      uint32_t sys, uint32_t stage, double *g, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) orc_gauss3(rounds, seed, site[i], step[i], sys, stage, g + 3 * i);
+}
+
+/* ------------------------------------------------------------------ */
+/* Lattices by brute-force geometry.                                  */
+/* Sites carry integer coordinates (X, Y, Z) in units (hx, hy, hz).   */
+/* SC: X = x, Y = y, Z = z, units (a, a, a).                          */
+/* L1_0 Fe sublattice (Appendix A, Fig. 5): Fe at the corners and the */
+/* centre of the a x a face of every a x a x c cell: X = 2x + s,      */
+/* Y = 2y + s, Z = z with units (a/2, a/2, c), s = 0, 1.              */
+/* Site index: SC x + nx (y + ny z); L1_0 2 (x + nx (y + ny z)) + s.  */
+/* Neighbours: every site within the cutoff, found by scanning a box  */
+/* of integer offsets, with minimum-image wrap on periodic axes; each */
+/* is assigned to the shell whose radius it matches.  Row order:      */
+/* shell ascending, then the offset (dZ, dY, dX) lexicographically.   */
+/* ------------------------------------------------------------------ */
+static void site_coords(int kind, int nx, int ny, int64_t i, int64_t *X, int64_t *Y, int64_t *Z)
+{
+    if (kind == ORC_SC) {
+        *X = i % nx;
+        *Y = (i / nx) % ny;
+        *Z = i / ((int64_t)nx * ny);
+    } else {
+        int64_t cell = i / 2, s = i % 2;
+        int64_t cx = cell % nx, cy = (cell / nx) % ny, cz = cell / ((int64_t)nx * ny);
+        *X = 2 * cx + s;
+        *Y = 2 * cy + s;
+        *Z = cz;
+    }
+}
+
+/* returns site index or -1 if no site sits at (X, Y, Z) */
+static int64_t site_at(int kind, int nx, int ny, int nz, int64_t X, int64_t Y, int64_t Z)
+{
+    if (kind == ORC_SC) {
+        if (X < 0 || X >= nx || Y < 0 || Y >= ny || Z < 0 || Z >= nz) return -1;
+        return X + (int64_t)nx * (Y + (int64_t)ny * Z);
+    }
+    if (X < 0 || X >= 2 * (int64_t)nx || Y < 0 || Y >= 2 * (int64_t)ny || Z < 0 || Z >= nz)
+        return -1;
+    if (((X - Y) % 2) != 0) return -1;
+    int64_t s = X % 2;
+    int64_t cx = (X - s) / 2, cy = (Y - s) / 2;
+    return 2 * (cx + (int64_t)nx * (cy + (int64_t)ny * Z)) + s;
+}
+
+static int64_t wrap(int64_t v, int64_t L) { return ((v % L) + L) % L; }
+
+typedef struct {
+    int shell;
+    int64_t dz, dy, dx;
+    int64_t j;
+} nb_entry;
+
+static int nb_cmp(const void *a, const void *b)
+{
+    const nb_entry *p = (const nb_entry *)a, *q = (const nb_entry *)b;
+    if (p->shell != q->shell) return p->shell < q->shell ? -1 : 1;
+    if (p->dz != q->dz) return p->dz < q->dz ? -1 : 1;
+    if (p->dy != q->dy) return p->dy < q->dy ? -1 : 1;
+    if (p->dx != q->dx) return p->dx < q->dx ? -1 : 1;
+    return 0;
+}
+
+int64_t orc_lattice_sites(int kind, int nx, int ny, int nz)
+{
+    return (kind == ORC_SC ? 1 : 2) * (int64_t)nx * ny * nz;
+}
+
+/* Pass row_ptr/col/shell = NULL to get the number of neighbour entries. */
+int64_t orc_build_neighbours(int kind, int nx, int ny, int nz, const int periodic[3], double a,
+                             double c, int n_shells, const double *radius, int64_t *row_ptr,
+                             int32_t *col, int8_t *shell)
+{
+    double hx = kind == ORC_SC ? a : 0.5 * a;
+    double hy = hx;
+    double hz = kind == ORC_SC ? a : c;
+    double rmax = 0.0;
+    for (int s = 0; s < n_shells; ++s) rmax = radius[s] > rmax ? radius[s] : rmax;
+    int64_t mx = (int64_t)ceil(rmax / hx) + 1, my = (int64_t)ceil(rmax / hy) + 1,
+            mz = (int64_t)ceil(rmax / hz) + 1;
+    int64_t LX = kind == ORC_SC ? nx : 2 * (int64_t)nx;
+    int64_t LY = kind == ORC_SC ? ny : 2 * (int64_t)ny;
+    int64_t LZ = nz;
+    int64_t n = orc_lattice_sites(kind, nx, ny, nz);
+    nb_entry *buf = (nb_entry *)malloc(sizeof(nb_entry) * (size_t)((2 * mx + 1) * (2 * my + 1) * (2 * mz + 1)));
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t X, Y, Z;
+        site_coords(kind, nx, ny, i, &X, &Y, &Z);
+        int cnt = 0;
+        for (int64_t dz = -mz; dz <= mz; ++dz)
+            for (int64_t dy = -my; dy <= my; ++dy)
+                for (int64_t dx = -mx; dx <= mx; ++dx) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    int64_t Xj = X + dx, Yj = Y + dy, Zj = Z + dz;
+                    if (periodic[0]) Xj = wrap(Xj, LX);
+                    if (periodic[1]) Yj = wrap(Yj, LY);
+                    if (periodic[2]) Zj = wrap(Zj, LZ);
+                    int64_t j = site_at(kind, nx, ny, nz, Xj, Yj, Zj);
+                    if (j < 0 || j == i) continue;
+                    double ddx = (double)dx * hx, ddy = (double)dy * hy, ddz = (double)dz * hz;
+                    double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+                    for (int s = 0; s < n_shells; ++s) {
+                        if (fabs(d - radius[s]) <= 1e-6 * radius[s]) {
+                            buf[cnt].shell = s;
+                            buf[cnt].dz = dz; buf[cnt].dy = dy; buf[cnt].dx = dx;
+                            buf[cnt].j = j;
+                            ++cnt;
+                            break;
+                        }
+                    }
+                }
+        qsort(buf, (size_t)cnt, sizeof(nb_entry), nb_cmp);
+        if (row_ptr) row_ptr[i] = total;
+        for (int k = 0; k < cnt; ++k) {
+            if (col) col[total + k] = (int32_t)buf[k].j;
+            if (shell) shell[total + k] = (int8_t)buf[k].shell;
+        }
+        total += cnt;
+    }
+    if (row_ptr) row_ptr[n] = total;
+    free(buf);
+    return total;
+}
+
+/* in-plane site positions in metres, in the frame of the stored lattice */
+void orc_site_positions(int kind, int nx, int ny, int nz, double a, double *px, double *py)
+{
+    double h = kind == ORC_SC ? a : 0.5 * a;
+    int64_t n = orc_lattice_sites(kind, nx, ny, nz);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t X, Y, Z;
+        site_coords(kind, nx, ny, i, &X, &Y, &Z);
+        px[i] = (double)X * h;
+        py[i] = (double)Y * h;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Columnar Voronoi grains (Sec. II "Voronoi construction", Sec. III). */
+/* Integer geometry in units of a/Q (SC) or a/(2Q) half-cells (L1_0). */
+/* Site p = (X Q, Y Q).  Label = index of the nearest seed (squared   */
+/* distance, minimum image on periodic axes; ties to the lower index). */
+/* A site is non-magnetic (label -1) when some other seed j has        */
+/* (d_j^2 - d_g^2)^2 < w^2 |s_j - s_g|^2, i.e. it lies closer than w/2 */
+/* to the bisector of its own seed g and seed j.  Brute force over all */
+/* seeds.                                                              */
+/* ------------------------------------------------------------------ */
+static int64_t min_image(int64_t d, int64_t L, int periodic)
+{
+    if (!periodic) return d;
+    d = ((d % L) + L) % L;
+    if (2 * d > L) d -= L;
+    return d;
+}
+
+void orc_voronoi_labels(int kind, int nx, int ny, int nz, const int periodic[2], int Q,
+                        const int32_t *seeds_xy, int n_seeds, int64_t w_units, int32_t *labels)
+{
+    int64_t LX = (kind == ORC_SC ? nx : 2 * (int64_t)nx) * (int64_t)Q;
+    int64_t LY = (kind == ORC_SC ? ny : 2 * (int64_t)ny) * (int64_t)Q;
+    int64_t n = orc_lattice_sites(kind, nx, ny, nz);
+    int64_t *dxs = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_seeds);
+    int64_t *dys = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_seeds);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t X, Y, Z;
+        site_coords(kind, nx, ny, i, &X, &Y, &Z);
+        int64_t px = X * Q, py = Y * Q;
+        int g = -1;
+        int64_t best = 0;
+        for (int k = 0; k < n_seeds; ++k) {
+            dxs[k] = min_image(px - seeds_xy[2 * k], LX, periodic[0]);
+            dys[k] = min_image(py - seeds_xy[2 * k + 1], LY, periodic[1]);
+            int64_t d2 = dxs[k] * dxs[k] + dys[k] * dys[k];
+            if (g < 0 || d2 < best) {
+                g = k;
+                best = d2;
+            }
+        }
+        int magnetic = 1;
+        for (int k = 0; k < n_seeds && magnetic; ++k) {
+            if (k == g) continue;
+            int64_t d2 = dxs[k] * dxs[k] + dys[k] * dys[k];
+            int64_t diff = d2 - best;
+            int64_t sx = dxs[g] - dxs[k], sy = dys[g] - dys[k];
+            int64_t sep2 = sx * sx + sy * sy;
+            if (diff * diff < w_units * w_units * sep2) magnetic = 0;
+        }
+        labels[i] = magnetic ? g : -1;
+    }
+    free(dxs);
+    free(dys);
+}
+
+/* ------------------------------------------------------------------ */
+/* sLLG right-hand side in Landau-Lifshitz form (Eq. 1 rewritten):    */
+/*   dS/dt = gp (S x B + alpha S x (S x B)),  gp = -gamma/(1+alpha^2) */
+/* ------------------------------------------------------------------ */
+static void ll_rhs(double gp, double alpha, const double S[3], const double B[3], double f[3])
+{
+    double cx = S[1] * B[2] - S[2] * B[1];
+    double cy = S[2] * B[0] - S[0] * B[2];
+    double cz = S[0] * B[1] - S[1] * B[0];
+    double dx = S[1] * cz - S[2] * cy;
+    double dy = S[2] * cx - S[0] * cz;
+    double dz = S[0] * cy - S[1] * cx;
+    f[0] = gp * (cx + alpha * dx);
+    f[1] = gp * (cy + alpha * dy);
+    f[2] = gp * (cz + alpha * dz);
+}
+
+static void normalise(double v[3])
+{
+    double n = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    v[0] = v[0] / n;
+    v[1] = v[1] / n;
+    v[2] = v[2] / n;
+}
+
+/* write-field polarity at step n (bit sequence by field polarity) */
+static double polarity(const orc_system *s, int64_t n)
+{
+    if (s->n_bits <= 0 || s->steps_per_bit <= 0) return 1.0;
+    int64_t k = (n / s->steps_per_bit) % s->n_bits;
+    return s->bits[k] ? 1.0 : -1.0;
+}
+
+/* Gaussian laser spot (Sec. III, Fig. 2): T = Tamb + (Tpk-Tamb) exp(-r^2/2s^2),
+ * s = FWHM / (2 sqrt(2 ln 2)), r the in-plane distance to the spot centre. */
+static double site_temperature(const orc_system *s, int64_t i, int64_t n)
+{
+    if (s->spot_mode == ORC_SPOT_NONE) return s->T_amb;
+    double xc;
+    if (s->spot_mode == ORC_SPOT_MOVING)
+        xc = s->x0 + s->v * ((double)n * s->dt);
+    else
+        xc = (double)s->origin * s->hx + s->x0;
+    double sd = s->fwhm / 2.3548200450309493;
+    double inv2s2 = 1.0 / ((2.0 * sd) * sd);
+    double dx = s->px[i] - xc;
+    double dy = s->py[i] - s->y0;
+    double q = (dx * dx + dy * dy) * inv2s2;
+    return s->T_amb + (s->T_peak - s->T_amb) * orc_exp(-q);
+}
+
+static int magnetic(const orc_system *s, int64_t i) { return s->label[i] >= 0; }
+static int evolves(const orc_system *s, int64_t i)
+{
+    return magnetic(s, i) && (s->active == NULL || s->active[i]);
+}
+
+/* B at site i for spin configuration (Sx,Sy,Sz): Eq. 2 grouped by shell,
+ * + Eq. 3 + write field + thermal field, in this order. */
+static void field(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+                  int64_t i, double pol, const double bth[3], double B[3])
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int sh = 0; sh < s->n_shells; ++sh) {
+        double part[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
+            if (s->shell[k] != sh) continue;
+            int64_t j = s->col[k];
+            if (s->label[j] != s->label[i]) continue; /* exchange-decoupled grains */
+            part[0] = part[0] + Sx[j];
+            part[1] = part[1] + Sy[j];
+            part[2] = part[2] + Sz[j];
+        }
+        double cex = s->J[sh] / s->mu_s;
+        acc[0] = acc[0] + cex * part[0];
+        acc[1] = acc[1] + cex * part[1];
+        acc[2] = acc[2] + cex * part[2];
+    }
+    double ku = s->ku_grain ? s->ku_grain[s->label[i]] : s->ku;
+    double can = (2.0 * ku) / s->mu_s;
+    double ban[3] = {0.0, 0.0, can * Sz[i]};
+    for (int k = 0; k < 3; ++k)
+        B[k] = ((acc[k] + ban[k]) + pol * s->B[k]) + bth[k];
+}
+
+int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int64_t step0,
+                   int64_t nsteps)
+{
+    int64_t n = s->n_sites;
+    double *Px = (double *)malloc(sizeof(double) * (size_t)n);
+    double *Py = (double *)malloc(sizeof(double) * (size_t)n);
+    double *Pz = (double *)malloc(sizeof(double) * (size_t)n);
+    double *f0 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *bth = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!Px || !Py || !Pz || !f0 || !bth) {
+        free(Px); free(Py); free(Pz); free(f0); free(bth);
+        return -1;
+    }
+    double gp = -s->gamma / (1.0 + s->alpha * s->alpha);
+    double h = 0.5 * s->dt;
+    double cth = ((2.0 * s->alpha) * ORC_KB) / ((s->gamma * s->mu_s) * s->dt);
+
+    for (int64_t t = 0; t < nsteps; ++t) {
+        int64_t step = step0 + t;
+        double pol = polarity(s, step);
+        /* thermal field: one Gaussian triple per site and step */
+        for (int64_t i = 0; i < n; ++i) {
+            if (!evolves(s, i)) continue;
+            double T = site_temperature(s, i, step);
+            double sigma = sqrt(cth * T);
+            double g[3];
+            orc_gauss3(s->rounds, s->seed, s->ctr0[i], (uint32_t)step, s->sys_id, 0u, g);
+            bth[3 * i + 0] = sigma * g[0];
+            bth[3 * i + 1] = sigma * g[1];
+            bth[3 * i + 2] = sigma * g[2];
+        }
+        /* predictor at every site before any corrector */
+        for (int64_t i = 0; i < n; ++i) {
+            if (!evolves(s, i)) {
+                Px[i] = Sx[i]; Py[i] = Sy[i]; Pz[i] = Sz[i];
+                continue;
+            }
+            double B[3], f[3], S[3] = {Sx[i], Sy[i], Sz[i]};
+            field(s, Sx, Sy, Sz, i, pol, bth + 3 * i, B);
+            ll_rhs(gp, s->alpha, S, B, f);
+            double P[3] = {S[0] + s->dt * f[0], S[1] + s->dt * f[1], S[2] + s->dt * f[2]};
+            normalise(P);
+            Px[i] = P[0]; Py[i] = P[1]; Pz[i] = P[2];
+            f0[3 * i + 0] = f[0]; f0[3 * i + 1] = f[1]; f0[3 * i + 2] = f[2];
+        }
+        /* corrector with the predicted configuration and the same noise */
+        for (int64_t i = 0; i < n; ++i) {
+            if (!evolves(s, i)) continue;
+            double B[3], f[3], Sp[3] = {Px[i], Py[i], Pz[i]};
+            field(s, Px, Py, Pz, i, pol, bth + 3 * i, B);
+            ll_rhs(gp, s->alpha, Sp, B, f);
+            double Q[3] = {Sx[i] + h * (f0[3 * i + 0] + f[0]), Sy[i] + h * (f0[3 * i + 1] + f[1]),
+                           Sz[i] + h * (f0[3 * i + 2] + f[2])};
+            normalise(Q);
+            Sx[i] = Q[0]; Sy[i] = Q[1]; Sz[i] = Q[2];
+        }
+    }
+    free(Px); free(Py); free(Pz); free(f0); free(bth);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Reductions: Neumaier-compensated sums.                             */
+/* ------------------------------------------------------------------ */
+typedef struct { double s, c; } nsum;
+static void nadd(nsum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double nval(const nsum *a) { return a->s + a->c; }
+
+/* per grain g (label g >= 0): (sum Sx, sum Sy, sum Sz, count) into out[4 g..];
+ * total over all magnetic sites into tot[4] (Eq. 6 moment sums / mu_s) */
+void orc_magnetisation(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+                       int n_grains, double *per_grain, double tot[4])
+{
+    nsum *acc = (nsum *)calloc((size_t)(4 * (n_grains + 1)), sizeof(nsum));
+    for (int64_t i = 0; i < s->n_sites; ++i) {
+        int g = s->label[i];
+        if (g < 0) continue;
+        double v[4] = {Sx[i], Sy[i], Sz[i], 1.0};
+        for (int k = 0; k < 4; ++k) {
+            if (g < n_grains) nadd(&acc[4 * g + k], v[k]);
+            nadd(&acc[4 * n_grains + k], v[k]);
+        }
+    }
+    for (int g = 0; g < n_grains; ++g)
+        for (int k = 0; k < 4; ++k) per_grain[4 * g + k] = nval(&acc[4 * g + k]);
+    for (int k = 0; k < 4; ++k) tot[k] = nval(&acc[4 * n_grains + k]);
+    free(acc);
+}
+
+/* energy (J) of the Hamiltonian whose field is Eqs. 2-3 + write field:
+ * E = -1/2 sum_i sum_j J_ij S_i.S_j - sum_i k_u S_iz^2 - sum_i mu_s B.S_i,
+ * over magnetic sites (active or frozen); out = (exchange, anisotropy,
+ * Zeeman, total). */
+void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+                int64_t step, double out[4])
+{
+    nsum ex = {0, 0}, an = {0, 0}, ze = {0, 0};
+    double pol = polarity(s, step);
+    for (int64_t i = 0; i < s->n_sites; ++i) {
+        if (!magnetic(s, i)) continue;
+        for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
+            int64_t j = s->col[k];
+            if (s->label[j] != s->label[i]) continue;
+            double d = Sx[i] * Sx[j] + Sy[i] * Sy[j] + Sz[i] * Sz[j];
+            nadd(&ex, -0.5 * s->J[s->shell[k]] * d);
+        }
+        double ku = s->ku_grain ? s->ku_grain[s->label[i]] : s->ku;
+        nadd(&an, -ku * Sz[i] * Sz[i]);
+        nadd(&ze, -s->mu_s * pol * (s->B[0] * Sx[i] + s->B[1] * Sy[i] + s->B[2] * Sz[i]));
+    }
+    out[0] = nval(&ex);
+    out[1] = nval(&an);
+    out[2] = nval(&ze);
+    out[3] = (out[0] + out[1]) + out[2];
+}

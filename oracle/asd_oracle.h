@@ -1,0 +1,86 @@
+/*
+ * asd_oracle.h -- declarations of the FP64 CPU oracle (test infrastructure
+ * only; see asd_oracle.c).  Nothing in the GPU library includes this file.
+ */
+#ifndef ASD_ORACLE_H
+#define ASD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_SC 0
+#define ORC_L10 1
+
+#define ORC_SPOT_NONE 0   /* uniform T_amb */
+#define ORC_SPOT_MOVING 1 /* centre x0 + v n dt (absolute frame) */
+#define ORC_SPOT_LOCKED 2 /* centre origin*hx + x0 (moves with the window) */
+
+/* Boltzmann constant, J/K (exact SI value) */
+#define ORC_KB 1.380649e-23
+
+typedef struct orc_system {
+    /* lattice and neighbour shells (CSR) */
+    int64_t n_sites;
+    const int64_t *row_ptr; /* [n_sites + 1] */
+    const int32_t *col;     /* neighbour site */
+    const int8_t *shell;    /* shell of each neighbour entry */
+    const int32_t *label;   /* grain label per site, -1 = non-magnetic */
+    const uint8_t *active;  /* 1 = evolves this step, 0 = frozen; NULL = all */
+    const double *px, *py;  /* in-plane positions (m) */
+    const uint32_t *ctr0;   /* Philox counter word 0 per site (absolute index) */
+    uint32_t sys_id;        /* Philox counter word 2 */
+    double hx;              /* x unit of the window origin (m) */
+    int64_t origin;         /* window origin in x units (locked spot) */
+    /* material */
+    int n_shells;
+    double J[4];            /* exchange per shell (J) */
+    double mu_s, alpha, gamma, dt;
+    double ku;              /* uniaxial anisotropy (J/atom) */
+    const double *ku_grain; /* per-grain k_u or NULL */
+    /* drive */
+    double B[3];            /* write field (T) */
+    int n_bits;             /* polarity bits (0 = constant +1) */
+    const uint8_t *bits;
+    int64_t steps_per_bit;
+    int spot_mode;
+    double T_amb, T_peak, fwhm, x0, y0, v;
+    /* noise */
+    uint64_t seed;
+    int rounds;
+} orc_system;
+
+void orc_philox4x32(int rounds, uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4]);
+void orc_philox_batch(int rounds, uint64_t seed, const uint32_t *ctr, uint32_t *out, int64_t n);
+double orc_ln(double u);
+void orc_sincos2pi(double u, double *s, double *c);
+double orc_exp(double x);
+void orc_gauss3(int rounds, uint64_t seed, uint32_t site, uint32_t step, uint32_t sys,
+                uint32_t stage, double g[3]);
+void orc_ln_batch(const double *u, double *out, int64_t n);
+void orc_exp_batch(const double *x, double *out, int64_t n);
+void orc_sincos2pi_batch(const double *u, double *s, double *c, int64_t n);
+void orc_gauss3_batch(int rounds, uint64_t seed, const uint32_t *site, const uint32_t *step,
+                      uint32_t sys, uint32_t stage, double *g, int64_t n);
+
+int64_t orc_lattice_sites(int kind, int nx, int ny, int nz);
+int64_t orc_build_neighbours(int kind, int nx, int ny, int nz, const int periodic[3], double a,
+                             double c, int n_shells, const double *radius, int64_t *row_ptr,
+                             int32_t *col, int8_t *shell);
+void orc_site_positions(int kind, int nx, int ny, int nz, double a, double *px, double *py);
+void orc_voronoi_labels(int kind, int nx, int ny, int nz, const int periodic[2], int Q,
+                        const int32_t *seeds_xy, int n_seeds, int64_t w_units, int32_t *labels);
+
+int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int64_t step0,
+                   int64_t nsteps);
+void orc_magnetisation(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+                       int n_grains, double *per_grain, double tot[4]);
+void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+                int64_t step, double out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,61 @@
+"""Build oracle systems from workload definitions (oracle side only).
+
+Everything here goes through ``oracle`` (lattice, neighbour shells, Voronoi
+labels, positions); the GPU library is never consulted.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import workloads as W
+
+
+def oracle_labels(w: W.Workload, seeds=None, nx_extent=None) -> np.ndarray:
+    nx = nx_extent if nx_extent is not None else (w.track_nx or w.nx)
+    if not w.grains:
+        return np.zeros(oracle.lattice_sites(w.kind, nx, w.ny, w.nz), dtype=np.int32)
+    if seeds is None:
+        seeds = W.voronoi_seeds(w, nx)
+    per = (int(w.bc[0] == W.BC_PERIODIC), int(w.bc[1] == W.BC_PERIODIC))
+    return oracle.voronoi_labels(w.kind, nx, w.ny, w.nz, per, W.Q_UNITS, seeds, w.w_units)
+
+
+def oracle_system(w: W.Workload, labels=None, ku_grain=None, sys_id=0, active=None, origin=0,
+                  T_amb=None) -> oracle.System:
+    """Oracle system over the full stored lattice (track length when x is a track)."""
+    nx = w.track_nx or w.nx
+    per = [int(b == W.BC_PERIODIC) for b in w.bc]
+    row, col, sh = oracle.neighbours(w.kind, nx, w.ny, w.nz, per, w.a, w.c, w.shell_radii)
+    px, py = oracle.site_positions(w.kind, nx, w.ny, w.nz, w.a)
+    if labels is None:
+        labels = oracle_labels(w)
+    n = len(labels)
+    return oracle.System(
+        row_ptr=row, col=col, shell=sh, label=labels, px=px, py=py,
+        ctr0=np.arange(n, dtype=np.uint32), n_shells=len(w.J), J=w.J, mu_s=w.mu_s,
+        alpha=w.alpha, gamma=w.gamma, dt=w.dt, ku=w.ku, ku_grain=ku_grain, B=w.B,
+        bits=w.bits, steps_per_bit=w.steps_per_bit, spot_mode=w.spot_mode,
+        T_amb=w.T_amb if T_amb is None else T_amb, T_peak=w.T_peak, fwhm=w.fwhm, x0=w.x0,
+        y0=w.y0, v=w.v, seed=w.seed, rounds=10, sys_id=sys_id, active=active, hx=w.hx,
+        origin=origin)
+
+
+def window_mask(w: W.Workload, origin: int) -> np.ndarray:
+    """1 for sites whose x column lies inside the window [origin, origin + nx)."""
+    nx = w.track_nx or w.nx
+    n = oracle.lattice_sites(w.kind, nx, w.ny, w.nz)
+    idx = np.arange(n)
+    cell = idx if w.kind == W.SC else idx // 2
+    x = cell % nx
+    return ((x >= origin) & (x < origin + w.nx)).astype(np.uint8)
+
+
+def free_spins_system(n: int, *, mu_s, alpha, gamma, dt, ku, B, T, seed=7, sys_id=0):
+    """n uncoupled spins (no neighbours), uniform temperature T."""
+    return oracle.System(
+        row_ptr=np.zeros(n + 1, dtype=np.int64), col=np.zeros(1, np.int32),
+        shell=np.zeros(1, np.int8), label=np.zeros(n, np.int32), px=np.zeros(n), py=np.zeros(n),
+        ctr0=np.arange(n, dtype=np.uint32), n_shells=0, J=(), mu_s=mu_s, alpha=alpha,
+        gamma=gamma, dt=dt, ku=ku, B=B, spot_mode=oracle.SPOT_NONE, T_amb=T, seed=seed,
+        sys_id=sys_id)

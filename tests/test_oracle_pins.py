@@ -1,0 +1,453 @@
+"""Pins of the FP64 oracle against what the mathematics and the paper fix.
+
+None of these re-types the oracle's own formula: each compares it with an
+independent implementation (rocRAND's Philox engine, libm via numpy, scipy's
+KD-tree), a closed form (damped precession, Heun's amplification factor of a
+spin wave, the Langevin function, the exact nearest-neighbour correlation of
+the classical Heisenberg chain, Boltzmann quadrature) or an invariant
+(unit length, energy decrease at T = 0, neighbour symmetry).
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.spatial import cKDTree
+
+import oracle
+import workloads as W
+from oracle_build import free_spins_system, oracle_labels, oracle_system
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ------------------------------------------------------------------ Philox
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND reference")
+    exe = str(tmp_path_factory.mktemp("philox") / "philox_ref")
+    subprocess.run([hipcc, "-O1", os.path.join(HERE, "helpers", "philox_rocrand_ref.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+
+    def run(seeds, ctr):
+        lines = "".join(f"{int(s)} {c[0]} {c[1]} {c[2]} {c[3]}\n" for s, c in zip(seeds, ctr))
+        out = subprocess.run([exe], input=lines, capture_output=True, text=True, check=True).stdout
+        return np.array([[int(v) for v in l.split()] for l in out.strip().splitlines()],
+                        dtype=np.uint64).astype(np.uint32)
+    return run
+
+
+def test_philox_matches_rocrand_engine(rocrand_ref):
+    rng = np.random.default_rng(11)
+    edge = [0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFE, 0xFFFFFFFF]
+    ctr = [[a, b, c, d] for a in edge[::2] for b in edge[1::2] for c in edge[::3] for d in edge[1::3]]
+    ctr += rng.integers(0, 2**32, size=(400, 4), dtype=np.uint64).tolist()
+    ctr = np.array(ctr, dtype=np.uint64).astype(np.uint32)
+    seeds = [0, 1, 2, 0xFFFFFFFF, 0x100000000, 0xFFFFFFFFFFFFFFFF, 0x0123456789ABCDEF]
+    for seed in seeds:
+        ref = rocrand_ref([seed] * len(ctr), ctr)
+        got = oracle.philox(ctr, seed, rounds=10)
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_philox_statistics():
+    n = 1 << 18
+    ctr = np.zeros((n, 4), dtype=np.uint32)
+    ctr[:, 0] = np.arange(n)
+    ctr[:, 1] = 17
+    w = oracle.philox(ctr, 1234)
+    # every bit of every word balanced within 5 sigma
+    for k in range(4):
+        bits = ((w[:, k, None] >> np.arange(32, dtype=np.uint32)) & 1).mean(0)
+        assert np.all(np.abs(bits - 0.5) < 5 * 0.5 / math.sqrt(n))
+    # top byte chi^2 (255 dof): mean 255, sd ~22.6
+    hist = np.bincount((w[:, 0] >> 24).astype(np.int64), minlength=256)
+    chi2 = ((hist - n / 256) ** 2 / (n / 256)).sum()
+    assert chi2 < 255 + 6 * math.sqrt(2 * 255)
+    # adjacent counters uncorrelated
+    u = w[:, 2].astype(np.float64) / 2**32
+    r = np.corrcoef(u[:-1], u[1:])[0, 1]
+    assert abs(r) < 5 / math.sqrt(n)
+
+
+# ------------------------------------------------------------------ transcendentals
+def _ulps(a, b):
+    return np.abs(a - b) / np.spacing(np.maximum(np.abs(b), 1e-300))
+
+
+def test_ln_against_libm():
+    rng = np.random.default_rng(3)
+    w = rng.integers(0, 2**32, 200000, dtype=np.uint64)
+    u = (w.astype(np.float64) + 0.5) * 2.0**-32      # the exact uniforms Box-Muller uses
+    u = np.concatenate([u, [2.0**-33, 0.5, 1.0 - 2.0**-33, math.sqrt(0.5), 1.0]])
+    got = oracle.ln(u)
+    ref = np.log(u)
+    ok = ref != 0
+    assert np.max(_ulps(got[ok], ref[ok])) <= 4
+    assert oracle.ln(np.array([1.0]))[0] == 0.0
+    for k in range(1, 40):
+        assert abs(oracle.ln(np.array([2.0**-k]))[0] + k * math.log(2.0)) <= 2e-16 * k
+
+
+def test_sincos2pi_against_libm():
+    rng = np.random.default_rng(4)
+    u = rng.integers(0, 2**32, 200000, dtype=np.uint64).astype(np.float64) * 2.0**-32
+    s, c = oracle.sincos2pi(u)
+    # reference in x87 extended precision (64-bit significand): 2 pi u carries ~1e-19 error
+    two_pi = np.longdouble("6.283185307179586476925286766559")
+    ang = two_pi * u.astype(np.longdouble)
+    assert np.max(np.abs(s - np.sin(ang).astype(np.float64))) <= 2.3e-16
+    assert np.max(np.abs(c - np.cos(ang).astype(np.float64))) <= 2.3e-16
+    s, c = oracle.sincos2pi(np.array([0.0, 0.25, 0.5, 0.75]))
+    np.testing.assert_array_equal(s, [0.0, 1.0, 0.0, -1.0])
+    np.testing.assert_array_equal(c, [1.0, 0.0, -1.0, 0.0])
+    s, c = oracle.sincos2pi(u[:1000])
+    assert np.max(np.abs(s * s + c * c - 1)) < 4e-16
+
+
+def test_exp_against_libm():
+    x = -np.random.default_rng(5).random(200000) * 60.0
+    got = oracle.exp(x)
+    assert np.max(_ulps(got, np.exp(x))) <= 4
+    assert oracle.exp(np.array([0.0]))[0] == 1.0
+    assert oracle.exp(np.array([-800.0]))[0] == 0.0
+
+
+def test_gaussian_moments():
+    n = 400000
+    g = oracle.gauss3(np.arange(n), 3, 0, 99).ravel()
+    m = len(g)
+    assert abs(g.mean()) < 5 / math.sqrt(m)
+    assert abs(g.var() - 1) < 5 * math.sqrt(2 / m)
+    assert abs((g**4).mean() - 3) < 5 * math.sqrt(96 / m)
+    assert abs((g**3).mean()) < 5 * math.sqrt(15 / m)
+    # the three components are independent
+    G = g.reshape(-1, 3)
+    c = np.corrcoef(G.T)
+    assert np.max(np.abs(c - np.eye(3))) < 5 / math.sqrt(n)
+
+
+def test_gaussian_follows_box_muller_of_philox_words():
+    """gx, gy, gz are the Box-Muller pairs of (w0,w1) and (w2,w3) (libm evaluation)."""
+    sites = np.arange(1000)
+    g = oracle.gauss3(sites, 12, 3, 77)
+    ctr = np.stack([sites, np.full(1000, 12), np.full(1000, 3), np.zeros(1000)], 1)
+    w = oracle.philox(ctr, 77).astype(np.float64)
+    ur0 = (w[:, 0] + 0.5) / 2**32
+    ut0 = w[:, 1] / 2**32
+    ur1 = (w[:, 2] + 0.5) / 2**32
+    ut1 = w[:, 3] / 2**32
+    r0, r1 = np.sqrt(-2 * np.log(ur0)), np.sqrt(-2 * np.log(ur1))
+    ref = np.stack([r0 * np.cos(2 * np.pi * ut0), r0 * np.sin(2 * np.pi * ut0),
+                    r1 * np.cos(2 * np.pi * ut1)], 1)
+    np.testing.assert_allclose(g, ref, rtol=1e-14, atol=1e-14)
+
+
+# ------------------------------------------------------------------ lattices
+def _kdtree_pairs(points, box, rmax):
+    tree = cKDTree(points, boxsize=box)
+    return tree.query_pairs(rmax * (1 + 1e-9), output_type="ndarray")
+
+
+@pytest.mark.parametrize("kind,dims,per", [
+    (W.SC, (7, 6, 5), (1, 1, 0)), (W.SC, (5, 4, 6), (0, 1, 1)), (W.L10, (6, 5, 4), (1, 1, 0)),
+    (W.L10, (4, 6, 3), (0, 0, 0)),
+])
+def test_neighbours_against_kdtree(kind, dims, per):
+    nx, ny, nz = dims
+    a, c = (0.3e-9, 0.3e-9) if kind == W.SC else (0.385e-9, 0.371e-9)
+    w = W.Workload("t", kind=kind, nx=nx, ny=ny, nz=nz, a=a, c=c,
+                   J=(1e-21,) if kind == W.SC else (1, 1, 1, 1))
+    radii = w.shell_radii
+    row, col, sh = oracle.neighbours(kind, nx, ny, nz, per, a, c, radii)
+    n = len(row) - 1
+    px, py = oracle.site_positions(kind, nx, ny, nz, a)
+    idx = np.arange(n)
+    zc = (idx if kind == W.SC else idx // 2) // (nx * ny)
+    pz = zc * (a if kind == W.SC else c)
+    Lx = nx * a
+    Ly = ny * a
+    Lz = nz * (a if kind == W.SC else c)
+    pts = np.stack([px, py, pz], 1) / 1e-9
+    # kd-tree periodic boxes need open axes padded far beyond the cutoff
+    box = [L / 1e-9 if p else 10 * L / 1e-9 + 10 for L, p in zip((Lx, Ly, Lz), per)]
+    pairs = _kdtree_pairs(pts, box, max(radii) / 1e-9)
+    ref = {(min(i, j), max(i, j)) for i, j in pairs}
+    got = set()
+    for i in range(n):
+        for k in range(row[i], row[i + 1]):
+            got.add((min(i, col[k]), max(i, col[k])))
+    assert got == ref
+    # symmetric lists, shell counts of a bulk site
+    for i in range(n):
+        for k in range(row[i], row[i + 1]):
+            j = col[k]
+            assert i in col[row[j]:row[j + 1]]
+    if kind == W.SC and all(per):
+        assert np.all(np.diff(row) == 6)
+    if kind == W.L10 and per == (1, 1, 0):
+        z = idx // 2 // (nx * ny)
+        mid = np.where((z > 0) & (z < nz - 1))[0]
+        for i in mid[:50]:
+            counts = np.bincount(sh[row[i]:row[i + 1]], minlength=4)
+            assert counts.tolist() == [4, 2, 4, 8]
+
+
+def test_voronoi_against_kdtree_and_bisector_distance():
+    w = W.c2_granular_slab().scaled(nx=80, ny=72, nz=1)
+    seeds = W.voronoi_seeds(w)
+    lab = oracle_labels(w, seeds)
+    Q = W.Q_UNITS
+    LX, LY = w.nx * Q, w.ny * Q
+    idx = np.arange(w.nx * w.ny)
+    P = np.stack([(idx % w.nx) * Q, (idx // w.nx) * Q], 1).astype(np.float64)
+    tree = cKDTree(seeds.astype(np.float64), boxsize=[LX, LY])
+    d, nearest = tree.query(P, k=2)
+    clear = d[:, 1] - d[:, 0] > 1e-6      # ties resolved by index are excluded
+    g = np.where(lab >= 0, lab, -1)
+    # magnetic sites carry the nearest seed
+    m = (lab >= 0) & clear
+    assert np.all(g[m] == nearest[m, 0])
+    # boundary: distance to the nearest bisector, from projection geometry
+    S = seeds.astype(np.float64)
+    near = nearest[:, 0]
+    dd = np.empty(len(P))
+    for i in range(len(P)):
+        p = P[i]
+        sg = S[near[i]]
+        dg = (p - sg + [LX / 2, LY / 2]) % [LX, LY] - [LX / 2, LY / 2]
+        sg_img = p - dg
+        best = np.inf
+        for k in range(len(S)):
+            if k == near[i]:
+                continue
+            dk = (p - S[k] + [LX / 2, LY / 2]) % [LX, LY] - [LX / 2, LY / 2]
+            sk_img = p - dk
+            mid = 0.5 * (sg_img + sk_img)
+            nrm = (sk_img - sg_img) / np.linalg.norm(sk_img - sg_img)
+            best = min(best, abs(np.dot(p - mid, nrm)))
+        dd[i] = best
+    half = w.w_units / 2.0
+    decided = np.abs(dd - half) > 1e-6
+    assert np.all((lab[decided] < 0) == (dd[decided] < half))
+    # 1 nm boundaries occupy a sizeable but minor fraction of an 8 nm-grain slab
+    frac = (lab < 0).mean()
+    assert 0.1 < frac < 0.35
+
+
+def test_grain_size_distribution_c2():
+    """Achieved interior grain diameters of the C2 recipe: mean near 8 nm, log-sd near 0.15."""
+    w = W.c2_granular_slab().scaled(nz=1)
+    lab = oracle_labels(w)
+    cnt = np.bincount(lab[lab >= 0])
+    cnt = cnt[cnt > 0]
+    D = np.sqrt(4 * cnt * w.a * w.a / np.pi)
+    assert 7.0e-9 < D.mean() < 9.0e-9
+    assert 0.10 < np.log(D).std() < 0.22
+
+
+# ------------------------------------------------------------------ dynamics
+MU_S = 3.23 * W.MU_B
+GAMMA = 1.76e11
+
+
+def _single_spin(theta0, phi0, B, alpha, dt, steps):
+    s = free_spins_system(1, mu_s=MU_S, alpha=alpha, gamma=GAMMA, dt=dt, ku=0.0,
+                          B=(0.0, 0.0, B), T=0.0)
+    S0 = np.array([[math.sin(theta0) * math.cos(phi0)], [math.sin(theta0) * math.sin(phi0)],
+                   [math.cos(theta0)]])
+    return s.heun(S0, 0, steps)[:, 0]
+
+
+def _closed_form(theta0, phi0, B, alpha, t):
+    gp = GAMMA / (1 + alpha * alpha)
+    th = 2 * math.atan(math.tan(theta0 / 2) * math.exp(-alpha * gp * B * t))
+    ph = phi0 + gp * B * t
+    return np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+
+
+def test_damped_precession_closed_form_and_order():
+    theta0, phi0, B, alpha = 2.5, 0.3, 5.0, 0.1
+    t = 2e-12
+    errs = []
+    for dt in (4e-15, 2e-15, 1e-15):
+        steps = int(round(t / dt))
+        S = _single_spin(theta0, phi0, B, alpha, dt, steps)
+        errs.append(np.max(np.abs(S - _closed_form(theta0, phi0, B, alpha, t))))
+    assert errs[-1] < 1e-6
+    o1, o2 = math.log2(errs[0] / errs[1]), math.log2(errs[1] / errs[2])
+    assert abs(o1 - 2) < 0.1 and abs(o2 - 2) < 0.1
+    S = _single_spin(theta0, phi0, B, alpha, 1e-17, 2000)
+    assert np.max(np.abs(S - _closed_form(theta0, phi0, B, alpha, 2e-14))) < 1e-10
+
+
+def test_spin_wave_phase_matches_heun_amplification():
+    """Linear spin wave on a periodic SC lattice at T = 0: each step multiplies the
+    transverse amplitude by Heun's factor 1 + z + z^2/2, z = (i - alpha) w dt, with
+    w = gamma' [B + 2 ku/mu_s + (J/mu_s) sum_j (1 - cos k.r_j)] (Eq. 2 with Eq. 3)."""
+    nx, ny, nz = 16, 8, 4
+    a, J, ku, B, alpha, dt = 0.3e-9, 6.7e-21, 2.6e-22, 0.8, 0.02, 1e-15
+    w = W.Workload("sw", nx=nx, ny=ny, nz=nz, a=a, J=(J,), bc=(1, 1, 1), ku=ku,
+                   B=(0.0, 0.0, B), alpha=alpha, T_amb=0.0)
+    sysm = oracle_system(w, T_amb=0.0)
+    idx = np.arange(nx * ny * nz)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    for (mx, my, mz) in [(1, 0, 0), (3, 2, 1), (8, 4, 2)]:
+        kx, ky, kz = 2 * np.pi * mx / nx, 2 * np.pi * my / ny, 2 * np.pi * mz / nz
+        ph = kx * x + ky * y + kz * z
+        eps = 1e-6
+        S0 = np.stack([eps * np.cos(ph), eps * np.sin(ph), np.ones_like(ph)])
+        S0 /= np.sqrt((S0 ** 2).sum(0))
+        steps = 20
+        S = sysm.heun(S0, 0, steps)
+        psi0 = (S0[0] + 1j * S0[1]) * np.exp(-1j * ph)
+        psi = (S[0] + 1j * S[1]) * np.exp(-1j * ph)
+        ratio = (psi / psi0).mean()
+        gp = GAMMA / (1 + alpha * alpha)
+        omega = gp * (B + 2 * ku / MU_S + (J / MU_S) * 2 * ((1 - math.cos(kx)) + (1 - math.cos(ky)) + (1 - math.cos(kz))))
+        zz = (1j - alpha) * omega * dt
+        expect = (1 + zz + zz * zz / 2) ** steps
+        assert abs(ratio / expect - 1) < 1e-6, (mx, my, mz, ratio, expect)
+
+
+def test_spin_wave_l10_shells():
+    """Same check on the L1_0 Fe sublattice with four shells: the dispersion sums every
+    shell's (J_s/mu_s)(1 - cos k.r_j) over its neighbour vectors."""
+    nx, ny, nz = 8, 8, 4
+    a, c = 0.385e-9, 0.371e-9
+    Js = (6.0e-21, 1.2e-21, 0.5e-21, 0.2e-21)
+    B, alpha, dt = 0.8, 0.02, 0.5e-15
+    w = W.Workload("swl", kind=W.L10, nx=nx, ny=ny, nz=nz, a=a, c=c, J=Js, bc=(1, 1, 1), ku=0.0,
+                   B=(0.0, 0.0, B), alpha=alpha, dt=dt, T_amb=0.0)
+    sysm = oracle_system(w, T_amb=0.0)
+    n = 2 * nx * ny * nz
+    px, py = oracle.site_positions(W.L10, nx, ny, nz, a)
+    pz = (np.arange(n) // 2 // (nx * ny)) * c
+    # wave vectors commensurate with the periodic box
+    for (mx, my, mz) in [(1, 0, 0), (2, 3, 1), (4, 4, 2)]:
+        k = np.array([2 * np.pi * mx / (nx * a), 2 * np.pi * my / (ny * a), 2 * np.pi * mz / (nz * c)])
+        ph = k[0] * px + k[1] * py + k[2] * pz
+        eps = 1e-6
+        S0 = np.stack([eps * np.cos(ph), eps * np.sin(ph), np.ones_like(ph)])
+        S0 /= np.sqrt((S0 ** 2).sum(0))
+        steps = 20
+        S = sysm.heun(S0, 0, steps)
+        ratio = ((S[0] + 1j * S[1]) / (S0[0] + 1j * S0[1])).mean()
+        vecs = {0: [(a / 2, a / 2, 0), (a / 2, -a / 2, 0), (-a / 2, a / 2, 0), (-a / 2, -a / 2, 0)],
+                1: [(0, 0, c), (0, 0, -c)],
+                2: [(a, 0, 0), (-a, 0, 0), (0, a, 0), (0, -a, 0)],
+                3: [(sx * a / 2, sy * a / 2, sz * c) for sx in (1, -1) for sy in (1, -1) for sz in (1, -1)]}
+        bex = sum(Js[s] / MU_S * sum(1 - math.cos(np.dot(k, v)) for v in vecs[s]) for s in range(4))
+        omega = GAMMA / (1 + alpha * alpha) * (B + bex)
+        zz = (1j - alpha) * omega * dt
+        expect = (1 + zz + zz * zz / 2) ** steps
+        assert abs(ratio / expect - 1) < 1e-6, (mx, my, mz)
+
+
+def test_unit_length_after_every_step():
+    w = W.c1_plain_sc()
+    sysm = oracle_system(w)
+    S = W.initial_spins(w.n_sites, 1)
+    for step in range(5):
+        S = sysm.heun(S, step, 1)
+        assert np.max(np.abs(np.sqrt((S ** 2).sum(0)) - 1)) <= 4 * 2.0**-52
+
+
+def test_energy_decreases_at_zero_temperature():
+    w = W.c1_plain_sc().scaled(T_amb=0.0, alpha=0.3, B=(0.0, 0.0, 0.5))
+    sysm = oracle_system(w, T_amb=0.0)
+    S = W.random_spins(w.n_sites, 3)
+    E = [sysm.energy(S, 0)[3]]
+    for step in range(40):
+        S = sysm.heun(S, step, 1)
+        E.append(sysm.energy(S, step + 1)[3])
+    dE = np.diff(E)
+    assert np.all(dE < 1e-3 * abs(E[0]) * 1e-3)
+    assert E[-1] < E[0]
+
+
+def test_langevin_function_single_spins():
+    """Uncoupled spins in B z at temperature T: <S_z> = coth x - 1/x, x = mu_s B / kB T,
+    independently of alpha (fluctuation-dissipation of the thermal field of Sec. II)."""
+    n, B, T = 2048, 100.0, 100.0
+    xarg = MU_S * B / (W.KB * T)
+    expect = 1 / math.tanh(xarg) - 1 / xarg
+    for alpha in (1.0, 0.5):
+        s = free_spins_system(n, mu_s=MU_S, alpha=alpha, gamma=GAMMA, dt=0.5e-15, ku=0.0,
+                              B=(0.0, 0.0, B), T=T, seed=21)
+        S = np.stack([np.zeros(n), np.zeros(n), np.ones(n)])
+        S = s.heun(S, 0, 600)
+        acc = []
+        for blk in range(12):
+            S = s.heun(S, 600 + 200 * blk, 200)
+            acc.append(S[2].mean())
+        m = np.mean(acc)
+        err = np.std(acc) / math.sqrt(len(acc))
+        assert abs(m - expect) < 4 * err + 0.01, (alpha, m, expect, err)
+
+
+def test_boltzmann_with_anisotropy():
+    """<S_z> and <S_z^2> of a single anisotropic spin in a field against quadrature of
+    exp[(k_u cos^2 t + mu_s B cos t)/kB T] (Eq. 3 + Zeeman + thermal field)."""
+    n, B, T, ku = 2048, 20.0, 100.0, 2.6e-22
+    s = free_spins_system(n, mu_s=MU_S, alpha=1.0, gamma=GAMMA, dt=0.5e-15, ku=ku,
+                          B=(0.0, 0.0, B), T=T, seed=22)
+    beta = 1 / (W.KB * T)
+    wfun = lambda c: math.exp(beta * (ku * c * c + MU_S * B * c))
+    Z = integrate.quad(wfun, -1, 1)[0]
+    m1 = integrate.quad(lambda c: c * wfun(c), -1, 1)[0] / Z
+    m2 = integrate.quad(lambda c: c * c * wfun(c), -1, 1)[0] / Z
+    S = np.stack([np.zeros(n), np.zeros(n), np.ones(n)])
+    S = s.heun(S, 0, 600)
+    a1, a2 = [], []
+    for blk in range(12):
+        S = s.heun(S, 600 + 200 * blk, 200)
+        a1.append(S[2].mean())
+        a2.append((S[2] ** 2).mean())
+    for acc, ref in ((a1, m1), (a2, m2)):
+        err = np.std(acc) / math.sqrt(len(acc))
+        assert abs(np.mean(acc) - ref) < 4 * err + 0.01, (np.mean(acc), ref)
+
+
+def test_heisenberg_chain_nearest_neighbour_correlation():
+    """Classical Heisenberg ring at zero field: <S_i.S_i+1> = coth K - 1/K, K = J/kB T
+    (exact in the thermodynamic limit).  Pins the exchange sign and strength together
+    with the thermal-field variance."""
+    n, J = 4096, 6.7e-21
+    for K in (1.0, 2.0):
+        T = J / (W.KB * K)
+        w = W.Workload("chain", nx=n, ny=1, nz=1, bc=(1, 0, 0), J=(J,), ku=0.0, B=(0.0, 0.0, 0.0),
+                       alpha=1.0, dt=0.25e-15, T_amb=T, seed=31)
+        sysm = oracle_system(w)
+        S = W.random_spins(n, 5)
+        S = sysm.heun(S, 0, 1500)
+        acc = []
+        for blk in range(10):
+            S = sysm.heun(S, 1500 + 150 * blk, 150)
+            acc.append((S * np.roll(S, -1, axis=1)).sum(0).mean())
+        expect = 1 / math.tanh(K) - 1 / K
+        err = np.std(acc) / math.sqrt(len(acc))
+        assert abs(np.mean(acc) - expect) < 4 * err + 0.01, (K, np.mean(acc), expect)
+
+
+def test_eq8_exchange_from_curie_temperature():
+    """Eq. 8 worked numbers (Sec. III): J = 3 kB T_C / (eps z)."""
+    Tc = 710.0
+    assert abs(3 * W.KB * Tc / (0.72 * 6) / 6.8e-21 - 1) < 2e-3
+    assert abs(3 * W.KB * Tc / (0.78 * 10) / 3.77e-21 - 1) < 1e-3
+
+
+def test_noise_depends_on_absolute_site_step_and_system():
+    """Counter layout: the thermal field of a site is a function of (seed, site, step,
+    system) only; frozen (inactive) sites and window position do not change it."""
+    g1 = oracle.gauss3(np.arange(10), 5, 0, 1)
+    g2 = oracle.gauss3(np.arange(10), 5, 1, 1)
+    g3 = oracle.gauss3(np.arange(10), 6, 0, 1)
+    g4 = oracle.gauss3(np.arange(10), 5, 0, 2)
+    for other in (g2, g3, g4):
+        assert np.all(np.abs(g1 - other) > 0)
