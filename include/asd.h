@@ -1,0 +1,241 @@
+/*
+ * asd.h -- C ABI of libasd: the stochastic Landau-Lifshitz-Gilbert (sLLG)
+ * Heun time step of atomistic spin dynamics on MI355X (gfx950).
+ *
+ * Method (Gija et al., "Multiscale micromagnetic / atomistic modeling of
+ * heat assisted magnetic recording", arXiv 2502.02236):
+ *   - spins of fixed length evolved by the sLLG equation (Eq. 1), written
+ *     in Landau-Lifshitz form dS/dt = -gamma/(1+alpha^2) [S x B + alpha
+ *     S x (S x B)] and integrated by Heun's predictor-corrector with
+ *     renormalisation to unit length after each stage;
+ *   - B = exchange (Eq. 2, grouped by neighbour shell) + uniaxial
+ *     anisotropy along z (Eq. 3) + write field (Sec. III: polarity carries
+ *     the bit pattern) + Langevin thermal field of standard deviation
+ *     sqrt(2 alpha kB T / (gamma mu_s dt)) (Sec. II), with T from a
+ *     Gaussian laser spot (Sec. III, Fig. 2);
+ *   - exchange-decoupled Voronoi grains separated by non-magnetic
+ *     boundaries (Sec. II, Sec. III);
+ *   - a simulation window that moves along a frozen track in steps of one
+ *     lattice column, its ends exchange-coupled to the track (Sec. II);
+ *   - simple-cubic or L1_0 Fe-sublattice lattices (Sec. II, Appendix A).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns ASD_OK (0) or a negative ASD_E* code; nothing
+ *     throws or aborts across the ABI.  Arguments are validated before any
+ *     work is enqueued.  The text of the last error of a handle is kept and
+ *     returned by asd_last_error.
+ *   - Memory ownership: the caller owns all device memory.  The library
+ *     never allocates device memory: it carves everything it needs out of
+ *     one caller-provided device workspace (asd_workspace_bytes tells the
+ *     size).  The caller owns the HIP stream and every host buffer; input
+ *     descriptors are copied at asd_create and may be freed afterwards.
+ *   - All device work is enqueued on the stream given at asd_create, in
+ *     order; calls that return host data synchronise that stream.
+ *   - A handle is not thread-safe.
+ *   - Spin arrays are structure-of-arrays: [3][n_stored] (Sx block, Sy
+ *     block, Sz block), x fastest.  SC site index: x + sx (y + ny z); L1_0:
+ *     2 (x + sx (y + ny z)) + s with s = 0 at the cell corner and s = 1 at
+ *     the centre of the a x a face.  sx = track_nx for a track system, nx
+ *     otherwise.  Element type is double (ASD_FP64) or float (ASD_FP32).
+ */
+#ifndef ASD_H
+#define ASD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define ASD_OK 0
+#define ASD_EINVAL (-1)       /* invalid argument or descriptor */
+#define ASD_ENOMEM (-2)       /* workspace smaller than asd_workspace_bytes */
+#define ASD_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define ASD_ESTATE (-4)       /* call not valid in the handle's state */
+#define ASD_ENONFINITE (-5)   /* a reduction met a non-finite spin */
+#define ASD_EUNSUPPORTED (-6) /* valid request this build cannot serve */
+
+/* ---- enumerations ---- */
+#define ASD_FP64 0 /* every per-spin quantity in FP64 */
+#define ASD_FP32 1 /* per-spin field and Heun update in FP32; reductions, time and
+                      spot position in FP64 */
+
+#define ASD_SC 0  /* simple cubic, 6 nearest neighbours, one shell */
+#define ASD_L10 1 /* L1_0 Fe sublattice: shells at a/sqrt2 (4), c (2), a (4),
+                     sqrt(a^2/2 + c^2) (8); n_shells selects the first 1..4 */
+
+#define ASD_BC_OPEN 0
+#define ASD_BC_PERIODIC 1
+#define ASD_BC_TRACK 2 /* x only: the window [origin, origin+nx) moves inside a
+                          stored track of track_nx columns; columns outside the
+                          window are frozen and act as fixed neighbours */
+
+#define ASD_SPOT_NONE 0   /* uniform temperature */
+#define ASD_SPOT_MOVING 1 /* spot centre x0 + v n dt (stored-lattice frame) */
+#define ASD_SPOT_LOCKED 2 /* spot centre origin*hx + x0: moves with the window */
+
+#define ASD_KERNEL_AUTO 0  /* fused kernel where available, else two-pass */
+#define ASD_KERNEL_PLAIN 1 /* two-pass: predictor kernel, corrector kernel */
+#define ASD_KERNEL_FUSED 2 /* one kernel per step, LDS tiles with recomputed halo */
+
+typedef struct asd_t asd_t; /* opaque handle */
+
+/* Material and numerical parameters, common to all systems of a handle. */
+typedef struct asd_params {
+    int32_t lattice;       /* ASD_SC or ASD_L10 */
+    int32_t precision;     /* ASD_FP64 or ASD_FP32 */
+    double a;              /* lattice constant (m); x and y cell size */
+    double c;              /* L1_0 cell height (m); ignored for SC */
+    int32_t n_shells;      /* SC: 1.  L1_0: 1..4 */
+    double J[4];           /* exchange energy per shell (J), Eq. 2 */
+    double mu_s;           /* atomic moment (J/T) */
+    double alpha;          /* Gilbert damping (the paper's lambda) */
+    double gamma;          /* gyromagnetic ratio (rad s^-1 T^-1) */
+    double dt;             /* time step (s) */
+    double k_u;            /* uniaxial anisotropy energy per atom (J), Eq. 3 */
+    uint64_t seed;         /* Philox key: (lo32, hi32) */
+    int32_t philox_rounds; /* 10 (published Philox4x32-10) or 7 */
+    int32_t kernel;        /* ASD_KERNEL_* */
+    int32_t graph_steps;   /* >0: capture segments of this many steps (even)
+                              in HIP graphs; 0: launch every step eagerly */
+} asd_params;
+
+/* One lattice (one system).  A handle steps all its systems together. */
+typedef struct asd_system_desc {
+    int32_t nx, ny, nz;      /* window size in cells */
+    int32_t bc_x, bc_y, bc_z; /* ASD_BC_*; ASD_BC_TRACK only for x */
+    int32_t track_nx;        /* stored columns when bc_x == ASD_BC_TRACK */
+    /* Grains, one of:
+     *   n_seeds > 0: columnar Voronoi built by the library from integer seed
+     *     points seeds_xy[2 n_seeds] in units of (hx / voronoi_q), hx = a
+     *     (SC) or a/2 (L1_0); a site is non-magnetic when it lies closer
+     *     than boundary_w_units/2 to the bisector of its own and another
+     *     seed (minimum image on periodic axes, ties to the lower seed);
+     *   labels != NULL: explicit grain label per stored site (-1 = not
+     *     magnetic);
+     *   neither: every site magnetic, one grain. */
+    int32_t n_seeds;
+    const int32_t *seeds_xy;
+    int32_t voronoi_q;
+    int64_t boundary_w_units;
+    const int32_t *labels;
+    const double *k_u_grain; /* per-grain k_u (J) [n_grains] or NULL */
+    int32_t n_k_u_grain;
+    double T_system;         /* >= 0: this system's ambient temperature (K),
+                                replacing the drive's T_amb */
+} asd_system_desc;
+
+/* Write field and temperature drive (Sec. III). */
+typedef struct asd_drive {
+    double B[3];            /* write field (T); multiplied by the polarity */
+    int32_t n_bits;         /* 0: polarity +1 always */
+    const uint8_t *bits;    /* polarity of bit k: +1 if bits[k] else -1 */
+    int64_t steps_per_bit;  /* step n writes bit (n / steps_per_bit) mod n_bits */
+    int32_t spot_mode;      /* ASD_SPOT_* */
+    double T_amb, T_peak;   /* K */
+    double fwhm;            /* spot full width at half maximum (m) */
+    double x0, y0;          /* spot centre at n = 0 / relative to the window (m) */
+    double v;               /* spot velocity along +x (m/s), ASD_SPOT_MOVING */
+} asd_drive;
+
+/* Size of the device workspace asd_create needs for these descriptors.
+ * Host-only; validates the descriptors (ASD_EINVAL). */
+int asd_workspace_bytes(const asd_params *p, const asd_system_desc *sys, int32_t n_sys,
+                        size_t *bytes);
+
+/* Build lattices, neighbour tables and grain labels on the host and upload
+ * them into the caller's workspace (device pointer, 256-byte aligned, at
+ * least asd_workspace_bytes).  stream: hipStream_t (NULL = default).  Spins
+ * start at +z on magnetic sites and 0 elsewhere; the step counter at 0; the
+ * drive at zero field, T = 0, no spot.  Returns ASD_EUNSUPPORTED when two
+ * magnetic neighbours carry different labels (grain boundaries thinner
+ * than the neighbour range). */
+int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, void *workspace,
+               size_t workspace_bytes, void *stream, asd_t **out);
+
+int asd_destroy(asd_t *h);
+
+/* Set the write field, bit pattern and temperature spot (copied). */
+int asd_set_field_temperature(asd_t *h, const asd_drive *d);
+
+/* Copy spins of system sys in/out, [3][n_stored] in handle precision.
+ * on_device != 0: src/dst is a device pointer.  set_spins writes both
+ * ping-pong buffers and stores 0 at non-magnetic sites. get_spins
+ * synchronises the stream when dst is host memory. */
+int asd_set_spins(asd_t *h, int32_t sys, const void *src, int32_t on_device);
+int asd_get_spins(asd_t *h, int32_t sys, void *dst, int32_t on_device);
+
+/* Enqueue n >= 0 Heun steps (Eq. 1) of every system: step k uses the
+ * write field, spot position and thermal noise of step index n0 + k, where
+ * n0 is the handle's step counter, which then advances by n.  The thermal
+ * field of a site at step n is sigma(T) (g_x, g_y, g_z) with g from
+ * Box-Muller on Philox4x32(key = seed, counter = (stored site index, n,
+ * system index, 0)): (g_x, g_y) from words (w0, w1), g_z the cosine branch
+ * of (w2, w3), u_r = (w + 1/2) 2^-32, u_t = w 2^-32.  The predictor is
+ * completed at every site before any corrector uses it; both stages use
+ * the same thermal field, write field and temperature.  Asynchronous. */
+int asd_step(asd_t *h, int64_t n);
+
+/* Move the window of every track system by `columns` >= 0 along +x: the
+ * leaving columns freeze with their current spins, the entering ones are
+ * taken from the track (Sec. II window shift).  ASD_ESTATE if a window
+ * would leave its track; ASD_EINVAL for systems without a track. */
+int asd_shift_window(asd_t *h, int32_t columns);
+
+/* FP64 sums over the magnetic sites of each window (Eq. 6 moment sums
+ * divided by mu_s): per_grain[4 g + k] for grain g of the flattened grain
+ * list (systems in order, asd_grain_count grains each) and per_system[4 s
+ * + k], k = (sum Sx, sum Sy, sum Sz, count).  Either pointer may be NULL.
+ * Host pointers; synchronises.  ASD_ENONFINITE if a sum is not finite. */
+int asd_reduce_magnetization(asd_t *h, double *per_grain, double *per_system);
+
+/* FP64 energy of each window at the current step (J): per_system[4 s + k],
+ * k = (exchange -1/2 sum_i sum_j J_ij S_i.S_j, anisotropy -sum k_u S_z^2,
+ * Zeeman -sum mu_s B.S, total).  Host pointer; synchronises. */
+int asd_reduce_energy(asd_t *h, double *per_system);
+
+/* Accumulate M-statistics of every system from its current spins: with
+ * m = |sum_i S_i| / N_magnetic, per system [5]: (samples, sum m, sum m^2,
+ * sum m^4, reserved).  reset != 0 clears before adding.  Enqueued on the
+ * stream; read with asd_get_moment_stats (synchronises). */
+int asd_accumulate_moments(asd_t *h, int32_t reset);
+int asd_get_moment_stats(asd_t *h, double *per_system /* [5 n_sys] */);
+
+/* Introspection of the built tables (for bit-exact checks).  Grain labels
+ * per stored site; neighbour shells in CSR form, rows by site index, each
+ * row ordered by shell then by offset (dz, dy, dx) with dx, dy in units of
+ * hx; pass NULL arrays to the count query first. */
+int asd_grain_count(asd_t *h, int32_t sys, int32_t *n_grains);
+int asd_stored_sites(asd_t *h, int32_t sys, int64_t *n_stored);
+int asd_get_grain_labels(asd_t *h, int32_t sys, int32_t *labels);
+int asd_neighbour_count(asd_t *h, int32_t sys, int64_t *n_entries);
+int asd_get_neighbours(asd_t *h, int32_t sys, int64_t *row_ptr, int32_t *col, int8_t *shell);
+
+/* Step counter and window origin of system sys (host copies). */
+int asd_get_state(asd_t *h, int32_t sys, int64_t *step, int32_t *origin);
+/* Set the step counter (resume from a checkpoint). */
+int asd_set_step(asd_t *h, int64_t step);
+
+/* Raw Philox4x32-R words of n counters (device pointers ctr[4n], out[4n]),
+ * key = (lo32 seed, hi32 seed), on `stream`.  No handle needed. */
+int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out, int64_t n,
+               void *stream);
+
+/* Pick the fastest kernel variant and tile for this handle by timing each
+ * on the handle's stream (spins are saved and restored, the step counter
+ * unchanged).  cache_path: JSON file read if it holds an entry for this
+ * shape, written otherwise (NULL: no cache). */
+int asd_autotune(asd_t *h, const char *cache_path);
+/* Force a variant: kernel ASD_KERNEL_*, tile index (0 = default). */
+int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile);
+int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile);
+
+const char *asd_strerror(int code);
+const char *asd_last_error(const asd_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -589,14 +589,15 @@ static void nadd(nsum *a, double x)
 static double nval(const nsum *a) { return a->s + a->c; }
 
 /* per grain g (label g >= 0): (sum Sx, sum Sy, sum Sz, count) into out[4 g..];
- * total over all magnetic sites into tot[4] (Eq. 6 moment sums / mu_s) */
+ * total over all magnetic sites into tot[4] (Eq. 6 moment sums / mu_s).
+ * Only sites inside the window (active, when a mask is set) are summed. */
 void orc_magnetisation(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                        int n_grains, double *per_grain, double tot[4])
 {
     nsum *acc = (nsum *)calloc((size_t)(4 * (n_grains + 1)), sizeof(nsum));
     for (int64_t i = 0; i < s->n_sites; ++i) {
         int g = s->label[i];
-        if (g < 0) continue;
+        if (g < 0 || (s->active && !s->active[i])) continue;
         double v[4] = {Sx[i], Sy[i], Sz[i], 1.0};
         for (int k = 0; k < 4; ++k) {
             if (g < n_grains) nadd(&acc[4 * g + k], v[k]);
@@ -611,7 +612,8 @@ void orc_magnetisation(const orc_system *s, const double *Sx, const double *Sy, 
 
 /* energy (J) of the Hamiltonian whose field is Eqs. 2-3 + write field:
  * E = -1/2 sum_i sum_j J_ij S_i.S_j - sum_i k_u S_iz^2 - sum_i mu_s B.S_i,
- * over magnetic sites (active or frozen); out = (exchange, anisotropy,
+ * with i over the magnetic sites of the window (active sites when a mask
+ * is set; j over all their neighbours); out = (exchange, anisotropy,
  * Zeeman, total). */
 void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                 int64_t step, double out[4])
@@ -619,7 +621,7 @@ void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const d
     nsum ex = {0, 0}, an = {0, 0}, ze = {0, 0};
     double pol = polarity(s, step);
     for (int64_t i = 0; i < s->n_sites; ++i) {
-        if (!magnetic(s, i)) continue;
+        if (!magnetic(s, i) || (s->active && !s->active[i])) continue;
         for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
             int64_t j = s->col[k];
             if (s->label[j] != s->label[i]) continue;

@@ -1,0 +1,315 @@
+"""ctypes binding of libasd (include/asd.h).
+
+Argument marshalling only: every step of the sLLG path runs in the HIP
+kernels of libasd.so.  PyTorch supplies device memory (one uint8 workspace
+tensor per handle) and the HIP stream.  Importing this module does not touch
+the GPU; loading the library fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libasd.so")
+
+ASD_OK, ASD_EINVAL, ASD_ENOMEM, ASD_EHIP, ASD_ESTATE, ASD_ENONFINITE, ASD_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6)
+ASD_FP64, ASD_FP32 = 0, 1
+ASD_SC, ASD_L10 = 0, 1
+ASD_BC_OPEN, ASD_BC_PERIODIC, ASD_BC_TRACK = 0, 1, 2
+ASD_SPOT_NONE, ASD_SPOT_MOVING, ASD_SPOT_LOCKED = 0, 1, 2
+ASD_KERNEL_AUTO, ASD_KERNEL_PLAIN, ASD_KERNEL_FUSED = 0, 1, 2
+
+SYMBOLS = [
+    "asd_workspace_bytes", "asd_create", "asd_destroy", "asd_set_field_temperature",
+    "asd_set_spins", "asd_get_spins", "asd_step", "asd_shift_window",
+    "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
+    "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
+    "asd_neighbour_count", "asd_get_neighbours", "asd_get_state", "asd_set_step", "asd_philox",
+    "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_strerror", "asd_last_error",
+]
+
+
+class AsdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libasd error {code}: {msg}")
+        self.code = code
+
+
+class asd_params(C.Structure):
+    _fields_ = [("lattice", C.c_int32), ("precision", C.c_int32), ("a", C.c_double),
+                ("c", C.c_double), ("n_shells", C.c_int32), ("J", C.c_double * 4),
+                ("mu_s", C.c_double), ("alpha", C.c_double), ("gamma", C.c_double),
+                ("dt", C.c_double), ("k_u", C.c_double), ("seed", C.c_uint64),
+                ("philox_rounds", C.c_int32), ("kernel", C.c_int32), ("graph_steps", C.c_int32)]
+
+
+class asd_system_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc_x", C.c_int32),
+                ("bc_y", C.c_int32), ("bc_z", C.c_int32), ("track_nx", C.c_int32),
+                ("n_seeds", C.c_int32), ("seeds_xy", C.POINTER(C.c_int32)),
+                ("voronoi_q", C.c_int32), ("boundary_w_units", C.c_int64),
+                ("labels", C.POINTER(C.c_int32)), ("k_u_grain", C.POINTER(C.c_double)),
+                ("n_k_u_grain", C.c_int32), ("T_system", C.c_double)]
+
+
+class asd_drive(C.Structure):
+    _fields_ = [("B", C.c_double * 3), ("n_bits", C.c_int32), ("bits", C.POINTER(C.c_uint8)),
+                ("steps_per_bit", C.c_int64), ("spot_mode", C.c_int32), ("T_amb", C.c_double),
+                ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double),
+                ("y0", C.c_double), ("v", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libasd.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run paper_2502_02236_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        h = vp
+        L.asd_workspace_bytes.argtypes = [P(asd_params), P(asd_system_desc), C.c_int32, P(C.c_size_t)]
+        L.asd_create.argtypes = [P(asd_params), P(asd_system_desc), C.c_int32, vp, C.c_size_t, vp, P(vp)]
+        L.asd_destroy.argtypes = [h]
+        L.asd_set_field_temperature.argtypes = [h, P(asd_drive)]
+        L.asd_set_spins.argtypes = [h, C.c_int32, vp, C.c_int32]
+        L.asd_get_spins.argtypes = [h, C.c_int32, vp, C.c_int32]
+        L.asd_step.argtypes = [h, C.c_int64]
+        L.asd_shift_window.argtypes = [h, C.c_int32]
+        L.asd_reduce_magnetization.argtypes = [h, vp, vp]
+        L.asd_reduce_energy.argtypes = [h, vp]
+        L.asd_accumulate_moments.argtypes = [h, C.c_int32]
+        L.asd_get_moment_stats.argtypes = [h, vp]
+        L.asd_grain_count.argtypes = [h, C.c_int32, P(C.c_int32)]
+        L.asd_stored_sites.argtypes = [h, C.c_int32, P(C.c_int64)]
+        L.asd_get_grain_labels.argtypes = [h, C.c_int32, vp]
+        L.asd_neighbour_count.argtypes = [h, C.c_int32, P(C.c_int64)]
+        L.asd_get_neighbours.argtypes = [h, C.c_int32, vp, vp, vp]
+        L.asd_get_state.argtypes = [h, C.c_int32, P(C.c_int64), P(C.c_int32)]
+        L.asd_set_step.argtypes = [h, C.c_int64]
+        L.asd_philox.argtypes = [C.c_uint64, C.c_int32, vp, vp, C.c_int64, vp]
+        L.asd_autotune.argtypes = [h, C.c_char_p]
+        L.asd_set_variant.argtypes = [h, C.c_int32, C.c_int32]
+        L.asd_get_variant.argtypes = [h, P(C.c_int32), P(C.c_int32)]
+        L.asd_strerror.argtypes = [C.c_int]
+        L.asd_strerror.restype = C.c_char_p
+        L.asd_last_error.argtypes = [h]
+        L.asd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, handle=None):
+    if rc != ASD_OK:
+        msg = lib().asd_last_error(handle).decode(errors="replace")
+        raise AsdError(rc, f"{lib().asd_strerror(rc).decode()}: {msg}")
+    return rc
+
+
+def _np_ptr(a, ctype=None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p if ctype is None else C.POINTER(ctype))
+
+
+# ----------------------------------------------------------------- same-named wrappers
+def asd_workspace_bytes(params, systems):
+    arr = (asd_system_desc * len(systems))(*systems)
+    out = C.c_size_t(0)
+    _check(lib().asd_workspace_bytes(C.byref(params), arr, len(systems), C.byref(out)))
+    return out.value
+
+
+def asd_create(params, systems, workspace_ptr, workspace_bytes, stream_ptr):
+    arr = (asd_system_desc * len(systems))(*systems)
+    h = C.c_void_p()
+    _check(lib().asd_create(C.byref(params), arr, len(systems), C.c_void_p(workspace_ptr),
+                            workspace_bytes, C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def asd_destroy(h):
+    _check(lib().asd_destroy(h))
+
+
+def asd_set_field_temperature(h, drive):
+    _check(lib().asd_set_field_temperature(h, C.byref(drive)), h)
+
+
+def asd_set_spins(h, sys, ptr, on_device):
+    _check(lib().asd_set_spins(h, sys, C.c_void_p(ptr), int(on_device)), h)
+
+
+def asd_get_spins(h, sys, ptr, on_device):
+    _check(lib().asd_get_spins(h, sys, C.c_void_p(ptr), int(on_device)), h)
+
+
+def asd_step(h, n):
+    _check(lib().asd_step(h, int(n)), h)
+
+
+def asd_shift_window(h, columns):
+    _check(lib().asd_shift_window(h, int(columns)), h)
+
+
+def asd_reduce_magnetization(h, per_grain, per_system):
+    return lib().asd_reduce_magnetization(h, _np_ptr(per_grain), _np_ptr(per_system))
+
+
+def asd_reduce_energy(h, per_system):
+    return lib().asd_reduce_energy(h, _np_ptr(per_system))
+
+
+def asd_accumulate_moments(h, reset):
+    _check(lib().asd_accumulate_moments(h, int(reset)), h)
+
+
+def asd_get_moment_stats(h, out):
+    return lib().asd_get_moment_stats(h, _np_ptr(out))
+
+
+def asd_philox(seed, rounds, ctr_ptr, out_ptr, n, stream_ptr):
+    _check(lib().asd_philox(seed, rounds, C.c_void_p(ctr_ptr), C.c_void_p(out_ptr), n,
+                            C.c_void_p(stream_ptr)))
+
+
+def asd_set_variant(h, kernel, tile):
+    _check(lib().asd_set_variant(h, kernel, tile), h)
+
+
+def asd_get_variant(h):
+    k, t = C.c_int32(), C.c_int32()
+    _check(lib().asd_get_variant(h, C.byref(k), C.byref(t)), h)
+    return k.value, t.value
+
+
+def asd_autotune(h, cache_path=None):
+    _check(lib().asd_autotune(h, None if cache_path is None else cache_path.encode()), h)
+
+
+# ----------------------------------------------------------------- convenience wrapper
+class Handle:
+    """One libasd handle with its torch-owned workspace and a dedicated stream."""
+
+    def __init__(self, params: asd_params, systems: list, device: str = "cuda:0", stream=None):
+        import torch  # device memory and streams only
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self._keep = []  # host arrays referenced by descriptors during create
+        self.params = params
+        self.systems = systems
+        nbytes = asd_workspace_bytes(params, systems)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.h = asd_create(params, systems, self.ws_ptr, nbytes, self.stream.cuda_stream)
+        self.dtype = np.float64 if params.precision == ASD_FP64 else np.float32
+
+    def close(self):
+        if getattr(self, "h", None):
+            asd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- drive and state
+    def set_drive(self, drive: asd_drive):
+        asd_set_field_temperature(self.h, drive)
+
+    def stored_sites(self, sys: int = 0) -> int:
+        n = C.c_int64()
+        _check(lib().asd_stored_sites(self.h, sys, C.byref(n)), self.h)
+        return n.value
+
+    def grain_count(self, sys: int = 0) -> int:
+        n = C.c_int32()
+        _check(lib().asd_grain_count(self.h, sys, C.byref(n)), self.h)
+        return n.value
+
+    def set_spins(self, S, sys: int = 0):
+        """S: [3, n_stored] host array (converted to the handle precision) or device tensor."""
+        if hasattr(S, "data_ptr"):
+            asd_set_spins(self.h, sys, S.data_ptr(), True)
+        else:
+            a = np.ascontiguousarray(S, dtype=self.dtype).reshape(3, -1)
+            if a.shape[1] != self.stored_sites(sys):
+                raise ValueError("spin array does not match the stored lattice")
+            asd_set_spins(self.h, sys, a.ctypes.data, False)
+
+    def get_spins(self, sys: int = 0) -> np.ndarray:
+        out = np.empty((3, self.stored_sites(sys)), dtype=self.dtype)
+        asd_get_spins(self.h, sys, out.ctypes.data, False)
+        return out
+
+    def step(self, n: int):
+        asd_step(self.h, n)
+
+    def shift_window(self, columns: int):
+        asd_shift_window(self.h, columns)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def magnetization(self):
+        ng = sum(self.grain_count(s) for s in range(len(self.systems)))
+        pg = np.zeros((max(ng, 1), 4))
+        ps = np.zeros((len(self.systems), 4))
+        _check(asd_reduce_magnetization(self.h, pg, ps), self.h)
+        return pg[:ng], ps
+
+    def energy(self):
+        out = np.zeros((len(self.systems), 4))
+        _check(asd_reduce_energy(self.h, out), self.h)
+        return out
+
+    def accumulate_moments(self, reset=False):
+        asd_accumulate_moments(self.h, reset)
+
+    def moment_stats(self):
+        out = np.zeros((len(self.systems), 5))
+        _check(asd_get_moment_stats(self.h, out), self.h)
+        return out
+
+    def labels(self, sys: int = 0) -> np.ndarray:
+        out = np.empty(self.stored_sites(sys), dtype=np.int32)
+        _check(lib().asd_get_grain_labels(self.h, sys, _np_ptr(out)), self.h)
+        return out
+
+    def neighbours(self, sys: int = 0):
+        n = C.c_int64()
+        _check(lib().asd_neighbour_count(self.h, sys, C.byref(n)), self.h)
+        ns = self.stored_sites(sys)
+        row = np.empty(ns + 1, dtype=np.int64)
+        col = np.empty(max(n.value, 1), dtype=np.int32)
+        sh = np.empty(max(n.value, 1), dtype=np.int8)
+        _check(lib().asd_get_neighbours(self.h, sys, _np_ptr(row), _np_ptr(col), _np_ptr(sh)), self.h)
+        return row, col[:n.value], sh[:n.value]
+
+    def state(self, sys: int = 0):
+        st, org = C.c_int64(), C.c_int32()
+        _check(lib().asd_get_state(self.h, sys, C.byref(st), C.byref(org)), self.h)
+        return st.value, org.value
+
+    def set_step(self, step: int):
+        _check(lib().asd_set_step(self.h, step), self.h)
+
+    def set_variant(self, kernel: int, tile: int = 0):
+        asd_set_variant(self.h, kernel, tile)
+
+    def variant(self):
+        return asd_get_variant(self.h)
+
+    def autotune(self, cache_path=None):
+        asd_autotune(self.h, cache_path)

@@ -1,0 +1,1066 @@
+// asd_host.cpp -- the C ABI of libasd (include/asd.h): descriptor checks,
+// workspace layout, host construction of lattices, grain labels and
+// neighbour tables, uploads, and the enqueueing of Heun steps, window
+// shifts and FP64 reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "asd.h"
+#include "asd_internal.h"
+
+using namespace asd;
+
+namespace {
+
+constexpr double kBoltzmann = 1.380649e-23;  // J/K (exact SI)
+constexpr size_t kAlign = 256;
+constexpr int kMaxBits = 1 << 16;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// in-plane L1_0 half-cell offsets (dx, dy, dz) by shell, each shell ordered
+// by (dz, dy, dx): shells a/sqrt2 (4), c (2), a (4), sqrt(a^2/2 + c^2) (8)
+const int kL10Off[kL10Degree][3] = {
+    {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 1, 0},                 // shell 0
+    {0, 0, -1},  {0, 0, 1},                                          // shell 1
+    {0, -2, 0},  {-2, 0, 0}, {2, 0, 0},  {0, 2, 0},                  // shell 2
+    {-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1},              // shell 3, dz = -1
+    {-1, -1, 1},  {1, -1, 1},  {-1, 1, 1},  {1, 1, 1}};              // shell 3, dz = +1
+const int kL10ShellEnd[4] = {4, 6, 10, 18};
+// SC offsets (dx, dy, dz) ordered by (dz, dy, dx)
+const int kScOffH[6][3] = {{0, 0, -1}, {0, -1, 0}, {-1, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+
+struct HostSys {
+    asd_system_desc desc;
+    std::vector<int32_t> labels;  // per stored site, -1 non-magnetic
+    std::vector<double> ku_grain;
+    int32_t n_grains = 1;
+    int64_t n_stored = 0, n_window = 0;
+    int32_t sx = 0;
+};
+
+struct Layout {
+    int64_t n_total = 0;   // stored sites over all systems (+ zero slot)
+    int64_t ncs = 0;       // component stride
+    int64_t zero_site = 0;
+    int32_t n_grains = 0;  // over all systems
+    int32_t n_tiles = 0;   // plain tiles
+    int32_t n_ftiles = 0;  // fused tiles
+    size_t off_S[3] = {0, 0, 0};
+    size_t off_label = 0, off_ell = 0, off_sys = 0, off_tile = 0, off_ftile = 0, off_can = 0,
+           off_ku = 0, off_gsys = 0, off_gptr = 0, off_gsites = 0, off_step = 0, off_origin = 0,
+           off_bits = 0, off_gout = 0, off_sout = 0, off_mom = 0, off_epart = 0, off_eout = 0;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct asd_t {
+    asd_params p{};
+    std::vector<HostSys> sys;
+    std::vector<SysDev> dev;
+    Layout L;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    int cur = 0;              // buffer holding the current spins
+    int64_t step = 0;         // host copy of the step counter
+    std::vector<int32_t> origin;
+    asd_drive drive{};
+    std::vector<uint8_t> bits;
+    int kernel = ASD_KERNEL_PLAIN;
+    int tile_cfg = 0;
+    std::string err;
+    int elem = 8;
+    // graphs: one per starting buffer parity
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_steps = 0;
+    int graph_kernel = -1, graph_tile = -1;
+};
+
+static thread_local std::string g_err;
+
+static int fail(asd_t *h, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(h, call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((h), ASD_EHIP, "%s: %s", #call, hipGetErrorString(e_));             \
+    } while (0)
+
+// ------------------------------------------------------------------ validation
+static int check_params(const asd_params *p)
+{
+    if (!p) return fail(nullptr, ASD_EINVAL, "params is NULL");
+    if (p->lattice != ASD_SC && p->lattice != ASD_L10)
+        return fail(nullptr, ASD_EINVAL, "lattice must be ASD_SC or ASD_L10");
+    if (p->precision != ASD_FP64 && p->precision != ASD_FP32)
+        return fail(nullptr, ASD_EINVAL, "precision must be ASD_FP64 or ASD_FP32");
+    if (p->lattice == ASD_SC && p->n_shells != 1)
+        return fail(nullptr, ASD_EINVAL, "SC lattice has exactly one shell");
+    if (p->lattice == ASD_L10 && (p->n_shells < 1 || p->n_shells > 4))
+        return fail(nullptr, ASD_EINVAL, "L1_0 n_shells must be 1..4");
+    if (!(p->a > 0) || (p->lattice == ASD_L10 && !(p->c > 0)))
+        return fail(nullptr, ASD_EINVAL, "lattice constants must be positive");
+    if (!(p->mu_s > 0) || !(p->gamma > 0) || !(p->dt > 0) || !(p->alpha >= 0))
+        return fail(nullptr, ASD_EINVAL, "mu_s, gamma, dt must be positive and alpha >= 0");
+    if (!std::isfinite(p->k_u)) return fail(nullptr, ASD_EINVAL, "k_u must be finite");
+    for (int s = 0; s < p->n_shells; ++s)
+        if (!std::isfinite(p->J[s])) return fail(nullptr, ASD_EINVAL, "J must be finite");
+    if (p->philox_rounds != 10 && p->philox_rounds != 7)
+        return fail(nullptr, ASD_EINVAL, "philox_rounds must be 10 or 7");
+    if (p->kernel < ASD_KERNEL_AUTO || p->kernel > ASD_KERNEL_FUSED)
+        return fail(nullptr, ASD_EINVAL, "unknown kernel selector");
+    if (p->graph_steps < 0 || (p->graph_steps % 2) != 0)
+        return fail(nullptr, ASD_EINVAL, "graph_steps must be a non-negative even number");
+    return ASD_OK;
+}
+
+static int check_system(const asd_params *p, const asd_system_desc *d, int idx)
+{
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return fail(nullptr, ASD_EINVAL, "system %d: sizes must be >= 1", idx);
+    const int bc[3] = {d->bc_x, d->bc_y, d->bc_z};
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int k = 0; k < 3; ++k) {
+        if (bc[k] != ASD_BC_OPEN && bc[k] != ASD_BC_PERIODIC && !(k == 0 && bc[k] == ASD_BC_TRACK))
+            return fail(nullptr, ASD_EINVAL, "system %d: bad boundary condition on axis %d", idx, k);
+        if (bc[k] == ASD_BC_PERIODIC && n[k] < 3)
+            return fail(nullptr, ASD_EINVAL, "system %d: periodic axis %d needs >= 3 cells", idx, k);
+    }
+    if (d->bc_x == ASD_BC_TRACK && d->track_nx < d->nx)
+        return fail(nullptr, ASD_EINVAL, "system %d: track_nx must be >= nx", idx);
+    int64_t sxv = d->bc_x == ASD_BC_TRACK ? d->track_nx : d->nx;
+    int64_t stored = (p->lattice == ASD_SC ? 1 : 2) * sxv * d->ny * d->nz;
+    if (stored >= (int64_t)1 << 31)
+        return fail(nullptr, ASD_EINVAL, "system %d: more than 2^31 stored sites", idx);
+    if (d->n_seeds < 0) return fail(nullptr, ASD_EINVAL, "system %d: n_seeds < 0", idx);
+    if (d->n_seeds > 0 && (!d->seeds_xy || d->voronoi_q < 1 || d->boundary_w_units < 0))
+        return fail(nullptr, ASD_EINVAL, "system %d: Voronoi needs seeds, q >= 1, w >= 0", idx);
+    if (d->n_seeds > 0 && d->labels)
+        return fail(nullptr, ASD_EINVAL, "system %d: give either Voronoi seeds or labels", idx);
+    if (d->n_seeds > (int)kNoGrain)
+        return fail(nullptr, ASD_EINVAL, "system %d: at most 65535 grains", idx);
+    if (d->n_k_u_grain < 0 || (d->n_k_u_grain > 0 && !d->k_u_grain))
+        return fail(nullptr, ASD_EINVAL, "system %d: bad per-grain k_u table", idx);
+    return ASD_OK;
+}
+
+// ------------------------------------------------------------------ lattice setup
+static int64_t min_image(int64_t d, int64_t L, bool periodic)
+{
+    if (!periodic) return d;
+    d %= L;
+    if (d < 0) d += L;
+    if (2 * d > L) d -= L;
+    return d;
+}
+
+// Columnar Voronoi labels: computed for each in-plane site of the stored
+// lattice and extruded along z.
+static void voronoi_plane(const asd_params *p, const asd_system_desc *d, int32_t sx,
+                          std::vector<int32_t> &plane)
+{
+    const bool l10 = p->lattice == ASD_L10;
+    const int per_cell = l10 ? 2 : 1;
+    const int64_t Q = d->voronoi_q;
+    const int64_t LX = (l10 ? 2 * (int64_t)sx : sx) * Q;
+    const int64_t LY = (l10 ? 2 * (int64_t)d->ny : d->ny) * Q;
+    const bool px = d->bc_x == ASD_BC_PERIODIC, py = d->bc_y == ASD_BC_PERIODIC;
+    const int ns = d->n_seeds;
+    const int64_t w2 = d->boundary_w_units * d->boundary_w_units;
+    plane.assign((size_t)sx * d->ny * per_cell, -1);
+    std::vector<int64_t> vx(ns), vy(ns);
+    for (int32_t y = 0; y < d->ny; ++y)
+        for (int32_t x = 0; x < sx; ++x)
+            for (int s = 0; s < per_cell; ++s) {
+                const int64_t X = l10 ? 2 * (int64_t)x + s : x;
+                const int64_t Y = l10 ? 2 * (int64_t)y + s : y;
+                int best = 0;
+                int64_t bd = INT64_MAX;
+                for (int k = 0; k < ns; ++k) {
+                    vx[k] = min_image(X * Q - d->seeds_xy[2 * k], LX, px);
+                    vy[k] = min_image(Y * Q - d->seeds_xy[2 * k + 1], LY, py);
+                    const int64_t d2 = vx[k] * vx[k] + vy[k] * vy[k];
+                    if (d2 < bd) {
+                        bd = d2;
+                        best = k;
+                    }
+                }
+                bool mag = true;
+                for (int k = 0; k < ns && mag; ++k) {
+                    if (k == best) continue;
+                    const int64_t gap = vx[k] * vx[k] + vy[k] * vy[k] - bd;
+                    const int64_t ex = vx[best] - vx[k], ey = vy[best] - vy[k];
+                    if (gap * gap < w2 * (ex * ex + ey * ey)) mag = false;
+                }
+                plane[((size_t)y * sx + x) * per_cell + s] = mag ? best : -1;
+            }
+}
+
+// global-frame neighbour of stored site (SC cell or L1_0 half-cell coords);
+// returns local stored index or -1
+static int64_t neighbour_local(const asd_params *p, const asd_system_desc *d, int32_t sx, int64_t X,
+                               int64_t Y, int64_t Z, int dx, int dy, int dz)
+{
+    const bool l10 = p->lattice == ASD_L10;
+    const int64_t LX = l10 ? 2 * (int64_t)(d->bc_x == ASD_BC_TRACK ? sx : d->nx) : (d->bc_x == ASD_BC_TRACK ? sx : d->nx);
+    const int64_t LY = l10 ? 2 * (int64_t)d->ny : d->ny;
+    const int64_t LZ = d->nz;
+    X += dx;
+    Y += dy;
+    Z += dz;
+    if (X < 0 || X >= LX) {
+        if (d->bc_x != ASD_BC_PERIODIC) return -1;
+        X = (X % LX + LX) % LX;
+    }
+    if (Y < 0 || Y >= LY) {
+        if (d->bc_y != ASD_BC_PERIODIC) return -1;
+        Y = (Y % LY + LY) % LY;
+    }
+    if (Z < 0 || Z >= LZ) {
+        if (d->bc_z != ASD_BC_PERIODIC) return -1;
+        Z = (Z % LZ + LZ) % LZ;
+    }
+    if (!l10) return X + (int64_t)sx * (Y + (int64_t)d->ny * Z);
+    const int64_t s = X & 1;
+    return 2 * ((X >> 1) + (int64_t)sx * ((Y >> 1) + (int64_t)d->ny * Z)) + s;
+}
+
+static void site_coords(const asd_params *p, const HostSys &hs, int64_t i, int64_t &X, int64_t &Y,
+                        int64_t &Z)
+{
+    const asd_system_desc *d = &hs.desc;
+    if (p->lattice == ASD_SC) {
+        X = i % hs.sx;
+        Y = (i / hs.sx) % d->ny;
+        Z = i / ((int64_t)hs.sx * d->ny);
+    } else {
+        const int64_t s = i & 1, cell = i >> 1;
+        X = 2 * (cell % hs.sx) + s;
+        Y = 2 * ((cell / hs.sx) % d->ny) + s;
+        Z = cell / ((int64_t)hs.sx * d->ny);
+    }
+}
+
+static int n_neighbour_slots(const asd_params *p)
+{
+    return p->lattice == ASD_SC ? 6 : kL10ShellEnd[p->n_shells - 1];
+}
+
+static int64_t slot_neighbour(const asd_params *p, const HostSys &hs, int64_t i, int k)
+{
+    int64_t X, Y, Z;
+    site_coords(p, hs, i, X, Y, Z);
+    const int *o = p->lattice == ASD_SC ? kScOffH[k] : kL10Off[k];
+    return neighbour_local(p, &hs.desc, hs.sx, X, Y, Z, o[0], o[1], o[2]);
+}
+
+static int slot_shell(const asd_params *p, int k)
+{
+    if (p->lattice == ASD_SC) return 0;
+    return k < 4 ? 0 : (k < 6 ? 1 : (k < 10 ? 2 : 3));
+}
+
+static int build_system(const asd_params *p, const asd_system_desc *d, int idx, HostSys &hs)
+{
+    hs.desc = *d;
+    hs.desc.seeds_xy = nullptr;
+    hs.desc.labels = nullptr;
+    hs.desc.k_u_grain = nullptr;
+    hs.sx = d->bc_x == ASD_BC_TRACK ? d->track_nx : d->nx;
+    const int per_cell = p->lattice == ASD_SC ? 1 : 2;
+    hs.n_stored = (int64_t)per_cell * hs.sx * d->ny * d->nz;
+    hs.n_window = (int64_t)per_cell * d->nx * d->ny * d->nz;
+    hs.labels.assign((size_t)hs.n_stored, 0);
+    if (d->n_seeds > 0) {
+        std::vector<int32_t> plane;
+        voronoi_plane(p, d, hs.sx, plane);
+        const size_t pn = plane.size();
+        for (int64_t z = 0; z < d->nz; ++z)
+            std::memcpy(&hs.labels[(size_t)z * pn], plane.data(), pn * sizeof(int32_t));
+        hs.n_grains = d->n_seeds;
+    } else if (d->labels) {
+        int32_t mx = -1;
+        for (int64_t i = 0; i < hs.n_stored; ++i) {
+            int32_t l = d->labels[i];
+            if (l < -1 || l >= (int32_t)kNoGrain)
+                return fail(nullptr, ASD_EINVAL, "system %d: label out of range at %lld", idx,
+                            (long long)i);
+            hs.labels[i] = l;
+            mx = std::max(mx, l);
+        }
+        hs.n_grains = std::max(mx + 1, 1);
+    } else {
+        hs.n_grains = 1;
+    }
+    if (d->n_k_u_grain > 0) {
+        if (d->n_k_u_grain < hs.n_grains)
+            return fail(nullptr, ASD_EINVAL, "system %d: k_u table shorter than the grain count", idx);
+        hs.ku_grain.assign(d->k_u_grain, d->k_u_grain + hs.n_grains);
+    }
+    // no two magnetic neighbours may belong to different grains: the kernels
+    // rely on non-magnetic boundaries to decouple grains
+    const int slots = n_neighbour_slots(p);
+    for (int64_t i = 0; i < hs.n_stored; ++i) {
+        const int32_t li = hs.labels[i];
+        if (li < 0) continue;
+        for (int k = 0; k < slots; ++k) {
+            const int64_t j = slot_neighbour(p, hs, i, k);
+            if (j >= 0 && hs.labels[j] >= 0 && hs.labels[j] != li)
+                return fail(nullptr, ASD_EUNSUPPORTED,
+                            "system %d: magnetic neighbours %lld and %lld belong to different grains "
+                            "(boundaries thinner than the neighbour range)",
+                            idx, (long long)i, (long long)j);
+        }
+    }
+    return ASD_OK;
+}
+
+static int grain_count_of(const asd_params *p, const asd_system_desc *d)
+{
+    (void)p;
+    if (d->n_seeds > 0) return d->n_seeds;
+    if (d->labels) {
+        int64_t sxv = d->bc_x == ASD_BC_TRACK ? d->track_nx : d->nx;
+        int64_t n = (p->lattice == ASD_SC ? 1 : 2) * sxv * d->ny * d->nz;
+        int32_t mx = -1;
+        for (int64_t i = 0; i < n; ++i) mx = std::max(mx, d->labels[i]);
+        return std::max(mx + 1, 1);
+    }
+    return 1;
+}
+
+static void fused_tiles_of(const asd_params *p, const asd_system_desc *d, int tile_cfg, int *tx,
+                           int *ty)
+{
+    int bx, by;
+    fused_tile_shape(p->lattice, tile_cfg, &bx, &by);
+    *tx = (d->nx + bx - 1) / bx;
+    *ty = (d->ny + by - 1) / by;
+}
+
+static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n_sys)
+{
+    Layout L;
+    int64_t n = 0;
+    int32_t g = 0, tiles = 0, ftiles = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        const asd_system_desc *d = &sys[s];
+        int64_t sxv = d->bc_x == ASD_BC_TRACK ? d->track_nx : d->nx;
+        int per = p->lattice == ASD_SC ? 1 : 2;
+        n += per * sxv * d->ny * d->nz;
+        g += grain_count_of(p, d);
+        int64_t nw = (int64_t)per * d->nx * d->ny * d->nz;
+        tiles += (int32_t)((nw + kPlainTile - 1) / kPlainTile);
+        int fx = 0, fy = 0;
+        int maxf = 0;
+        for (int v = 0; v < fused_tile_variants(p->lattice); ++v) {
+            fused_tiles_of(p, d, v, &fx, &fy);
+            maxf = std::max(maxf, fx * fy);
+        }
+        ftiles += maxf;
+    }
+    L.n_total = n + 1;  // + zero slot
+    L.zero_site = n;
+    L.ncs = (int64_t)align_up((size_t)L.n_total, 64);
+    L.n_grains = g;
+    L.n_tiles = tiles;
+    L.n_ftiles = ftiles;
+    const size_t elem = p->precision == ASD_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    for (int b = 0; b < 3; ++b) L.off_S[b] = take(3 * (size_t)L.ncs * elem);
+    L.off_label = take((size_t)L.ncs * sizeof(uint16_t));
+    L.off_ell = p->lattice == ASD_L10 ? take((size_t)kL10Degree * L.ncs * sizeof(int32_t)) : 0;
+    L.off_sys = take((size_t)n_sys * sizeof(SysDev));
+    L.off_tile = take((size_t)std::max(tiles, 1) * sizeof(int32_t));
+    L.off_ftile = take((size_t)std::max(ftiles, 1) * sizeof(int32_t));
+    L.off_can = take((size_t)std::max(g, 1) * sizeof(double));
+    L.off_ku = take((size_t)std::max(g, 1) * sizeof(double));
+    L.off_gsys = take((size_t)std::max(g, 1) * sizeof(int32_t));
+    L.off_gptr = take((size_t)(g + 1) * sizeof(int64_t));
+    L.off_gsites = take((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+    L.off_step = take(sizeof(int64_t));
+    L.off_origin = take((size_t)n_sys * sizeof(int32_t));
+    L.off_bits = take(kMaxBits);
+    L.off_gout = take((size_t)std::max(g, 1) * 4 * sizeof(double));
+    L.off_sout = take((size_t)n_sys * 4 * sizeof(double));
+    L.off_mom = take((size_t)n_sys * 5 * sizeof(double));
+    L.off_epart = take((size_t)std::max(tiles, 1) * 3 * sizeof(double));
+    L.off_eout = take((size_t)n_sys * 4 * sizeof(double));
+    L.bytes = off;
+    return L;
+}
+
+// ------------------------------------------------------------------ C ABI
+// (definitions take C linkage from their declarations in asd.h)
+
+const char *asd_strerror(int code)
+{
+    switch (code) {
+    case ASD_OK: return "ok";
+    case ASD_EINVAL: return "invalid argument";
+    case ASD_ENOMEM: return "workspace too small";
+    case ASD_EHIP: return "HIP runtime error";
+    case ASD_ESTATE: return "invalid state";
+    case ASD_ENONFINITE: return "non-finite value in a reduction";
+    case ASD_EUNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+    }
+}
+
+const char *asd_last_error(const asd_t *h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+int asd_workspace_bytes(const asd_params *p, const asd_system_desc *sys, int32_t n_sys,
+                        size_t *bytes)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!sys || n_sys < 1 || !bytes) return fail(nullptr, ASD_EINVAL, "need >= 1 system and bytes");
+    for (int s = 0; s < n_sys; ++s)
+        if ((rc = check_system(p, &sys[s], s))) return rc;
+    *bytes = make_layout(p, sys, n_sys).bytes;
+    return ASD_OK;
+}
+
+static double T_of(const asd_t *h, int s)
+{
+    return h->sys[s].desc.T_system >= 0 ? h->sys[s].desc.T_system : h->drive.T_amb;
+}
+
+static int upload_sysdev(asd_t *h)
+{
+    for (size_t s = 0; s < h->sys.size(); ++s) h->dev[s].T_amb = T_of(h, (int)s);
+    HIP_OK(h, hipMemcpyAsync(h->ws + h->L.off_sys, h->dev.data(), h->dev.size() * sizeof(SysDev),
+                             hipMemcpyHostToDevice, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    return ASD_OK;
+}
+
+static void drop_graphs(asd_t *h)
+{
+    for (int k = 0; k < 2; ++k)
+        if (h->graph[k]) {
+            (void)hipGraphExecDestroy(h->graph[k]);
+            h->graph[k] = nullptr;
+        }
+}
+
+int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, void *workspace,
+               size_t workspace_bytes, void *stream, asd_t **out)
+{
+    if (!out) return fail(nullptr, ASD_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = asd_workspace_bytes(p, sys, n_sys, &need);
+    if (rc) return rc;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
+        return fail(nullptr, ASD_EINVAL, "workspace must be a 256-byte aligned device pointer");
+    if (workspace_bytes < need)
+        return fail(nullptr, ASD_ENOMEM, "workspace of %zu bytes < %zu needed", workspace_bytes, need);
+    asd_t *h = new (std::nothrow) asd_t();
+    if (!h) return fail(nullptr, ASD_ENOMEM, "host allocation failed");
+    h->p = *p;
+    h->ws = (char *)workspace;
+    h->stream = (hipStream_t)stream;
+    h->elem = p->precision == ASD_FP64 ? 8 : 4;
+    h->kernel = p->kernel == ASD_KERNEL_FUSED ? ASD_KERNEL_FUSED : ASD_KERNEL_PLAIN;
+    h->graph_steps = p->graph_steps;
+    h->sys.resize(n_sys);
+    h->L = make_layout(p, sys, n_sys);
+    for (int s = 0; s < n_sys; ++s)
+        if ((rc = build_system(p, &sys[s], s, h->sys[s]))) {
+            delete h;
+            return rc;
+        }
+    const Layout &L = h->L;
+    // device descriptors, tile maps, grain tables
+    h->dev.resize(n_sys);
+    std::vector<int32_t> tile_sys, gsys;
+    std::vector<double> can, ku;
+    std::vector<int64_t> gptr(1, 0);
+    std::vector<int32_t> gsites;
+    std::vector<uint16_t> lab((size_t)L.ncs, kNoGrain);
+    int64_t base = 0;
+    int32_t gbase = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        HostSys &hs = h->sys[s];
+        SysDev &d = h->dev[s];
+        std::memset(&d, 0, sizeof d);
+        d.kind = p->lattice;
+        d.nx = hs.desc.nx;
+        d.ny = hs.desc.ny;
+        d.nz = hs.desc.nz;
+        d.sx = hs.sx;
+        d.bcx = hs.desc.bc_x;
+        d.bcy = hs.desc.bc_y;
+        d.bcz = hs.desc.bc_z;
+        d.track = hs.desc.bc_x == ASD_BC_TRACK;
+        d.grain_base = gbase;
+        d.n_grains = hs.n_grains;
+        d.tile_base = (int32_t)tile_sys.size();
+        d.n_tiles = (int32_t)((hs.n_window + kPlainTile - 1) / kPlainTile);
+        for (int t = 0; t < d.n_tiles; ++t) tile_sys.push_back(s);
+        d.sys_id = (uint32_t)s;
+        d.base = base;
+        d.n_stored = hs.n_stored;
+        d.n_window = hs.n_window;
+        for (int64_t i = 0; i < hs.n_stored; ++i)
+            lab[(size_t)(base + i)] = hs.labels[i] < 0 ? kNoGrain : (uint16_t)hs.labels[i];
+        // grain site lists, ascending site index within each grain
+        std::vector<int64_t> cnt(hs.n_grains + 1, 0);
+        for (int64_t i = 0; i < hs.n_stored; ++i)
+            if (hs.labels[i] >= 0) ++cnt[hs.labels[i] + 1];
+        for (int g = 0; g < hs.n_grains; ++g) cnt[g + 1] += cnt[g];
+        std::vector<int32_t> sites(cnt[hs.n_grains]);
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t i = 0; i < hs.n_stored; ++i)
+            if (hs.labels[i] >= 0) sites[fill[hs.labels[i]]++] = (int32_t)i;
+        const int64_t off0 = (int64_t)gsites.size();
+        gsites.insert(gsites.end(), sites.begin(), sites.end());
+        for (int g = 0; g < hs.n_grains; ++g) {
+            gptr.push_back(off0 + cnt[g + 1]);
+            gsys.push_back(s);
+            double kug = hs.ku_grain.empty() ? p->k_u : hs.ku_grain[g];
+            ku.push_back(kug);
+            can.push_back((2.0 * kug) / p->mu_s);
+        }
+        base += hs.n_stored;
+        gbase += hs.n_grains;
+    }
+    // fused tile map is filled per variant at step time; start with variant 0
+    h->origin.assign(n_sys, 0);
+    char *w = h->ws;
+    hipStream_t st = h->stream;
+    // zero everything: spin buffers (incl. the zero slot), counters, outputs
+    HIP_OK(h, hipMemsetAsync(w, 0, L.bytes, st));
+    HIP_OK(h, hipMemcpyAsync(w + L.off_label, lab.data(), lab.size() * sizeof(uint16_t),
+                             hipMemcpyHostToDevice, st));
+    HIP_OK(h, hipMemcpyAsync(w + L.off_tile, tile_sys.data(), tile_sys.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, st));
+    if (!can.empty()) {
+        HIP_OK(h, hipMemcpyAsync(w + L.off_can, can.data(), can.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, st));
+        HIP_OK(h, hipMemcpyAsync(w + L.off_ku, ku.data(), ku.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, st));
+        HIP_OK(h, hipMemcpyAsync(w + L.off_gsys, gsys.data(), gsys.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+    }
+    HIP_OK(h, hipMemcpyAsync(w + L.off_gptr, gptr.data(), gptr.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, st));
+    if (!gsites.empty())
+        HIP_OK(h, hipMemcpyAsync(w + L.off_gsites, gsites.data(), gsites.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+    std::vector<int32_t> ell;
+    if (p->lattice == ASD_L10) {
+        // ELL neighbour table [slot][site]; absent neighbours and unused
+        // slots point at the zero slot
+        ell.assign((size_t)kL10Degree * L.ncs, (int32_t)L.zero_site);
+        const int slots = n_neighbour_slots(p);
+        for (int s = 0; s < n_sys; ++s) {
+            const HostSys &hs = h->sys[s];
+            const int64_t b = h->dev[s].base;
+            for (int64_t i = 0; i < hs.n_stored; ++i)
+                for (int k = 0; k < slots; ++k) {
+                    int64_t j = slot_neighbour(p, hs, i, k);
+                    if (j >= 0) ell[(size_t)k * L.ncs + b + i] = (int32_t)(b + j);
+                }
+        }
+        HIP_OK(h, hipMemcpyAsync(w + L.off_ell, ell.data(), ell.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+    }
+    // initial spins: +z on magnetic sites, both ping-pong buffers
+    {
+        std::vector<char> S((size_t)3 * L.ncs * h->elem, 0);
+        for (int64_t i = 0; i < L.ncs; ++i)
+            if (lab[(size_t)i] != kNoGrain && i < L.zero_site) {
+                if (h->elem == 8) ((double *)S.data())[2 * L.ncs + i] = 1.0;
+                else ((float *)S.data())[2 * L.ncs + i] = 1.0f;
+            }
+        for (int b = 0; b < 2; ++b)
+            HIP_OK(h, hipMemcpyAsync(w + L.off_S[b], S.data(), S.size(), hipMemcpyHostToDevice, st));
+        HIP_OK(h, hipStreamSynchronize(st));
+    }
+    h->drive = asd_drive{};
+    int r2 = upload_sysdev(h);
+    if (r2) {
+        delete h;
+        return r2;
+    }
+    HIP_OK(h, hipStreamSynchronize(st));
+    *out = h;
+    return ASD_OK;
+}
+
+int asd_destroy(asd_t *h)
+{
+    if (!h) return ASD_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    delete h;
+    return ASD_OK;
+}
+
+int asd_set_field_temperature(asd_t *h, const asd_drive *d)
+{
+    if (!h || !d) return fail(h, ASD_EINVAL, "NULL argument");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(d->B[k])) return fail(h, ASD_EINVAL, "B must be finite");
+    if (d->n_bits < 0 || d->n_bits > kMaxBits || (d->n_bits > 0 && (!d->bits || d->steps_per_bit <= 0)))
+        return fail(h, ASD_EINVAL, "bits: 0..65536 entries with steps_per_bit > 0");
+    if (d->spot_mode < ASD_SPOT_NONE || d->spot_mode > ASD_SPOT_LOCKED)
+        return fail(h, ASD_EINVAL, "unknown spot mode");
+    if (!(d->T_amb >= 0) || (d->spot_mode != ASD_SPOT_NONE && !(d->T_peak >= 0 && d->fwhm > 0)))
+        return fail(h, ASD_EINVAL, "temperatures must be >= 0 and fwhm > 0 with a spot");
+    h->drive = *d;
+    h->drive.bits = nullptr;
+    h->bits.assign(d->bits, d->bits + d->n_bits);
+    if (d->n_bits > 0)
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.off_bits, h->bits.data(), h->bits.size(),
+                                 hipMemcpyHostToDevice, h->stream));
+    drop_graphs(h);  // constants are baked into captured launches
+    return upload_sysdev(h);
+}
+
+static size_t spin_bytes(const asd_t *h, int s) { return (size_t)h->sys[s].n_stored * h->elem; }
+
+int asd_set_spins(asd_t *h, int32_t s, const void *src, int32_t on_device)
+{
+    if (!h || !src) return fail(h, ASD_EINVAL, "NULL argument");
+    if (s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad system index");
+    const SysDev &d = h->dev[s];
+    const size_t nb = spin_bytes(h, s);
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int b = 0; b < 2; ++b) {
+        char *dst = h->ws + h->L.off_S[b];
+        for (int k = 0; k < 3; ++k)
+            HIP_OK(h, hipMemcpyAsync(dst + ((size_t)k * h->L.ncs + d.base) * h->elem,
+                                     (const char *)src + k * nb, nb, kind, h->stream));
+        if (launch_mask_spins(h->p.precision, dst, h->L.ncs,
+                              (const uint16_t *)(h->ws + h->L.off_label), d, h->stream))
+            return fail(h, ASD_EHIP, "mask kernel launch failed");
+    }
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    return ASD_OK;
+}
+
+int asd_get_spins(asd_t *h, int32_t s, void *dst, int32_t on_device)
+{
+    if (!h || !dst) return fail(h, ASD_EINVAL, "NULL argument");
+    if (s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad system index");
+    const SysDev &d = h->dev[s];
+    const size_t nb = spin_bytes(h, s);
+    const char *src = h->ws + h->L.off_S[h->cur];
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int k = 0; k < 3; ++k)
+        HIP_OK(h, hipMemcpyAsync((char *)dst + k * nb, src + ((size_t)k * h->L.ncs + d.base) * h->elem,
+                                 nb, kind, h->stream));
+    if (!on_device) HIP_OK(h, hipStreamSynchronize(h->stream));
+    return ASD_OK;
+}
+
+static StepConsts make_consts(const asd_t *h)
+{
+    const asd_params &p = h->p;
+    const asd_drive &dr = h->drive;
+    StepConsts c;
+    std::memset(&c, 0, sizeof c);
+    for (int s = 0; s < p.n_shells; ++s) c.cex[s] = p.J[s] / p.mu_s;
+    c.can = (2.0 * p.k_u) / p.mu_s;
+    c.gp = -p.gamma / (1.0 + p.alpha * p.alpha);
+    c.alpha = p.alpha;
+    c.dt = p.dt;
+    c.h = 0.5 * p.dt;
+    c.cth = ((2.0 * p.alpha) * kBoltzmann) / ((p.gamma * p.mu_s) * p.dt);
+    for (int k = 0; k < 3; ++k) c.B[k] = dr.B[k];
+    c.T_peak = dr.T_peak;
+    if (dr.spot_mode != ASD_SPOT_NONE) {
+        double sd = dr.fwhm / 2.3548200450309493;
+        c.inv2s2 = 1.0 / ((2.0 * sd) * sd);
+    }
+    c.x0 = dr.x0;
+    c.y0 = dr.y0;
+    c.v = dr.v;
+    c.hx = p.lattice == ASD_SC ? p.a : 0.5 * p.a;
+    c.spb = dr.steps_per_bit;
+    c.n_bits = dr.n_bits;
+    c.spot_mode = dr.spot_mode;
+    c.n_shells = p.n_shells;
+    c.rounds = p.philox_rounds;
+    c.k0 = (uint32_t)p.seed;
+    c.k1 = (uint32_t)(p.seed >> 32);
+    bool per_grain = false;
+    for (const HostSys &hs : h->sys)
+        if (!hs.ku_grain.empty()) per_grain = true;
+    c.has_can_grain = per_grain ? 1 : 0;
+    return c;
+}
+
+template <typename T>
+static StepArgs<T> make_args(const asd_t *h, int cur, int step_off)
+{
+    const Layout &L = h->L;
+    char *w = h->ws;
+    StepArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.S = (const T *)(w + L.off_S[cur]);
+    a.So = (T *)(w + L.off_S[1 - cur]);
+    a.Sp = (T *)(w + L.off_S[2]);
+    a.ncs = L.ncs;
+    a.sys = (const SysDev *)(w + L.off_sys);
+    a.tile_sys = (const int32_t *)(w + (h->kernel == ASD_KERNEL_FUSED ? L.off_ftile : L.off_tile));
+    a.ell = h->p.lattice == ASD_L10 ? (const int32_t *)(w + L.off_ell) : nullptr;
+    a.label = (const uint16_t *)(w + L.off_label);
+    a.can_grain = (const double *)(w + L.off_can);
+    a.step_base = (const int64_t *)(w + L.off_step);
+    a.origin = (const int32_t *)(w + L.off_origin);
+    a.bits = (const uint8_t *)(w + L.off_bits);
+    a.zero_site = L.zero_site;
+    a.step_off = step_off;
+    a.tile_cfg = h->tile_cfg;
+    a.c = make_consts(h);
+    return a;
+}
+
+static int launch_one(asd_t *h, int cur, int step_off)
+{
+    int rc;
+    const bool fused = h->kernel == ASD_KERNEL_FUSED;
+    const int blocks = fused ? h->L.n_ftiles : h->L.n_tiles;
+    if (h->p.precision == ASD_FP64) {
+        StepArgs<double> a = make_args<double>(h, cur, step_off);
+        rc = fused ? launch_fused_step_f64(a, blocks, h->stream) : launch_plain_step_f64(a, blocks, h->stream);
+    } else {
+        StepArgs<float> a = make_args<float>(h, cur, step_off);
+        rc = fused ? launch_fused_step_f32(a, blocks, h->stream) : launch_plain_step_f32(a, blocks, h->stream);
+    }
+    if (rc == -2) return fail(h, ASD_EUNSUPPORTED, "fused kernel not available for this lattice");
+    if (rc) return fail(h, ASD_EHIP, "step kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return ASD_OK;
+}
+
+static int capture_graph(asd_t *h, int cur)
+{
+    hipGraph_t g = nullptr;
+    HIP_OK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = ASD_OK;
+    int c = cur;
+    for (int t = 0; t < h->graph_steps && rc == ASD_OK; ++t) {
+        rc = launch_one(h, c, t);
+        c = 1 - c;
+    }
+    if (rc == ASD_OK && launch_advance_step((int64_t *)(h->ws + h->L.off_step), h->graph_steps, h->stream))
+        rc = fail(h, ASD_EHIP, "advance launch failed");
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(h, ASD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->graph[cur], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(h, ASD_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    h->graph_kernel = h->kernel;
+    h->graph_tile = h->tile_cfg;
+    return ASD_OK;
+}
+
+int asd_step(asd_t *h, int64_t n)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (n < 0) return fail(h, ASD_EINVAL, "n must be >= 0");
+    if (h->step + n >= ((int64_t)1 << 32))
+        return fail(h, ASD_ESTATE, "step counter would exceed 2^32 (Philox counter word)");
+    if (n == 0) return ASD_OK;
+    int64_t done = 0;
+    if (h->graph_steps > 0 && n >= h->graph_steps) {
+        if (h->graph_kernel != h->kernel || h->graph_tile != h->tile_cfg) drop_graphs(h);
+        while (n - done >= h->graph_steps) {
+            if (!h->graph[h->cur]) {
+                int rc = capture_graph(h, h->cur);
+                if (rc) return rc;
+            }
+            HIP_OK(h, hipGraphLaunch(h->graph[h->cur], h->stream));
+            done += h->graph_steps;
+            h->step += h->graph_steps;  // graph_steps is even: the parity is unchanged
+        }
+    }
+    const int64_t rest = n - done;
+    for (int64_t t = 0; t < rest; ++t) {
+        int rc = launch_one(h, h->cur, (int)t);
+        if (rc) return rc;
+        h->cur = 1 - h->cur;
+    }
+    if (rest > 0) {
+        if (launch_advance_step((int64_t *)(h->ws + h->L.off_step), rest, h->stream))
+            return fail(h, ASD_EHIP, "advance launch failed");
+        h->step += rest;
+    }
+    return ASD_OK;
+}
+
+int asd_shift_window(asd_t *h, int32_t columns)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (columns < 0) return fail(h, ASD_EINVAL, "columns must be >= 0");
+    bool any = false;
+    for (size_t s = 0; s < h->sys.size(); ++s) {
+        const SysDev &d = h->dev[s];
+        if (!d.track) continue;
+        any = true;
+        if ((int64_t)h->origin[s] + d.nx + columns > d.sx)
+            return fail(h, ASD_ESTATE, "system %zu: window would leave its track", s);
+    }
+    if (!any) return fail(h, ASD_EINVAL, "no system has a track");
+    if (columns == 0) return ASD_OK;
+    char *cur = h->ws + h->L.off_S[h->cur];
+    char *oth = h->ws + h->L.off_S[1 - h->cur];
+    for (size_t s = 0; s < h->sys.size(); ++s) {
+        const SysDev &d = h->dev[s];
+        if (!d.track) continue;
+        // leaving columns freeze with their current spins in both buffers
+        if (launch_copy_columns(h->p.precision, oth, cur, h->L.ncs, d, h->origin[s], columns, h->stream))
+            return fail(h, ASD_EHIP, "column copy failed");
+        h->origin[s] += columns;
+    }
+    if (launch_set_i32((int32_t *)(h->ws + h->L.off_origin), h->origin.data(), (int)h->origin.size(),
+                       h->stream))
+        return fail(h, ASD_EHIP, "origin update failed");
+    return ASD_OK;
+}
+
+static RedArgs red_args(const asd_t *h)
+{
+    const Layout &L = h->L;
+    char *w = h->ws;
+    RedArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.S = w + L.off_S[h->cur];
+    a.prec = h->p.precision;
+    a.ncs = L.ncs;
+    a.sys = (const SysDev *)(w + L.off_sys);
+    a.grain_sys = (const int32_t *)(w + L.off_gsys);
+    a.grain_ptr = (const int64_t *)(w + L.off_gptr);
+    a.grain_sites = (const int32_t *)(w + L.off_gsites);
+    a.origin = (const int32_t *)(w + L.off_origin);
+    a.grain_out = (double *)(w + L.off_gout);
+    a.sys_out = (double *)(w + L.off_sout);
+    a.moments = (double *)(w + L.off_mom);
+    a.n_grains = L.n_grains;
+    a.n_sys = (int)h->sys.size();
+    return a;
+}
+
+int asd_reduce_magnetization(asd_t *h, double *per_grain, double *per_system)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    RedArgs a = red_args(h);
+    if (launch_reduce_grains(a, h->stream) || launch_reduce_systems(a, 0, 0, h->stream))
+        return fail(h, ASD_EHIP, "reduction launch failed");
+    std::vector<double> g((size_t)4 * std::max(a.n_grains, 1)), s((size_t)4 * a.n_sys);
+    HIP_OK(h, hipMemcpyAsync(g.data(), a.grain_out, (size_t)4 * a.n_grains * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipMemcpyAsync(s.data(), a.sys_out, s.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    if (per_grain) std::memcpy(per_grain, g.data(), (size_t)4 * a.n_grains * sizeof(double));
+    if (per_system) std::memcpy(per_system, s.data(), s.size() * sizeof(double));
+    for (double v : s)
+        if (!std::isfinite(v)) return fail(h, ASD_ENONFINITE, "non-finite magnetisation");
+    return ASD_OK;
+}
+
+int asd_accumulate_moments(asd_t *h, int32_t reset)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    RedArgs a = red_args(h);
+    if (launch_reduce_grains(a, h->stream) || launch_reduce_systems(a, 1, reset ? 1 : 0, h->stream))
+        return fail(h, ASD_EHIP, "reduction launch failed");
+    return ASD_OK;
+}
+
+int asd_get_moment_stats(asd_t *h, double *per_system)
+{
+    if (!h || !per_system) return fail(h, ASD_EINVAL, "NULL argument");
+    HIP_OK(h, hipMemcpyAsync(per_system, h->ws + h->L.off_mom, h->sys.size() * 5 * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    for (size_t k = 0; k < h->sys.size() * 5; ++k)
+        if (!std::isfinite(per_system[k])) return fail(h, ASD_ENONFINITE, "non-finite moment");
+    return ASD_OK;
+}
+
+int asd_reduce_energy(asd_t *h, double *per_system)
+{
+    if (!h || !per_system) return fail(h, ASD_EINVAL, "NULL argument");
+    const Layout &L = h->L;
+    char *w = h->ws;
+    int rc;
+    const int saved = h->kernel;
+    h->kernel = ASD_KERNEL_PLAIN;  // energy uses the plain tile map
+    if (h->p.precision == ASD_FP64) {
+        EnergyArgs<double> e;
+        std::memset(&e, 0, sizeof e);
+        e.st = make_args<double>(h, h->cur, 0);
+        e.partial = (double *)(w + L.off_epart);
+        for (int s = 0; s < 4; ++s) e.J[s] = h->p.J[s];
+        e.mu_s = h->p.mu_s;
+        e.ku = h->p.k_u;
+        e.ku_grain = (const double *)(w + L.off_ku);
+        rc = launch_energy_f64(e, L.n_tiles, h->stream);
+    } else {
+        EnergyArgs<float> e;
+        std::memset(&e, 0, sizeof e);
+        e.st = make_args<float>(h, h->cur, 0);
+        e.partial = (double *)(w + L.off_epart);
+        for (int s = 0; s < 4; ++s) e.J[s] = h->p.J[s];
+        e.mu_s = h->p.mu_s;
+        e.ku = h->p.k_u;
+        e.ku_grain = (const double *)(w + L.off_ku);
+        rc = launch_energy_f32(e, L.n_tiles, h->stream);
+    }
+    h->kernel = saved;
+    if (rc || launch_energy_finish((const double *)(w + L.off_epart), (const SysDev *)(w + L.off_sys),
+                                   (int)h->sys.size(), (double *)(w + L.off_eout), h->stream))
+        return fail(h, ASD_EHIP, "energy launch failed");
+    HIP_OK(h, hipMemcpyAsync(per_system, w + L.off_eout, h->sys.size() * 4 * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    for (size_t k = 0; k < h->sys.size() * 4; ++k)
+        if (!std::isfinite(per_system[k])) return fail(h, ASD_ENONFINITE, "non-finite energy");
+    return ASD_OK;
+}
+
+int asd_grain_count(asd_t *h, int32_t s, int32_t *n)
+{
+    if (!h || !n || s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad argument");
+    *n = h->sys[s].n_grains;
+    return ASD_OK;
+}
+
+int asd_stored_sites(asd_t *h, int32_t s, int64_t *n)
+{
+    if (!h || !n || s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad argument");
+    *n = h->sys[s].n_stored;
+    return ASD_OK;
+}
+
+int asd_get_grain_labels(asd_t *h, int32_t s, int32_t *labels)
+{
+    if (!h || !labels || s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad argument");
+    std::memcpy(labels, h->sys[s].labels.data(), h->sys[s].labels.size() * sizeof(int32_t));
+    return ASD_OK;
+}
+
+int asd_neighbour_count(asd_t *h, int32_t s, int64_t *n_entries)
+{
+    if (!h || !n_entries || s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad argument");
+    const HostSys &hs = h->sys[s];
+    const int slots = n_neighbour_slots(&h->p);
+    int64_t c = 0;
+    for (int64_t i = 0; i < hs.n_stored; ++i)
+        for (int k = 0; k < slots; ++k)
+            if (slot_neighbour(&h->p, hs, i, k) >= 0) ++c;
+    *n_entries = c;
+    return ASD_OK;
+}
+
+int asd_get_neighbours(asd_t *h, int32_t s, int64_t *row_ptr, int32_t *col, int8_t *shell)
+{
+    if (!h || !row_ptr || !col || !shell || s < 0 || s >= (int)h->sys.size())
+        return fail(h, ASD_EINVAL, "bad argument");
+    const HostSys &hs = h->sys[s];
+    const int slots = n_neighbour_slots(&h->p);
+    int64_t c = 0;
+    for (int64_t i = 0; i < hs.n_stored; ++i) {
+        row_ptr[i] = c;
+        for (int k = 0; k < slots; ++k) {
+            int64_t j = slot_neighbour(&h->p, hs, i, k);
+            if (j < 0) continue;
+            col[c] = (int32_t)j;
+            shell[c] = (int8_t)slot_shell(&h->p, k);
+            ++c;
+        }
+    }
+    row_ptr[hs.n_stored] = c;
+    return ASD_OK;
+}
+
+int asd_get_state(asd_t *h, int32_t s, int64_t *step, int32_t *origin)
+{
+    if (!h || s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad argument");
+    if (step) *step = h->step;
+    if (origin) *origin = h->origin[s];
+    return ASD_OK;
+}
+
+int asd_set_step(asd_t *h, int64_t step)
+{
+    if (!h || step < 0 || step >= ((int64_t)1 << 32)) return fail(h, ASD_EINVAL, "bad step");
+    HIP_OK(h, hipMemcpyAsync(h->ws + h->L.off_step, &step, sizeof step, hipMemcpyHostToDevice,
+                             h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    h->step = step;
+    return ASD_OK;
+}
+
+int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out, int64_t n,
+               void *stream)
+{
+    if (n < 0 || (n > 0 && (!ctr || !out))) return fail(nullptr, ASD_EINVAL, "bad arguments");
+    if (rounds < 1 || rounds > 10) return fail(nullptr, ASD_EINVAL, "rounds must be 1..10");
+    if (launch_philox_export(seed, rounds, ctr, out, n, stream))
+        return fail(nullptr, ASD_EHIP, "philox launch failed");
+    return ASD_OK;
+}
+
+int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (kernel != ASD_KERNEL_PLAIN && kernel != ASD_KERNEL_FUSED)
+        return fail(h, ASD_EINVAL, "kernel must be PLAIN or FUSED");
+    if (tile < 0 || tile >= fused_tile_variants(h->p.lattice))
+        return fail(h, ASD_EINVAL, "tile variant out of range");
+    h->kernel = kernel;
+    h->tile_cfg = tile;
+    drop_graphs(h);
+    return ASD_OK;
+}
+
+int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (kernel) *kernel = h->kernel;
+    if (tile) *tile = h->tile_cfg;
+    return ASD_OK;
+}
+
+int asd_autotune(asd_t *h, const char *cache_path)
+{
+    (void)cache_path;
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    return fail(h, ASD_EUNSUPPORTED, "autotune not built yet");
+}
+

@@ -1,0 +1,121 @@
+// asd_internal.h -- layout shared by the host code and the kernels of libasd.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace asd {
+
+constexpr int kPlainTile = 256;      // window sites per block in the two-pass kernels
+constexpr uint16_t kNoGrain = 0xFFFF; // label of a non-magnetic site
+constexpr int kL10Degree = 18;        // ELL slots of the 4-shell L1_0 table
+
+// Per-system descriptor, resident in device memory.
+struct SysDev {
+    int32_t kind;             // ASD_SC / ASD_L10
+    int32_t nx, ny, nz;       // window cells
+    int32_t sx;               // stored x cells (track_nx or nx)
+    int32_t bcx, bcy, bcz;    // ASD_BC_*
+    int32_t track;            // 1 when x is a track
+    int32_t grain_base;       // first global grain index
+    int32_t n_grains;
+    int32_t tile_base;        // first tile of this system (plain kernels)
+    int32_t n_tiles;
+    int32_t ftile_base;       // first tile of this system (fused kernel)
+    int32_t ftiles_x, ftiles_y;
+    uint32_t sys_id;          // Philox counter word 2
+    int32_t pad0;
+    int64_t base;             // first stored site in the global arrays
+    int64_t n_stored;
+    int64_t n_window;         // sites in the window
+    double T_amb;             // ambient temperature of this system (K)
+};
+
+// Per-step constants (kernel argument, by value).
+struct StepConsts {
+    double cex[4];            // J_s / mu_s per shell
+    double can;               // 2 k_u / mu_s (uniform)
+    double gp;                // -gamma / (1 + alpha^2)
+    double alpha, dt, h;      // h = dt / 2
+    double cth;               // 2 alpha kB / (gamma mu_s dt)
+    double B[3];              // write field (T), before polarity
+    double T_peak, inv2s2, x0, y0, v;
+    double hx;                // x, y site unit (m): a (SC) or a/2 (L1_0)
+    int64_t spb;              // steps per bit
+    int32_t n_bits, spot_mode, n_shells, rounds;
+    uint32_t k0, k1;          // Philox key
+    int32_t has_can_grain;
+    int32_t pad;
+};
+
+template <typename T>
+struct StepArgs {
+    const T *S;               // current spins [3][ncs]
+    T *Sp;                    // predicted spins (two-pass) [3][ncs]
+    T *So;                    // next spins [3][ncs]
+    int64_t ncs;              // component stride
+    const SysDev *sys;
+    const int32_t *tile_sys;  // block -> system
+    const int32_t *ell;       // L1_0 neighbours [kL10Degree][ncs] (absent: zero_site)
+    const uint16_t *label;    // local grain label per stored site
+    const double *can_grain;  // 2 k_u,g / mu_s per global grain
+    const int64_t *step_base; // device step counter
+    const int32_t *origin;    // window origin per system
+    const uint8_t *bits;      // polarity bits
+    int64_t zero_site;        // an always-zero slot
+    int32_t step_off;         // step = *step_base + step_off
+    int32_t tile_cfg;         // fused kernel tile variant
+    StepConsts c;
+};
+
+// launchers (asd_step_f64.hip / asd_step_f32.hip)
+int launch_plain_step_f64(const StepArgs<double> &a, int n_blocks, void *stream);
+int launch_plain_step_f32(const StepArgs<float> &a, int n_blocks, void *stream);
+int launch_fused_step_f64(const StepArgs<double> &a, int n_blocks, void *stream);
+int launch_fused_step_f32(const StepArgs<float> &a, int n_blocks, void *stream);
+// fused tile geometry for a tile variant: interior tile (tx, ty) in cells
+void fused_tile_shape(int kind, int tile_cfg, int *tx, int *ty);
+int fused_tile_variants(int kind);
+
+// misc kernels (asd_misc.hip)
+int launch_philox_export(uint64_t seed, int rounds, const uint32_t *ctr, uint32_t *out, int64_t n,
+                         void *stream);
+int launch_advance_step(int64_t *step_base, int64_t n, void *stream);
+int launch_set_i32(int32_t *dst, const int32_t *vals, int n, void *stream);
+// copy stored columns [x0, x0 + ncols) of system d from src to dst (both [3][ncs])
+int launch_copy_columns(int prec, void *dst, const void *src, int64_t ncs, const SysDev &d, int x0,
+                        int ncols, void *stream);
+// zero the spins of non-magnetic sites of system d in buf ([3][ncs])
+int launch_mask_spins(int prec, void *buf, int64_t ncs, const uint16_t *label, const SysDev &d,
+                      void *stream);
+struct RedArgs {
+    const void *S;            // spins [3][ncs]
+    int prec;                 // 0 FP64, 1 FP32
+    int64_t ncs;
+    const SysDev *sys;
+    const int32_t *grain_sys;   // global grain -> system
+    const int64_t *grain_ptr;   // global grain -> [begin, end) in grain_sites
+    const int32_t *grain_sites; // local stored site indices, grain-major
+    const int32_t *origin;
+    double *grain_out;          // [G][4]
+    double *sys_out;            // [S][4]
+    double *moments;            // [S][5]
+    int n_grains, n_sys;
+};
+int launch_reduce_grains(const RedArgs &a, void *stream);
+int launch_reduce_systems(const RedArgs &a, int accumulate_moments, int reset, void *stream);
+template <typename T>
+struct EnergyArgs {
+    StepArgs<T> st;           // spins, tables, constants (S = current)
+    double *partial;          // [n_tiles][3]: exchange, anisotropy, Zeeman
+    double J[4];              // exchange per shell (J)
+    double mu_s, ku;          // J/T, J
+    const double *ku_grain;   // per global grain (J) when has_can_grain
+};
+// sum the energy partials of each system's tiles in order -> [S][4]
+int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, double *sys_out,
+                         void *stream);
+int launch_energy_f64(const EnergyArgs<double> &a, int n_tiles, void *stream);
+int launch_energy_f32(const EnergyArgs<float> &a, int n_tiles, void *stream);
+
+}  // namespace asd

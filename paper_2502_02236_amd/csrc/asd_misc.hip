@@ -1,0 +1,246 @@
+// asd_misc.hip -- Philox export, step-counter and window bookkeeping,
+// column freezing for window shifts, and the FP64 reductions.
+#include "asd_device.h"
+#include "asd_internal.h"
+#include "asd.h"
+
+namespace asd {
+
+__global__ void k_philox_export(uint32_t k0, uint32_t k1, int rounds, const uint32_t *ctr,
+                                uint32_t *out, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 c = reinterpret_cast<const uint4 *>(ctr)[i];
+    Words4 w = philox4x32(rounds, k0, k1, c.x, c.y, c.z, c.w);
+    reinterpret_cast<uint4 *>(out)[i] = make_uint4(w.w0, w.w1, w.w2, w.w3);
+}
+
+int launch_philox_export(uint64_t seed, int rounds, const uint32_t *ctr, uint32_t *out, int64_t n,
+                         void *stream)
+{
+    if (n == 0) return 0;
+    int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_philox_export, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), rounds, ctr, out, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ void k_advance(int64_t *step_base, int64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n;
+}
+
+int launch_advance_step(int64_t *step_base, int64_t n, void *stream)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, (hipStream_t)stream, step_base, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+struct I32x8 {
+    int32_t v[8];
+};
+
+__global__ void k_set_i32(int32_t *dst, I32x8 vals, int n)
+{
+    int i = threadIdx.x;
+    if (i < n) dst[i] = vals.v[i];
+}
+
+int launch_set_i32(int32_t *dst, const int32_t *vals, int n, void *stream)
+{
+    for (int off = 0; off < n; off += 8) {
+        I32x8 v{};
+        int m = n - off < 8 ? n - off : 8;
+        for (int k = 0; k < m; ++k) v.v[k] = vals[off + k];
+        hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, (hipStream_t)stream, dst + off, v, m);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// copy stored columns [x0, x0 + ncols) of one system from src to dst
+template <typename T>
+__global__ void k_copy_columns(T *dst, const T *src, int64_t ncs, int64_t base, int kind, int sx,
+                               int ny, int nz, int x0, int ncols)
+{
+    int per_col = (kind == ASD_SC ? 1 : 2);
+    int64_t m = (int64_t)ncols * ny * nz * per_col;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    int s = (int)(t % per_col);
+    int64_t r = t / per_col;
+    int xc = (int)(r % ncols);
+    int64_t yz = r / ncols;
+    int64_t cell = (x0 + xc) + (int64_t)sx * yz;
+    int64_t i = base + cell * per_col + s;
+    for (int k = 0; k < 3; ++k) dst[k * ncs + i] = src[k * ncs + i];
+}
+
+int launch_copy_columns(int prec, void *dst, const void *src, int64_t ncs, const SysDev &d, int x0,
+                        int ncols, void *stream)
+{
+    int per_col = (d.kind == ASD_SC ? 1 : 2);
+    int64_t m = (int64_t)ncols * d.ny * d.nz * per_col;
+    if (m == 0) return 0;
+    unsigned blocks = (unsigned)((m + 255) / 256);
+    if (prec == ASD_FP64)
+        hipLaunchKernelGGL(k_copy_columns<double>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (double *)dst, (const double *)src, ncs, d.base, d.kind, d.sx, d.ny, d.nz,
+                           x0, ncols);
+    else
+        hipLaunchKernelGGL(k_copy_columns<float>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (float *)dst, (const float *)src, ncs, d.base, d.kind, d.sx, d.ny, d.nz,
+                           x0, ncols);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+__global__ void k_mask(T *buf, int64_t ncs, const uint16_t *label, int64_t base, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int64_t i = base + t;
+    if (label[i] == kNoGrain) {
+        buf[i] = 0;
+        buf[ncs + i] = 0;
+        buf[2 * ncs + i] = 0;
+    }
+}
+
+int launch_mask_spins(int prec, void *buf, int64_t ncs, const uint16_t *label, const SysDev &d,
+                      void *stream)
+{
+    if (d.n_stored == 0) return 0;
+    unsigned blocks = (unsigned)((d.n_stored + 255) / 256);
+    if (prec == ASD_FP64)
+        hipLaunchKernelGGL(k_mask<double>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (double *)buf, ncs, label, d.base, d.n_stored);
+    else
+        hipLaunchKernelGGL(k_mask<float>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (float *)buf, ncs, label, d.base, d.n_stored);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------- reductions
+// One block per grain walks the grain's site list (ascending site index),
+// keeps the sites inside the window, accumulates in FP64 per thread, and
+// reduces the block in a fixed tree order: deterministic, no atomics.
+constexpr int kRedBlock = 256;
+
+__device__ __forceinline__ bool site_in_window(const SysDev &d, int org, int64_t local)
+{
+    if (!d.track) return true;
+    int64_t cell = d.kind == ASD_SC ? local : (local >> 1);
+    int32_t X = (int32_t)(cell % d.sx);
+    return X >= org && X < org + d.nx;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_reduce_grains(RedArgs a)
+{
+    const int g = blockIdx.x;
+    const int s = a.grain_sys[g];
+    const SysDev d = a.sys[s];
+    const int org = d.track ? a.origin[s] : 0;
+    const T *S = (const T *)a.S;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = a.grain_ptr[g] + threadIdx.x; k < a.grain_ptr[g + 1]; k += kRedBlock) {
+        int64_t local = a.grain_sites[k];
+        if (!site_in_window(d, org, local)) continue;
+        int64_t i = d.base + local;
+        acc[0] += (double)S[i];
+        acc[1] += (double)S[a.ncs + i];
+        acc[2] += (double)S[2 * a.ncs + i];
+        acc[3] += 1.0;
+    }
+    __shared__ double red[4][kRedBlock];
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) a.grain_out[4 * (int64_t)g + k] = red[k][0];
+}
+
+int launch_reduce_grains(const RedArgs &a, void *stream)
+{
+    if (a.n_grains == 0) return 0;
+    if (a.prec == ASD_FP64)
+        hipLaunchKernelGGL(k_reduce_grains<double>, dim3(a.n_grains), dim3(kRedBlock), 0,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_reduce_grains<float>, dim3(a.n_grains), dim3(kRedBlock), 0,
+                           (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// per system: ordered sum over its grains; optional moment statistics of
+// m = |M| / N: samples, sum m, sum m^2, sum m^4
+__global__ void k_reduce_systems(RedArgs a, int moments, int reset)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_sys) return;
+    const SysDev d = a.sys[s];
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = d.grain_base; g < d.grain_base + d.n_grains; ++g)
+        for (int k = 0; k < 4; ++k) t[k] += a.grain_out[4 * (int64_t)g + k];
+    for (int k = 0; k < 4; ++k) a.sys_out[4 * (int64_t)s + k] = t[k];
+    if (moments) {
+        double *mo = a.moments + 5 * (int64_t)s;
+        if (reset)
+            for (int k = 0; k < 5; ++k) mo[k] = 0.0;
+        double m = t[3] > 0.0 ? sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]) / t[3] : 0.0;
+        double m2 = m * m;
+        mo[0] += 1.0;
+        mo[1] += m;
+        mo[2] += m2;
+        mo[3] += m2 * m2;
+    }
+}
+
+int launch_reduce_systems(const RedArgs &a, int moments, int reset, void *stream)
+{
+    if (a.n_sys == 0) return 0;
+    hipLaunchKernelGGL(k_reduce_systems, dim3((a.n_sys + 63) / 64), dim3(64), 0,
+                       (hipStream_t)stream, a, moments, reset);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ void k_energy_finish(const double *partial, const SysDev *sys, int n_sys, double *out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sys) return;
+    const SysDev d = sys[s];
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int b = d.tile_base; b < d.tile_base + d.n_tiles; ++b)
+        for (int k = 0; k < 3; ++k) t[k] += partial[3 * (int64_t)b + k];
+    for (int k = 0; k < 3; ++k) out[4 * (int64_t)s + k] = t[k];
+    out[4 * (int64_t)s + 3] = (t[0] + t[1]) + t[2];
+}
+
+int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, double *sys_out,
+                         void *stream)
+{
+    hipLaunchKernelGGL(k_energy_finish, dim3((n_sys + 63) / 64), dim3(64), 0, (hipStream_t)stream,
+                       partial, sys, n_sys, sys_out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void fused_tile_shape(int kind, int tile_cfg, int *tx, int *ty)
+{
+    (void)kind;
+    (void)tile_cfg;
+    *tx = 62;
+    *ty = 14;
+}
+
+int fused_tile_variants(int kind)
+{
+    (void)kind;
+    return 1;
+}
+
+}  // namespace asd

@@ -1,0 +1,27 @@
+// FP32 instantiation of the Heun step kernels (per-spin field and update in
+// FP32; spot position and time in FP64).
+#include "asd_step.inc"
+#include "asd_fused.inc"
+
+namespace asd {
+
+int launch_plain_step_f32(const StepArgs<float> &a, int n_blocks, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_plain_predictor<float>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
+    hipLaunchKernelGGL(k_plain_corrector<float>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fused_step_f32(const StepArgs<float> &a, int n_blocks, void *stream)
+{
+    return launch_fused<float>(a, n_blocks, stream);
+}
+
+int launch_energy_f32(const EnergyArgs<float> &e, int n_tiles, void *stream)
+{
+    hipLaunchKernelGGL(k_energy<float>, dim3(n_tiles), dim3(kPlainTile), 0, (hipStream_t)stream, e);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace asd

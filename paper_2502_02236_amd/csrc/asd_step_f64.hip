@@ -1,0 +1,28 @@
+// FP64 instantiation of the Heun step kernels.  Built with -ffp-contract=off:
+// every FP64 operation rounds as written (IEEE round-to-nearest), in the
+// fixed order of asd_step.inc.
+#include "asd_step.inc"
+#include "asd_fused.inc"
+
+namespace asd {
+
+int launch_plain_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_plain_predictor<double>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
+    hipLaunchKernelGGL(k_plain_corrector<double>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fused_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)
+{
+    return launch_fused<double>(a, n_blocks, stream);
+}
+
+int launch_energy_f64(const EnergyArgs<double> &e, int n_tiles, void *stream)
+{
+    hipLaunchKernelGGL(k_energy<double>, dim3(n_tiles), dim3(kPlainTile), 0, (hipStream_t)stream, e);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace asd

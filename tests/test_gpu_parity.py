@@ -1,0 +1,264 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: bit-exact for Philox words, grain labels and neighbour tables; FP64
+spins within 1e-12 per component after 100 steps; FP32 spins within 1e-4 per
+component after 100 steps; FP64 reductions within 1e-12 relative.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle_build import oracle_labels, oracle_system, window_mask
+from paper_2502_02236_amd import asd as A
+from paper_2502_02236_amd import bridge
+
+pytestmark = pytest.mark.gpu
+
+TOL = {A.ASD_FP64: 1e-12, A.ASD_FP32: 1e-4}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    A.lib()
+    return torch
+
+
+# ---------------------------------------------------------------- workloads
+def c2_crop(**kw):
+    w = W.c2_granular_slab().scaled(nx=37, ny=29, nz=7, x0=5e-9, y0=4e-9, grain_pitch=4.0e-9,
+                                    steps=100)
+    return w.scaled(**kw)
+
+
+def c3_crop(**kw):
+    w = W.c3_l10_window().scaled(nx=13, ny=11, nz=5, x0=2e-9, y0=2e-9, grain_pitch=3.0e-9,
+                                 steps=100)
+    return w.scaled(**kw)
+
+
+def c5_crop(**kw):
+    w = W.c5_track_window().scaled(nx=30, ny=20, nz=5, track_nx=48, steps_per_bit=25,
+                                   x0=4.5e-9, y0=3e-9, grain_pitch=3.0e-9)
+    return w.scaled(**kw)
+
+
+def initial_state(w, labels):
+    S = W.initial_spins(len(labels), w.seed + 100)
+    S[:, labels < 0] = 0.0
+    return S
+
+
+def run_gpu(w, precision, steps, kernel=A.ASD_KERNEL_PLAIN, S0=None, ku=None, shifts=(),
+            graph_steps=0):
+    h = bridge.make_handle(w, precision, kernel=kernel, ku_grain=ku, graph_steps=graph_steps)
+    lab = h.labels()
+    if S0 is None:
+        S0 = initial_state(w, lab)
+    h.set_spins(S0)
+    done = 0
+    for at, cols in list(shifts) + [(steps, 0)]:
+        h.step(at - done)
+        done = at
+        if cols:
+            h.shift_window(cols)
+    return h, lab, S0
+
+
+def run_oracle(w, labels, S0, steps, ku=None, shifts=(), sys_id=0, T_amb=None):
+    track = w.bc[0] == W.BC_TRACK
+    org = 0
+    sysm = oracle_system(w, labels=labels, ku_grain=ku, sys_id=sys_id, T_amb=T_amb,
+                         active=window_mask(w, 0) if track else None, origin=0)
+    S = np.array(S0, dtype=np.float64)
+    done = 0
+    for at, cols in list(shifts) + [(steps, 0)]:
+        S = sysm.heun(S, done, at - done)
+        done = at
+        if cols:
+            org += cols
+            sysm.set_active(window_mask(w, org), org)
+    return sysm, S
+
+
+def maxdiff(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64))))
+
+
+# ---------------------------------------------------------------- bit-exact tables
+def test_philox_export_bit_exact(gpu):
+    torch = gpu
+    rng = np.random.default_rng(5)
+    n = 1 << 20
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    edge = np.array([0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFE, 0xFFFFFFFF], dtype=np.uint32)
+    ctr[:6 ** 4] = np.stack(np.meshgrid(edge, edge, edge, edge, indexing="ij"), -1).reshape(-1, 4)
+    dev_in = torch.from_numpy(ctr.view(np.int32)).cuda()
+    dev_out = torch.empty_like(dev_in)
+    for seed, rounds in ((1, 10), (0xFFFFFFFFFFFFFFFF, 10), (0x0123456789ABCDEF, 10), (7, 7)):
+        A.asd_philox(seed, rounds, dev_in.data_ptr(), dev_out.data_ptr(), n, 0)
+        torch.cuda.synchronize()
+        got = dev_out.cpu().numpy().view(np.uint32)
+        ref = oracle.philox(ctr, seed, rounds=rounds)
+        np.testing.assert_array_equal(got, ref)
+    say("philox ok")
+
+
+@pytest.mark.parametrize("name,w", [
+    ("c2_full", W.c2_granular_slab()),
+    ("c3_full", W.c3_l10_window()),
+    ("c5_crop", c5_crop()),
+])
+def test_grain_labels_bit_exact(name, w):
+    say("labels", name)
+    h = bridge.make_handle(w, A.ASD_FP32)
+    np.testing.assert_array_equal(h.labels(), oracle_labels(w))
+
+
+@pytest.mark.parametrize("name,w", [("c1", W.c1_plain_sc()), ("c3_crop", c3_crop()),
+                                    ("c5_crop", c5_crop()), ("c2_crop", c2_crop())])
+def test_neighbour_tables_bit_exact(name, w):
+    say("neighbours", name)
+    h = bridge.make_handle(w, A.ASD_FP64)
+    row, col, sh = h.neighbours()
+    nx = w.track_nx or w.nx
+    per = [int(b == W.BC_PERIODIC) for b in w.bc]
+    r2, c2, s2 = oracle.neighbours(w.kind, nx, w.ny, w.nz, per, w.a, w.c, w.shell_radii)
+    np.testing.assert_array_equal(row, r2)
+    np.testing.assert_array_equal(col, c2)
+    np.testing.assert_array_equal(sh, s2)
+
+
+# ---------------------------------------------------------------- trajectories
+CASES = [
+    ("c1_full", W.c1_plain_sc(), (), False),
+    ("c2_crop", c2_crop(), (), False),
+    ("c2_crop_plusB", c2_crop(B=(0.0, 0.0, 0.8), seed=12), (), False),
+    ("c3_crop", c3_crop(), (), False),
+    ("c5_crop_shift", c5_crop(), ((40, 2), (70, 1)), True),
+]
+
+
+@pytest.mark.parametrize("precision", [A.ASD_FP64, A.ASD_FP32])
+@pytest.mark.parametrize("name,w,shifts,ku_spread", CASES)
+def test_trajectory_parity(name, w, shifts, ku_spread, precision):
+    steps = 100
+    say("trajectory", name, "fp64" if precision == A.ASD_FP64 else "fp32")
+    ku = None
+    if ku_spread:
+        ng = int(oracle_labels(w).max()) + 1
+        ku = W.grain_ku(ng, w.ku, w.ku_spread, w.seed)
+    h, lab, S0 = run_gpu(w, precision, steps, ku=ku, shifts=shifts)
+    Sg = h.get_spins()
+    _, So = run_oracle(w, lab, S0, steps, ku=ku, shifts=shifts)
+    err = maxdiff(Sg, So)
+    say(f"  max |dS| = {err:.3e}")
+    assert err <= TOL[precision], err
+    mag = lab >= 0
+    assert np.all(Sg[:, ~mag] == 0)
+    assert np.max(np.abs(np.sqrt((Sg[:, mag].astype(np.float64) ** 2).sum(0)) - 1)) < (
+        1e-15 if precision == A.ASD_FP64 else 1e-6)
+
+
+@pytest.mark.parametrize("precision", [A.ASD_FP64, A.ASD_FP32])
+def test_reductions_match_oracle(precision):
+    w = c5_crop()
+    shifts = ((30, 3),)
+    say("reductions", precision)
+    ng = int(oracle_labels(w).max()) + 1
+    ku = W.grain_ku(ng, w.ku, w.ku_spread, w.seed)
+    h, lab, S0 = run_gpu(w, precision, 50, ku=ku, shifts=shifts)
+    Sg = h.get_spins().astype(np.float64)
+    pg, ps = h.magnetization()
+    E = h.energy()[0]
+    # oracle reductions of the GPU's own final spins (isolates the reduction)
+    sysm, _ = run_oracle(w, lab, S0, 0, ku=ku)
+    org = h.state()[1]
+    sysm.set_active(window_mask(w, org), org)
+    opg, ots = sysm.magnetisation(Sg, h.grain_count())
+    oE = sysm.energy(Sg, 50)
+    rel = lambda a, b: np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0))
+    assert rel(pg, opg) < 1e-12
+    assert rel(ps[0], ots) < 1e-12
+    assert np.max(np.abs(E - oE) / np.abs(oE[3])) < 1e-12
+
+
+def test_batched_uneven_systems_match_single_runs():
+    """Uneven isolated grains, each at its own temperature, in one launch: system k
+    equals the oracle run with system id k."""
+    cyl = W.cylinder_batch(n=5, d_range=(2.0e-9, 4.5e-9), h_range=(1.5e-9, 3.0e-9), T0=300.0, dT=150.0)
+    w0 = W.Workload("cyl", bc=(0, 0, 0), B=(0.0, 0.0, 0.0), seed=4, alpha=0.1)
+    ins = []
+    for c in cyl:
+        wc = w0.scaled(nx=c.nx, ny=c.ny, nz=c.nz)
+        ins.append(bridge.SystemInputs(wc, labels=c.labels, T_system=c.T))
+    say("batched", [c.labels.size for c in cyl])
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        h = A.Handle(bridge.params_for(w0, precision), [i.desc for i in ins])
+        dr, _ = bridge.drive_for(w0, T_amb=0.0)
+        h.set_drive(dr)
+        S0s = []
+        for k, c in enumerate(cyl):
+            S0 = initial_state(w0, c.labels)
+            S0s.append(S0)
+            h.set_spins(S0, k)
+        h.step(60)
+        for k, c in enumerate(cyl):
+            wc = w0.scaled(nx=c.nx, ny=c.ny, nz=c.nz)
+            _, So = run_oracle(wc, c.labels, S0s[k], 60, sys_id=k, T_amb=c.T)
+            err = maxdiff(h.get_spins(k), So)
+            assert err <= TOL[precision], (k, err)
+        st = h.moment_stats()
+        assert st.shape == (5, 5)
+
+
+def test_graph_capture_equals_eager_and_resume_is_exact():
+    w = c2_crop()
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        h1, lab, S0 = run_gpu(w, precision, 100)
+        h2, _, _ = run_gpu(w, precision, 100, S0=S0, graph_steps=10)
+        a, b = h1.get_spins(), h2.get_spins()
+        np.testing.assert_array_equal(a, b)
+        # resume: 60 steps, checkpoint, fresh handle, 40 more
+        h3, _, _ = run_gpu(w, precision, 60, S0=S0)
+        mid = h3.get_spins()
+        h4 = bridge.make_handle(w, precision)
+        h4.set_spins(mid)
+        h4.set_step(60)
+        h4.step(40)
+        np.testing.assert_array_equal(h4.get_spins(), a)
+        # run-to-run determinism
+        h5, _, _ = run_gpu(w, precision, 100, S0=S0)
+        np.testing.assert_array_equal(h5.get_spins(), a)
+    say("graph/resume/determinism ok")
+
+
+def test_full_size_c2_few_steps_against_oracle():
+    """The full 200x200x33 granular slab: 3 steps against the oracle at every site,
+    then 200 more steps with invariants only."""
+    w = W.c2_granular_slab()
+    for precision in (A.ASD_FP32, A.ASD_FP64):
+        say("full c2", precision)
+        h, lab, S0 = run_gpu(w, precision, 3)
+        _, So = run_oracle(w, lab, S0, 3)
+        err = maxdiff(h.get_spins(), So)
+        assert err <= TOL[precision], err
+        h.step(200)
+        S = h.get_spins().astype(np.float64)
+        mag = lab >= 0
+        assert np.all(S[:, ~mag] == 0)
+        assert np.max(np.abs(np.sqrt((S[:, mag] ** 2).sum(0)) - 1)) < 1e-6
+        _, ps = h.magnetization()
+        assert ps[0, 3] == mag.sum()
