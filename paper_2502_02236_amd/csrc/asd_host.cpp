@@ -14,6 +14,7 @@
 
 #include "asd.h"
 #include "asd_internal.h"
+#include "asd_variants.h"
 
 using namespace asd;
 
@@ -82,6 +83,7 @@ struct asd_t {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_steps = 0;
     int graph_kernel = -1, graph_tile = -1;
+    int n_ftiles = 0;         // fused tiles of the current variant
 };
 
 static thread_local std::string g_err;
@@ -352,7 +354,7 @@ static void fused_tiles_of(const asd_params *p, const asd_system_desc *d, int ti
                            int *ty)
 {
     int bx, by;
-    fused_tile_shape(p->lattice, tile_cfg, &bx, &by);
+    fused_tile_interior(p->precision == ASD_FP64, tile_cfg, &bx, &by);
     *tx = (d->nx + bx - 1) / bx;
     *ty = (d->ny + by - 1) / by;
 }
@@ -372,7 +374,7 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         tiles += (int32_t)((nw + kPlainTile - 1) / kPlainTile);
         int fx = 0, fy = 0;
         int maxf = 0;
-        for (int v = 0; v < fused_tile_variants(p->lattice); ++v) {
+        for (int v = 0; v < fused_variant_count(p->precision == ASD_FP64); ++v) {
             fused_tiles_of(p, d, v, &fx, &fy);
             maxf = std::max(maxf, fx * fy);
         }
@@ -468,6 +470,8 @@ static void drop_graphs(asd_t *h)
         }
 }
 
+static const char *fused_unsupported(const asd_t *h);
+
 int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, void *workspace,
                size_t workspace_bytes, void *stream, asd_t **out)
 {
@@ -486,7 +490,7 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
     h->ws = (char *)workspace;
     h->stream = (hipStream_t)stream;
     h->elem = p->precision == ASD_FP64 ? 8 : 4;
-    h->kernel = p->kernel == ASD_KERNEL_FUSED ? ASD_KERNEL_FUSED : ASD_KERNEL_PLAIN;
+    h->kernel = ASD_KERNEL_PLAIN;
     h->graph_steps = p->graph_steps;
     h->sys.resize(n_sys);
     h->L = make_layout(p, sys, n_sys);
@@ -610,6 +614,21 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
         return r2;
     }
     HIP_OK(h, hipStreamSynchronize(st));
+    // AUTO: fused where it applies; FUSED: required
+    if (p->kernel != ASD_KERNEL_PLAIN) {
+        const char *why = fused_unsupported(h);
+        if (!why) {
+            int r3 = asd_set_variant(h, ASD_KERNEL_FUSED, 0);
+            if (r3) {
+                delete h;
+                return r3;
+            }
+        } else if (p->kernel == ASD_KERNEL_FUSED) {
+            fail(nullptr, ASD_EUNSUPPORTED, "%s", why);
+            delete h;
+            return ASD_EUNSUPPORTED;
+        }
+    }
     *out = h;
     return ASD_OK;
 }
@@ -748,7 +767,7 @@ static int launch_one(asd_t *h, int cur, int step_off)
 {
     int rc;
     const bool fused = h->kernel == ASD_KERNEL_FUSED;
-    const int blocks = fused ? h->L.n_ftiles : h->L.n_tiles;
+    const int blocks = fused ? h->n_ftiles : h->L.n_tiles;
     if (h->p.precision == ASD_FP64) {
         StepArgs<double> a = make_args<double>(h, cur, step_off);
         rc = fused ? launch_fused_step_f64(a, blocks, h->stream) : launch_plain_step_f64(a, blocks, h->stream);
@@ -1036,13 +1055,47 @@ int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out
     return ASD_OK;
 }
 
+// reason the fused kernel cannot serve this handle, or NULL
+static const char *fused_unsupported(const asd_t *h)
+{
+    if (h->p.lattice != ASD_SC) return "the fused kernel covers the SC lattice only";
+    for (const HostSys &hs : h->sys)
+        if (hs.desc.bc_z != ASD_BC_OPEN) return "the fused kernel marches z between open surfaces";
+    return nullptr;
+}
+
+// fill the fused tile map for variant v and upload it with the descriptors
+static int setup_fused_tiles(asd_t *h, int v)
+{
+    std::vector<int32_t> map;
+    for (size_t s = 0; s < h->sys.size(); ++s) {
+        int fx, fy;
+        fused_tiles_of(&h->p, &h->sys[s].desc, v, &fx, &fy);
+        SysDev &d = h->dev[s];
+        d.ftile_base = (int32_t)map.size();
+        d.ftiles_x = fx;
+        d.ftiles_y = fy;
+        for (int t = 0; t < fx * fy; ++t) map.push_back((int32_t)s);
+    }
+    h->n_ftiles = (int)map.size();
+    HIP_OK(h, hipMemcpyAsync(h->ws + h->L.off_ftile, map.data(), map.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, h->stream));
+    return upload_sysdev(h);
+}
+
 int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile)
 {
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
     if (kernel != ASD_KERNEL_PLAIN && kernel != ASD_KERNEL_FUSED)
         return fail(h, ASD_EINVAL, "kernel must be PLAIN or FUSED");
-    if (tile < 0 || tile >= fused_tile_variants(h->p.lattice))
+    if (tile < 0 || tile >= fused_variant_count(h->p.precision == ASD_FP64))
         return fail(h, ASD_EINVAL, "tile variant out of range");
+    if (kernel == ASD_KERNEL_FUSED) {
+        const char *why = fused_unsupported(h);
+        if (why) return fail(h, ASD_EUNSUPPORTED, "%s", why);
+        int rc = setup_fused_tiles(h, tile);
+        if (rc) return rc;
+    }
     h->kernel = kernel;
     h->tile_cfg = tile;
     drop_graphs(h);
@@ -1057,10 +1110,144 @@ int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile)
     return ASD_OK;
 }
 
-int asd_autotune(asd_t *h, const char *cache_path)
+// ------------------------------------------------------------------ autotuning
+static std::string tune_key(const asd_t *h)
 {
-    (void)cache_path;
-    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
-    return fail(h, ASD_EUNSUPPORTED, "autotune not built yet");
+    char buf[256];
+    int64_t sites = 0;
+    for (const HostSys &hs : h->sys) sites += hs.n_window;
+    const asd_system_desc &d = h->sys[0].desc;
+    snprintf(buf, sizeof buf, "lat%d_prec%d_%dx%dx%d_n%zu_w%lld", h->p.lattice, h->p.precision, d.nx,
+             d.ny, d.nz, h->sys.size(), (long long)sites);
+    return buf;
 }
 
+static bool tune_cache_lookup(const char *path, const std::string &key, int *kernel, int *tile)
+{
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    fclose(f);
+    const std::string pat = "\"" + key + "\": {\"kernel\": ";
+    size_t p = text.find(pat);
+    if (p == std::string::npos) return false;
+    return sscanf(text.c_str() + p + pat.size(), "%d, \"tile\": %d", kernel, tile) == 2;
+}
+
+static void tune_cache_store(const char *path, const std::string &key, int kernel, int tile,
+                             double ms)
+{
+    if (!path) return;
+    std::string text;
+    if (FILE *f = fopen(path, "r")) {
+        char buf[4096];
+        size_t n;
+        while ((n = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+        fclose(f);
+    }
+    // one entry per line between braces: {"key": {...},\n ...}
+    std::vector<std::string> lines;
+    size_t a = 0;
+    while (a < text.size()) {
+        size_t b = text.find('\n', a);
+        if (b == std::string::npos) b = text.size();
+        std::string ln = text.substr(a, b - a);
+        if (ln.find("\"kernel\"") != std::string::npos && ln.find("\"" + key + "\"") == std::string::npos) {
+            while (!ln.empty() && (ln.back() == ',' || ln.back() == ' ')) ln.pop_back();
+            size_t q = ln.find('"');
+            lines.push_back(ln.substr(q));
+        }
+        a = b + 1;
+    }
+    char e[512];
+    snprintf(e, sizeof e, "\"%s\": {\"kernel\": %d, \"tile\": %d, \"ms_per_step\": %.6f}", key.c_str(),
+             kernel, tile, ms);
+    lines.push_back(e);
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fputs("{\n", f);
+    for (size_t i = 0; i < lines.size(); ++i) fprintf(f, "  %s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    fputs("}\n", f);
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+// time `steps` eager steps of the current variant (ms per step)
+static int time_variant(asd_t *h, int steps, double *ms)
+{
+    hipEvent_t e0, e1;
+    HIP_OK(h, hipEventCreate(&e0));
+    HIP_OK(h, hipEventCreate(&e1));
+    int rc = asd_step(h, 2);  // warm-up
+    if (!rc) {
+        (void)hipEventRecord(e0, h->stream);
+        rc = asd_step(h, steps);
+        (void)hipEventRecord(e1, h->stream);
+    }
+    float t = 0.f;
+    if (!rc) {
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&t, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / steps;
+    return rc;
+}
+
+int asd_autotune(asd_t *h, const char *cache_path)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    const std::string key = tune_key(h);
+    int kern = 0, tile = 0;
+    if (tune_cache_lookup(cache_path, key, &kern, &tile) &&
+        (kern == ASD_KERNEL_PLAIN || kern == ASD_KERNEL_FUSED))
+        return asd_set_variant(h, kern, tile);
+    // save spins and counters; every trial runs from the same state
+    const size_t nb = (size_t)3 * h->L.ncs * h->elem;
+    std::vector<char> saved(nb);
+    HIP_OK(h, hipMemcpyAsync(saved.data(), h->ws + h->L.off_S[h->cur], nb, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    const int64_t step0 = h->step;
+    const int cur0 = h->cur;
+    const int gsteps = h->graph_steps;
+    h->graph_steps = 0;
+    struct Cand {
+        int kernel, tile;
+    };
+    std::vector<Cand> cands{{ASD_KERNEL_PLAIN, 0}};
+    if (!fused_unsupported(h))
+        for (int v = 0; v < fused_variant_count(h->p.precision == ASD_FP64); ++v)
+            cands.push_back({ASD_KERNEL_FUSED, v});
+    double best = 1e30;
+    Cand pick = cands[0];
+    int rc = ASD_OK;
+    for (const Cand &c : cands) {
+        if ((rc = asd_set_variant(h, c.kernel, c.tile))) break;
+        double ms = 0;
+        if ((rc = time_variant(h, 20, &ms))) break;
+        if (ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    h->graph_steps = gsteps;
+    // restore the state into both ping-pong buffers and the step counter
+    h->cur = cur0;
+    for (int b = 0; b < 2; ++b)
+        HIP_OK(h, hipMemcpyAsync(h->ws + h->L.off_S[b], saved.data(), nb, hipMemcpyHostToDevice,
+                                 h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    int r2 = asd_set_step(h, step0);
+    if (rc) return rc;
+    if (r2) return r2;
+    if ((rc = asd_set_variant(h, pick.kernel, pick.tile))) return rc;
+    tune_cache_store(cache_path, key, pick.kernel, pick.tile, best);
+    return ASD_OK;
+}

@@ -73,9 +73,6 @@ int launch_plain_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)
 int launch_plain_step_f32(const StepArgs<float> &a, int n_blocks, void *stream);
 int launch_fused_step_f64(const StepArgs<double> &a, int n_blocks, void *stream);
 int launch_fused_step_f32(const StepArgs<float> &a, int n_blocks, void *stream);
-// fused tile geometry for a tile variant: interior tile (tx, ty) in cells
-void fused_tile_shape(int kind, int tile_cfg, int *tx, int *ty);
-int fused_tile_variants(int kind);
 
 // misc kernels (asd_misc.hip)
 int launch_philox_export(uint64_t seed, int rounds, const uint32_t *ctr, uint32_t *out, int64_t n,

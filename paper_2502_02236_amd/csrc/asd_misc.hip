@@ -229,18 +229,4 @@ int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, do
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-void fused_tile_shape(int kind, int tile_cfg, int *tx, int *ty)
-{
-    (void)kind;
-    (void)tile_cfg;
-    *tx = 62;
-    *ty = 14;
-}
-
-int fused_tile_variants(int kind)
-{
-    (void)kind;
-    return 1;
-}
-
 }  // namespace asd

@@ -62,8 +62,11 @@ def initial_state(w, labels):
 
 
 def run_gpu(w, precision, steps, kernel=A.ASD_KERNEL_PLAIN, S0=None, ku=None, shifts=(),
-            graph_steps=0):
-    h = bridge.make_handle(w, precision, kernel=kernel, ku_grain=ku, graph_steps=graph_steps)
+            graph_steps=0, tile=0):
+    h = bridge.make_handle(w, precision, kernel=A.ASD_KERNEL_PLAIN, ku_grain=ku,
+                           graph_steps=graph_steps)
+    if kernel == A.ASD_KERNEL_FUSED:
+        h.set_variant(A.ASD_KERNEL_FUSED, tile)
     lab = h.labels()
     if S0 is None:
         S0 = initial_state(w, lab)
@@ -151,20 +154,24 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("kernel", [A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED])
 @pytest.mark.parametrize("precision", [A.ASD_FP64, A.ASD_FP32])
 @pytest.mark.parametrize("name,w,shifts,ku_spread", CASES)
-def test_trajectory_parity(name, w, shifts, ku_spread, precision):
+def test_trajectory_parity(name, w, shifts, ku_spread, precision, kernel):
     steps = 100
-    say("trajectory", name, "fp64" if precision == A.ASD_FP64 else "fp32")
+    if kernel == A.ASD_KERNEL_FUSED and w.kind != W.SC:
+        pytest.skip("the fused kernel covers the SC lattice")
+    say("trajectory", name, "fp64" if precision == A.ASD_FP64 else "fp32",
+        "fused" if kernel == A.ASD_KERNEL_FUSED else "plain")
     ku = None
     if ku_spread:
         ng = int(oracle_labels(w).max()) + 1
         ku = W.grain_ku(ng, w.ku, w.ku_spread, w.seed)
-    h, lab, S0 = run_gpu(w, precision, steps, ku=ku, shifts=shifts)
+    h, lab, S0 = run_gpu(w, precision, steps, kernel=kernel, ku=ku, shifts=shifts)
     Sg = h.get_spins()
     _, So = run_oracle(w, lab, S0, steps, ku=ku, shifts=shifts)
     err = maxdiff(Sg, So)
-    say(f"  max |dS| = {err:.3e}")
+    say(f"  max |dS| = {err:.3e}  bit-identical: {bool(np.array_equal(Sg.astype(np.float64), So))}")
     assert err <= TOL[precision], err
     mag = lab >= 0
     assert np.all(Sg[:, ~mag] == 0)
@@ -224,34 +231,38 @@ def test_batched_uneven_systems_match_single_runs():
         assert st.shape == (5, 5)
 
 
-def test_graph_capture_equals_eager_and_resume_is_exact():
+@pytest.mark.parametrize("kernel", [A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED])
+def test_graph_capture_equals_eager_and_resume_is_exact(kernel):
     w = c2_crop()
     for precision in (A.ASD_FP64, A.ASD_FP32):
-        h1, lab, S0 = run_gpu(w, precision, 100)
-        h2, _, _ = run_gpu(w, precision, 100, S0=S0, graph_steps=10)
+        h1, lab, S0 = run_gpu(w, precision, 100, kernel=kernel)
+        h2, _, _ = run_gpu(w, precision, 100, S0=S0, graph_steps=10, kernel=kernel)
         a, b = h1.get_spins(), h2.get_spins()
         np.testing.assert_array_equal(a, b)
         # resume: 60 steps, checkpoint, fresh handle, 40 more
-        h3, _, _ = run_gpu(w, precision, 60, S0=S0)
+        h3, _, _ = run_gpu(w, precision, 60, S0=S0, kernel=kernel)
         mid = h3.get_spins()
         h4 = bridge.make_handle(w, precision)
+        if kernel == A.ASD_KERNEL_FUSED:
+            h4.set_variant(kernel, 0)
         h4.set_spins(mid)
         h4.set_step(60)
         h4.step(40)
         np.testing.assert_array_equal(h4.get_spins(), a)
         # run-to-run determinism
-        h5, _, _ = run_gpu(w, precision, 100, S0=S0)
+        h5, _, _ = run_gpu(w, precision, 100, S0=S0, kernel=kernel)
         np.testing.assert_array_equal(h5.get_spins(), a)
     say("graph/resume/determinism ok")
 
 
-def test_full_size_c2_few_steps_against_oracle():
+@pytest.mark.parametrize("kernel", [A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED])
+def test_full_size_c2_few_steps_against_oracle(kernel):
     """The full 200x200x33 granular slab: 3 steps against the oracle at every site,
-    then 200 more steps with invariants only."""
+    then 200 more steps with invariants only (the benchmark's configuration)."""
     w = W.c2_granular_slab()
     for precision in (A.ASD_FP32, A.ASD_FP64):
-        say("full c2", precision)
-        h, lab, S0 = run_gpu(w, precision, 3)
+        say("full c2", precision, kernel)
+        h, lab, S0 = run_gpu(w, precision, 3, kernel=kernel)
         _, So = run_oracle(w, lab, S0, 3)
         err = maxdiff(h.get_spins(), So)
         assert err <= TOL[precision], err
@@ -262,3 +273,45 @@ def test_full_size_c2_few_steps_against_oracle():
         assert np.max(np.abs(np.sqrt((S[:, mag] ** 2).sum(0)) - 1)) < 1e-6
         _, ps = h.magnetization()
         assert ps[0, 3] == mag.sum()
+
+
+@pytest.mark.parametrize("name,w,shifts", [("c2_crop", c2_crop(), ()),
+                                           ("c5_crop", c5_crop(ku_spread=0.0), ((40, 2),)),
+                                           ("c1", W.c1_plain_sc(), ())])
+def test_fp64_identical_across_kernels_and_tiles(name, w, shifts):
+    """FP64 spins after 100 steps are bit-identical for the two-pass kernel and every
+    tile variant of the fused kernel (also a check for LDS races)."""
+    say("tile invariance", name)
+    ref, lab, S0 = run_gpu(w, A.ASD_FP64, 100, shifts=shifts)
+    a = ref.get_spins()
+    for tile in range(3):
+        h, _, _ = run_gpu(w, A.ASD_FP64, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
+                          shifts=shifts)
+        np.testing.assert_array_equal(h.get_spins(), a)
+    for tile in range(4):
+        h, _, _ = run_gpu(w, A.ASD_FP32, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
+                          shifts=shifts)
+        assert maxdiff(h.get_spins(), a) <= TOL[A.ASD_FP32]
+
+
+def test_autotune_picks_a_variant_and_restores_state(tmp_path):
+    w = c2_crop()
+    cache = str(tmp_path / "tune.json")
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        ref, lab, S0 = run_gpu(w, precision, 30)
+        h = bridge.make_handle(w, precision, kernel=A.ASD_KERNEL_AUTO)
+        h.set_spins(S0)
+        h.step(10)
+        h.autotune(cache)
+        kern, tile = h.variant()
+        assert kern in (A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED)
+        assert h.state()[0] == 10
+        h.step(20)
+        err = maxdiff(h.get_spins(), ref.get_spins())
+        assert err <= (0.0 if precision == A.ASD_FP64 else TOL[A.ASD_FP32]), err
+        # a second handle reads the cached choice
+        h2 = bridge.make_handle(w, precision)
+        h2.autotune(cache)
+        assert h2.variant() == (kern, tile)
+    text = open(cache).read()
+    assert text.count('"kernel"') == 2
