@@ -29,27 +29,66 @@ struct Words4 {
     uint32_t w0, w1, w2, w3;
 };
 
+__device__ __forceinline__ void philox_round(uint32_t k0, uint32_t k1, uint32_t &c0, uint32_t &c1,
+                                             uint32_t &c2, uint32_t &c3)
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    uint64_t p0 = (uint64_t)M0 * c0;
+    uint64_t p1 = (uint64_t)M1 * c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+}
+
+// rounds is 7 or 10 (or 1..10 for the raw export); the key schedule is
+// uniform across the wavefront, so the bumps stay on the scalar unit
 __device__ __forceinline__ Words4 philox4x32(int rounds, uint32_t k0, uint32_t k1, uint32_t c0,
                                              uint32_t c1, uint32_t c2, uint32_t c3)
 {
-    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
     const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    if (rounds == 10) {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r < rounds) {
-            uint64_t p0 = (uint64_t)M0 * c0;
-            uint64_t p1 = (uint64_t)M1 * c2;
-            uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-            uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-            c1 = (uint32_t)p1;
-            c3 = (uint32_t)p0;
-            c0 = n0;
-            c2 = n2;
-            k0 += W0;
-            k1 += W1;
-        }
+        for (int r = 0; r < 10; ++r) philox_round(k0 + r * W0, k1 + r * W1, c0, c1, c2, c3);
+    } else if (rounds == 7) {
+#pragma unroll
+        for (int r = 0; r < 7; ++r) philox_round(k0 + r * W0, k1 + r * W1, c0, c1, c2, c3);
+    } else {
+        for (int r = 0; r < rounds; ++r) philox_round(k0 + r * W0, k1 + r * W1, c0, c1, c2, c3);
     }
     return Words4{c0, c1, c2, c3};
+}
+
+// Division by a run-time divisor d >= 1 for 32-bit unsigned dividends with a
+// precomputed multiplier (Granlund and Montgomery, PLDI 1994, Fig. 4.1):
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+// q = (t + ((n - t) >> 1)) >> (l - 1), t = mulhi(m, n); d = 1 handled by l = 0.
+struct FastDiv {
+    uint32_t d, m, l;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+    f.l = l;
+    f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+    return f;
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, FastDiv f)
+{
+    if (f.l == 0) return n;
+#ifdef __HIP_DEVICE_COMPILE__
+    uint32_t t = __umulhi(f.m, n);
+#else
+    uint32_t t = (uint32_t)(((uint64_t)f.m * n) >> 32);
+#endif
+    return (t + ((n - t) >> 1)) >> (f.l - 1);
 }
 
 // ---------------------------------------------------------------- FP64

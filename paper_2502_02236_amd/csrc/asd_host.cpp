@@ -55,6 +55,7 @@ struct Layout {
     int32_t n_tiles = 0;   // plain tiles
     int32_t n_ftiles = 0;  // fused tiles
     size_t off_S[3] = {0, 0, 0};
+    size_t off_F0 = 0, off_Bt = 0;  // stash buffers of the two-pass variant 1
     size_t off_label = 0, off_ell = 0, off_sys = 0, off_tile = 0, off_ftile = 0, off_can = 0,
            off_ku = 0, off_gsys = 0, off_gptr = 0, off_gsites = 0, off_step = 0, off_origin = 0,
            off_bits = 0, off_gout = 0, off_sout = 0, off_mom = 0, off_epart = 0, off_eout = 0;
@@ -351,12 +352,27 @@ static int grain_count_of(const asd_params *p, const asd_system_desc *d)
 }
 
 static void fused_tiles_of(const asd_params *p, const asd_system_desc *d, int tile_cfg, int *tx,
-                           int *ty)
+                           int *ty, int *tz = nullptr, int *lz = nullptr)
 {
     int bx, by;
     fused_tile_interior(p->precision == ASD_FP64, tile_cfg, &bx, &by);
     *tx = (d->nx + bx - 1) / bx;
     *ty = (d->ny + by - 1) / by;
+    const FusedVariant f = fused_variant(p->precision == ASD_FP64, tile_cfg);
+    const int len = f.lz > 0 ? std::min(f.lz, d->nz) : d->nz;
+    if (lz) *lz = len;
+    if (tz) *tz = (d->nz + len - 1) / len;
+}
+
+static FastDivH host_fastdiv(uint32_t d)
+{
+    FastDivH f;
+    f.d = d;
+    uint32_t l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+    f.l = l;
+    f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+    return f;
 }
 
 static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n_sys)
@@ -372,11 +388,11 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         g += grain_count_of(p, d);
         int64_t nw = (int64_t)per * d->nx * d->ny * d->nz;
         tiles += (int32_t)((nw + kPlainTile - 1) / kPlainTile);
-        int fx = 0, fy = 0;
+        int fx = 0, fy = 0, fz = 0;
         int maxf = 0;
         for (int v = 0; v < fused_variant_count(p->precision == ASD_FP64); ++v) {
-            fused_tiles_of(p, d, v, &fx, &fy);
-            maxf = std::max(maxf, fx * fy);
+            fused_tiles_of(p, d, v, &fx, &fy, &fz);
+            maxf = std::max(maxf, fx * fy * fz);
         }
         ftiles += maxf;
     }
@@ -394,6 +410,8 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         return o;
     };
     for (int b = 0; b < 3; ++b) L.off_S[b] = take(3 * (size_t)L.ncs * elem);
+    L.off_F0 = take(3 * (size_t)L.ncs * elem);
+    L.off_Bt = take(3 * (size_t)L.ncs * elem);
     L.off_label = take((size_t)L.ncs * sizeof(uint16_t));
     L.off_ell = p->lattice == ASD_L10 ? take((size_t)kL10Degree * L.ncs * sizeof(int32_t)) : 0;
     L.off_sys = take((size_t)n_sys * sizeof(SysDev));
@@ -528,6 +546,8 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
         d.n_tiles = (int32_t)((hs.n_window + kPlainTile - 1) / kPlainTile);
         for (int t = 0; t < d.n_tiles; ++t) tile_sys.push_back(s);
         d.sys_id = (uint32_t)s;
+        d.fd_nx = host_fastdiv((uint32_t)d.nx);
+        d.fd_ny = host_fastdiv((uint32_t)d.ny);
         d.base = base;
         d.n_stored = hs.n_stored;
         d.n_window = hs.n_window;
@@ -747,6 +767,8 @@ static StepArgs<T> make_args(const asd_t *h, int cur, int step_off)
     a.S = (const T *)(w + L.off_S[cur]);
     a.So = (T *)(w + L.off_S[1 - cur]);
     a.Sp = (T *)(w + L.off_S[2]);
+    a.F0 = (T *)(w + L.off_F0);
+    a.Bt = (T *)(w + L.off_Bt);
     a.ncs = L.ncs;
     a.sys = (const SysDev *)(w + L.off_sys);
     a.tile_sys = (const int32_t *)(w + (h->kernel == ASD_KERNEL_FUSED ? L.off_ftile : L.off_tile));
@@ -1069,13 +1091,17 @@ static int setup_fused_tiles(asd_t *h, int v)
 {
     std::vector<int32_t> map;
     for (size_t s = 0; s < h->sys.size(); ++s) {
-        int fx, fy;
-        fused_tiles_of(&h->p, &h->sys[s].desc, v, &fx, &fy);
+        int fx, fy, fz, lz;
+        fused_tiles_of(&h->p, &h->sys[s].desc, v, &fx, &fy, &fz, &lz);
         SysDev &d = h->dev[s];
         d.ftile_base = (int32_t)map.size();
         d.ftiles_x = fx;
         d.ftiles_y = fy;
-        for (int t = 0; t < fx * fy; ++t) map.push_back((int32_t)s);
+        d.ftiles_z = fz;
+        d.fz_len = lz;
+        d.fd_ftx = host_fastdiv((uint32_t)fx);
+        d.fd_fty = host_fastdiv((uint32_t)fy);
+        for (int t = 0; t < fx * fy * fz; ++t) map.push_back((int32_t)s);
     }
     h->n_ftiles = (int)map.size();
     HIP_OK(h, hipMemcpyAsync(h->ws + h->L.off_ftile, map.data(), map.size() * sizeof(int32_t),
@@ -1088,8 +1114,9 @@ int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile)
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
     if (kernel != ASD_KERNEL_PLAIN && kernel != ASD_KERNEL_FUSED)
         return fail(h, ASD_EINVAL, "kernel must be PLAIN or FUSED");
-    if (tile < 0 || tile >= fused_variant_count(h->p.precision == ASD_FP64))
-        return fail(h, ASD_EINVAL, "tile variant out of range");
+    const int nvar = kernel == ASD_KERNEL_PLAIN ? kPlainVariants
+                                                : fused_variant_count(h->p.precision == ASD_FP64);
+    if (tile < 0 || tile >= nvar) return fail(h, ASD_EINVAL, "variant out of range");
     if (kernel == ASD_KERNEL_FUSED) {
         const char *why = fused_unsupported(h);
         if (why) return fail(h, ASD_EUNSUPPORTED, "%s", why);
@@ -1221,7 +1248,8 @@ int asd_autotune(asd_t *h, const char *cache_path)
     struct Cand {
         int kernel, tile;
     };
-    std::vector<Cand> cands{{ASD_KERNEL_PLAIN, 0}};
+    std::vector<Cand> cands;
+    for (int v = 0; v < kPlainVariants; ++v) cands.push_back({ASD_KERNEL_PLAIN, v});
     if (!fused_unsupported(h))
         for (int v = 0; v < fused_variant_count(h->p.precision == ASD_FP64); ++v)
             cands.push_back({ASD_KERNEL_FUSED, v});

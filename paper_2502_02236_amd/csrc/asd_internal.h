@@ -6,6 +6,10 @@
 
 namespace asd {
 
+struct FastDivH {            // mirror of the device FastDiv (d, multiplier, shift)
+    uint32_t d, m, l;
+};
+
 constexpr int kPlainTile = 256;      // window sites per block in the two-pass kernels
 constexpr uint16_t kNoGrain = 0xFFFF; // label of a non-magnetic site
 constexpr int kL10Degree = 18;        // ELL slots of the 4-shell L1_0 table
@@ -22,9 +26,11 @@ struct SysDev {
     int32_t tile_base;        // first tile of this system (plain kernels)
     int32_t n_tiles;
     int32_t ftile_base;       // first tile of this system (fused kernel)
-    int32_t ftiles_x, ftiles_y;
+    int32_t ftiles_x, ftiles_y, ftiles_z;
+    int32_t fz_len;           // z planes per fused tile
     uint32_t sys_id;          // Philox counter word 2
-    int32_t pad0;
+    FastDivH fd_nx, fd_ny;    // division by nx, ny (window)
+    FastDivH fd_ftx, fd_fty;  // division by ftiles_x, ftiles_y
     int64_t base;             // first stored site in the global arrays
     int64_t n_stored;
     int64_t n_window;         // sites in the window
@@ -53,6 +59,8 @@ struct StepArgs {
     const T *S;               // current spins [3][ncs]
     T *Sp;                    // predicted spins (two-pass) [3][ncs]
     T *So;                    // next spins [3][ncs]
+    T *F0;                    // stash: f at the start of the step [3][ncs]
+    T *Bt;                    // stash: thermal field [3][ncs]
     int64_t ncs;              // component stride
     const SysDev *sys;
     const int32_t *tile_sys;  // block -> system
@@ -64,7 +72,8 @@ struct StepArgs {
     const uint8_t *bits;      // polarity bits
     int64_t zero_site;        // an always-zero slot
     int32_t step_off;         // step = *step_base + step_off
-    int32_t tile_cfg;         // fused kernel tile variant
+    int32_t tile_cfg;         // tile variant
+    int32_t n_blocks;         // blocks of the launch (XCD-contiguous tile order)
     StepConsts c;
 };
 

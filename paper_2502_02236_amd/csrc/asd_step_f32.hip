@@ -7,10 +7,7 @@ namespace asd {
 
 int launch_plain_step_f32(const StepArgs<float> &a, int n_blocks, void *stream)
 {
-    hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_plain_predictor<float>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
-    hipLaunchKernelGGL(k_plain_corrector<float>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    return launch_plain<float>(a, n_blocks, stream);
 }
 
 int launch_fused_step_f32(const StepArgs<float> &a, int n_blocks, void *stream)

@@ -8,10 +8,7 @@ namespace asd {
 
 int launch_plain_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)
 {
-    hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_plain_predictor<double>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
-    hipLaunchKernelGGL(k_plain_corrector<double>, dim3(n_blocks), dim3(kPlainTile), 0, st, a);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    return launch_plain<double>(a, n_blocks, stream);
 }
 
 int launch_fused_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)

@@ -1,28 +1,38 @@
-// asd_variants.h -- tile variants of the fused SC kernel (host and device).
+// asd_variants.h -- kernel variants (host and device).
 #pragma once
 
 namespace asd {
 
-// fused kernel variant v: WAVES wavefronts of 64 lanes, R rows per wave;
-// extended tile 64 x (WAVES R), interior 62 x (WAVES R - 2)
-inline int fused_variant_count(bool fp64) { return fp64 ? 3 : 4; }
+// Two-pass kernel variants: 0 recomputes f(S) and the thermal field in the
+// corrector; 1 stashes them from the predictor.
+constexpr int kPlainVariants = 2;
 
-inline void fused_variant_geom(bool fp64, int v, int *waves, int *rows)
+// Fused SC kernel variant: TXE lanes across x (64, 32 or 16), WAVES
+// wavefronts, R column slots per lane, z planes per tile LZ (0: all).
+// Extended tile TXE x TYE with TYE = WAVES R 64 / TXE; interior
+// (TXE - 2) x (TYE - 2) x LZ.
+struct FusedVariant {
+    int txe, waves, rows, lz;
+};
+
+inline int fused_variant_count(bool fp64) { return fp64 ? 4 : 8; }
+
+inline FusedVariant fused_variant(bool fp64, int v)
 {
-    static const int f32w[4] = {8, 4, 8, 4}, f32r[4] = {4, 4, 2, 2};
-    static const int f64w[3] = {4, 8, 8}, f64r[3] = {2, 2, 1};
+    static const FusedVariant f32v[8] = {
+        {64, 8, 4, 0}, {64, 4, 2, 0}, {32, 4, 2, 11}, {32, 4, 2, 0},
+        {32, 8, 2, 8}, {16, 4, 2, 11}, {64, 4, 4, 0}, {32, 4, 1, 11}};
+    static const FusedVariant f64v[4] = {{64, 4, 2, 0}, {32, 4, 2, 11}, {32, 4, 1, 0}, {32, 8, 1, 11}};
     const int n = fused_variant_count(fp64);
     if (v < 0 || v >= n) v = 0;
-    *waves = fp64 ? f64w[v] : f32w[v];
-    *rows = fp64 ? f64r[v] : f32r[v];
+    return fp64 ? f64v[v] : f32v[v];
 }
 
 inline void fused_tile_interior(bool fp64, int v, int *tx, int *ty)
 {
-    int w, r;
-    fused_variant_geom(fp64, v, &w, &r);
-    *tx = 62;
-    *ty = w * r - 2;
+    FusedVariant f = fused_variant(fp64, v);
+    *tx = f.txe - 2;
+    *ty = f.waves * f.rows * 64 / f.txe - 2;
 }
 
 }  // namespace asd

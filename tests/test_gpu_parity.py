@@ -65,8 +65,7 @@ def run_gpu(w, precision, steps, kernel=A.ASD_KERNEL_PLAIN, S0=None, ku=None, sh
             graph_steps=0, tile=0):
     h = bridge.make_handle(w, precision, kernel=A.ASD_KERNEL_PLAIN, ku_grain=ku,
                            graph_steps=graph_steps)
-    if kernel == A.ASD_KERNEL_FUSED:
-        h.set_variant(A.ASD_KERNEL_FUSED, tile)
+    h.set_variant(kernel, tile)
     lab = h.labels()
     if S0 is None:
         S0 = initial_state(w, lab)
@@ -149,25 +148,30 @@ CASES = [
     ("c1_full", W.c1_plain_sc(), (), False),
     ("c2_crop", c2_crop(), (), False),
     ("c2_crop_plusB", c2_crop(B=(0.0, 0.0, 0.8), seed=12), (), False),
+    ("c2_crop_tall", c2_crop(nz=25, seed=13), (), False),
     ("c3_crop", c3_crop(), (), False),
     ("c5_crop_shift", c5_crop(), ((40, 2), (70, 1)), True),
 ]
 
 
-@pytest.mark.parametrize("kernel", [A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED])
+VARIANTS = [(A.ASD_KERNEL_PLAIN, 0), (A.ASD_KERNEL_PLAIN, 1), (A.ASD_KERNEL_FUSED, 0),
+            (A.ASD_KERNEL_FUSED, 1), (A.ASD_KERNEL_FUSED, 2)]
+
+
+@pytest.mark.parametrize("kernel,tile", VARIANTS)
 @pytest.mark.parametrize("precision", [A.ASD_FP64, A.ASD_FP32])
 @pytest.mark.parametrize("name,w,shifts,ku_spread", CASES)
-def test_trajectory_parity(name, w, shifts, ku_spread, precision, kernel):
+def test_trajectory_parity(name, w, shifts, ku_spread, precision, kernel, tile):
     steps = 100
     if kernel == A.ASD_KERNEL_FUSED and w.kind != W.SC:
         pytest.skip("the fused kernel covers the SC lattice")
     say("trajectory", name, "fp64" if precision == A.ASD_FP64 else "fp32",
-        "fused" if kernel == A.ASD_KERNEL_FUSED else "plain")
+        "fused" if kernel == A.ASD_KERNEL_FUSED else "plain", tile)
     ku = None
     if ku_spread:
         ng = int(oracle_labels(w).max()) + 1
         ku = W.grain_ku(ng, w.ku, w.ku_spread, w.seed)
-    h, lab, S0 = run_gpu(w, precision, steps, kernel=kernel, ku=ku, shifts=shifts)
+    h, lab, S0 = run_gpu(w, precision, steps, kernel=kernel, tile=tile, ku=ku, shifts=shifts)
     Sg = h.get_spins()
     _, So = run_oracle(w, lab, S0, steps, ku=ku, shifts=shifts)
     err = maxdiff(Sg, So)
@@ -233,36 +237,48 @@ def test_batched_uneven_systems_match_single_runs():
 
 @pytest.mark.parametrize("kernel", [A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED])
 def test_graph_capture_equals_eager_and_resume_is_exact(kernel):
-    w = c2_crop()
+
+    w = c2_crop(nz=25)
     for precision in (A.ASD_FP64, A.ASD_FP32):
-        h1, lab, S0 = run_gpu(w, precision, 100, kernel=kernel)
-        h2, _, _ = run_gpu(w, precision, 100, S0=S0, graph_steps=10, kernel=kernel)
+        # fused: a z-chunked variant; plain: the stash variant
+        tile = 1 if kernel == A.ASD_KERNEL_PLAIN else (1 if precision == A.ASD_FP64 else 2)
+        h1, lab, S0 = run_gpu(w, precision, 100, kernel=kernel, tile=tile)
+        h2, _, _ = run_gpu(w, precision, 100, S0=S0, graph_steps=10, kernel=kernel, tile=tile)
         a, b = h1.get_spins(), h2.get_spins()
         np.testing.assert_array_equal(a, b)
         # resume: 60 steps, checkpoint, fresh handle, 40 more
-        h3, _, _ = run_gpu(w, precision, 60, S0=S0, kernel=kernel)
+        h3, _, _ = run_gpu(w, precision, 60, S0=S0, kernel=kernel, tile=tile)
         mid = h3.get_spins()
         h4 = bridge.make_handle(w, precision)
-        if kernel == A.ASD_KERNEL_FUSED:
-            h4.set_variant(kernel, 0)
+        h4.set_variant(kernel, tile)
         h4.set_spins(mid)
         h4.set_step(60)
         h4.step(40)
         np.testing.assert_array_equal(h4.get_spins(), a)
         # run-to-run determinism
-        h5, _, _ = run_gpu(w, precision, 100, S0=S0, kernel=kernel)
+        h5, _, _ = run_gpu(w, precision, 100, S0=S0, kernel=kernel, tile=tile)
         np.testing.assert_array_equal(h5.get_spins(), a)
     say("graph/resume/determinism ok")
 
 
 @pytest.mark.parametrize("kernel", [A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED])
-def test_full_size_c2_few_steps_against_oracle(kernel):
+def test_full_size_c2_few_steps_against_oracle(kernel, tmp_path):
     """The full 200x200x33 granular slab: 3 steps against the oracle at every site,
     then 200 more steps with invariants only (the benchmark's configuration)."""
     w = W.c2_granular_slab()
     for precision in (A.ASD_FP32, A.ASD_FP64):
         say("full c2", precision, kernel)
-        h, lab, S0 = run_gpu(w, precision, 3, kernel=kernel)
+        if kernel == A.ASD_KERNEL_FUSED:
+            # the variant the benchmark runs: the autotuner's pick among all of them
+            h = bridge.make_handle(w, precision, kernel=A.ASD_KERNEL_AUTO)
+            lab = h.labels()
+            S0 = initial_state(w, lab)
+            h.set_spins(S0)
+            h.autotune(str(tmp_path / "tune.json"))
+            say("  autotuned variant", h.variant())
+            h.step(3)
+        else:
+            h, lab, S0 = run_gpu(w, precision, 3, kernel=kernel)
         _, So = run_oracle(w, lab, S0, 3)
         err = maxdiff(h.get_spins(), So)
         assert err <= TOL[precision], err
@@ -275,7 +291,7 @@ def test_full_size_c2_few_steps_against_oracle(kernel):
         assert ps[0, 3] == mag.sum()
 
 
-@pytest.mark.parametrize("name,w,shifts", [("c2_crop", c2_crop(), ()),
+@pytest.mark.parametrize("name,w,shifts", [("c2_crop", c2_crop(nz=25), ()),
                                            ("c5_crop", c5_crop(ku_spread=0.0), ((40, 2),)),
                                            ("c1", W.c1_plain_sc(), ())])
 def test_fp64_identical_across_kernels_and_tiles(name, w, shifts):
@@ -284,11 +300,13 @@ def test_fp64_identical_across_kernels_and_tiles(name, w, shifts):
     say("tile invariance", name)
     ref, lab, S0 = run_gpu(w, A.ASD_FP64, 100, shifts=shifts)
     a = ref.get_spins()
-    for tile in range(3):
+    h, _, _ = run_gpu(w, A.ASD_FP64, 100, kernel=A.ASD_KERNEL_PLAIN, tile=1, S0=S0, shifts=shifts)
+    np.testing.assert_array_equal(h.get_spins(), a)
+    for tile in range(4):
         h, _, _ = run_gpu(w, A.ASD_FP64, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
                           shifts=shifts)
         np.testing.assert_array_equal(h.get_spins(), a)
-    for tile in range(4):
+    for tile in range(8):
         h, _, _ = run_gpu(w, A.ASD_FP32, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
                           shifts=shifts)
         assert maxdiff(h.get_spins(), a) <= TOL[A.ASD_FP32]
