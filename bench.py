@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto ~15 s)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of known size (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -88,18 +90,20 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps):
             "fused": A.ASD_KERNEL_FUSED}[kernel_name]
     w = W.c2_granular_slab()
     h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_PLAIN, graph_steps=graph_steps)
-    if kern == A.ASD_KERNEL_AUTO:
-        try:
-            h.autotune(os.path.join(ROOT, "_build", "asd_tune.json"))
-        except A.AsdError:
-            pass
-    elif kern == A.ASD_KERNEL_FUSED:
-        h.set_variant(A.ASD_KERNEL_FUSED, max(args.tile, 0))
-    kernel_used, tile_used = h.variant()
     lab = h.labels()
     S0 = W.initial_spins(len(lab), w.seed + 100)
     S0[:, lab < 0] = 0
     h.set_spins(S0)
+    if kern == A.ASD_KERNEL_AUTO:
+        os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
+        h.autotune(os.path.join(ROOT, "_build", "asd_tune.json"))
+        h.set_spins(S0)
+        h.set_step(0)
+    elif kern == A.ASD_KERNEL_FUSED:
+        h.set_variant(A.ASD_KERNEL_FUSED, max(args.tile, 0))
+    elif args.tile >= 0:
+        h.set_variant(A.ASD_KERNEL_PLAIN, args.tile)
+    kernel_used, tile_used = h.variant()
     n_mag = int((lab >= 0).sum())
     n_sites = len(lab)
     h.step(warmup)
@@ -144,6 +148,12 @@ def main():
                                    "not part of this build (see DESIGN.md: sharding)"}))
         sys.exit(2)
     r = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, args.graph_steps)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     value = r["n_mag"] * r["steps"] / r["t"]
     bps = bytes_per_site(args.precision, "fused" if r["kernel"] == 2 else "plain")
     alg_bytes = bps * r["n_sites"]
@@ -167,8 +177,8 @@ def main():
                    "graph_steps": args.graph_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "heun step (all kernels of one step)" if r["kernel"] != 2
-                     else "k_fused_step", "bytes_per_site": bps,
+                     "kernel": "heun step (predictor + corrector kernels)" if r["kernel"] != 2
+                     else "k_fused_sc", "bytes_per_site": bps,
                      "step_ms_mean": 1e3 * r["step_mean"], "step_ms_median": 1e3 * r["step_med"]},
         "max_norm_error": r["norm_err"],
     }
