@@ -1,11 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the sLLG Heun step on one MI355X.
 
-Workload: the 200x200x33 simple-cubic granular slab (1.32M sites, Voronoi
-8 nm grains with 1 nm non-magnetic boundaries, 800 K Gaussian laser spot
-moving at 10 m/s over 300 K, -0.8 T write field), seeded synthetic input.
-A step is one full Heun step of every site (spot temperature, Philox noise,
-Box-Muller, exchange, anisotropy, Zeeman, predictor, corrector).
+Default workload (--workload slab): the 200x200x33 simple-cubic granular slab
+(1.32M sites, Voronoi 8 nm grains with 1 nm non-magnetic boundaries, 800 K
+Gaussian laser spot moving at 10 m/s over 300 K, -0.8 T write field), seeded
+synthetic input.  A step is one full Heun step of every site (spot
+temperature, Philox noise, Box-Muller, exchange, anisotropy, Zeeman,
+predictor, corrector).  Other workloads: l10 (L1_0 Fe sublattice window,
+four shells, 2.19M sites), cylinders (512 isolated grains of uneven size,
+each at its own temperature, moment statistics every 10 steps), track
+(16 seeds of a 400x200x33 moving window in an 800-column track with
+per-grain anisotropy spread and bit-timed write field).
 
 Prints one JSON line: spin-updates/s (magnetic sites x steps / s) with the
 roofline of the dominant kernel (algorithmic bytes per launch / its average
@@ -34,6 +39,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track"], default="slab")
     ap.add_argument("--kernel", choices=["auto", "plain", "fused"], default="auto")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--graph-steps", type=int, default=100)
@@ -45,23 +51,40 @@ def parse():
     return ap.parse_args()
 
 
-def bytes_per_site(precision: str, kernel: str) -> int:
-    """Algorithmic HBM bytes per lattice site and step: read S once, write S once."""
+def bytes_per_site(precision: str, workload: str) -> int:
+    """Algorithmic HBM bytes per lattice site and step: read S once, write S once
+    (+2 B grain label where k_u varies per grain; +72 B of neighbour indices for
+    the L1_0 table)."""
     e = 8 if precision == "fp64" else 4
-    return 2 * 3 * e
+    b = 2 * 3 * e
+    if workload == "track":
+        b += 2
+    if workload == "l10":
+        b += 4 * 18
+    return b
 
 
-def time_steps(torch, h, k):
-    """Whole-job time of k steps on the handle's stream (events + synchronize)."""
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(h.stream)
-    h.step(k)
-    stop.record(h.stream)
-    stop.synchronize()
-    torch.cuda.synchronize()
-    return start.elapsed_time(stop) / 1e3
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("asd_device.h", "asd_step.inc", "asd_fused.inc", "asd_variants.h", "asd_internal.h"):
+        with open(os.path.join(ROOT, "paper_2502_02236_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name, workload, precision):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary, if it was
+    taken on this kernel, workload and precision with the current kernel sources."""
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
+        with open(path) as f:
+            t = json.load(f)
+        if (t.get("kernel", "").split("(")[0].replace("void asd::", "") == kernel_name
+                and t.get("workload") == workload and t.get("precision") == precision
+                and t.get("source_hash") == kernel_sources_hash()):
+            return t["traffic_bytes"], os.path.basename(path)
+    return None, None
 
 
 def kernel_duration(torch, h, k):
@@ -79,42 +102,116 @@ def kernel_duration(torch, h, k):
     return float(np.median(d)), float(np.mean(d))
 
 
-def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps):
-    import torch
+def build_workload(name, prec, graph_steps):
+    """Handle + per-system initial spins + window-magnetic count for a workload."""
     import workloads as W
     from paper_2502_02236_amd import asd as A
     from paper_2502_02236_amd import bridge
 
+    extra = {}
+    if name in ("slab", "l10"):
+        w = W.c2_granular_slab() if name == "slab" else W.c3_l10_window()
+        h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_PLAIN, graph_steps=graph_steps)
+        labs = [h.labels()]
+        window = [np.ones(len(labs[0]), bool)]
+    elif name == "cylinders":
+        cyl = W.cylinder_batch(n=512)
+        w = W.Workload("cylinders512_d5-12nm_h8-12nm_T300-900K", bc=(0, 0, 0),
+                       B=(0.0, 0.0, 0.0), seed=4)
+        ins = [bridge.SystemInputs(w.scaled(nx=c.nx, ny=c.ny, nz=c.nz), labels=c.labels,
+                                   T_system=c.T) for c in cyl]
+        h = A.Handle(bridge.params_for(w, prec, graph_steps=graph_steps), [i.desc for i in ins])
+        dr, _ = bridge.drive_for(w, T_amb=0.0)
+        h.set_drive(dr)
+        h._inputs = ins
+        labs = [c.labels for c in cyl]
+        window = [np.ones(len(l), bool) for l in labs]
+        extra["moments_every"] = 10
+    else:  # track
+        n_seeds = 16
+        w = W.c5_track_window()
+        ins = []
+        for k in range(n_seeds):
+            wk = w.scaled(seed=w.seed + k)
+            seeds = W.voronoi_seeds(wk)
+            ku = W.grain_ku(len(seeds), w.ku, w.ku_spread, wk.seed)
+            ins.append(bridge.SystemInputs(wk, seeds=seeds, ku_grain=ku))
+        h = A.Handle(bridge.params_for(w, prec, graph_steps=graph_steps), [i.desc for i in ins])
+        dr, bits = bridge.drive_for(w)
+        h.set_drive(dr)
+        h._inputs = (ins, bits)
+        labs = [h.labels(k) for k in range(n_seeds)]
+        xs = np.arange(len(labs[0])) % w.track_nx
+        window = [(xs < w.nx)] * n_seeds
+        extra["shift_every"] = W.steps_per_column(w)
+    S0s = []
+    for k, lab in enumerate(labs):
+        S0 = W.initial_spins(len(lab), w.seed + 100 + k)
+        S0[:, lab < 0] = 0
+        S0s.append(S0)
+        h.set_spins(S0, k)
+    n_mag = int(sum(((l >= 0) & m).sum() for l, m in zip(labs, window)))
+    n_sites = int(sum(m.sum() for m in window))
+    return w, h, S0s, n_mag, n_sites, extra
+
+
+def run_steps(h, k, extra, done):
+    """k steps of the workload (moment samples / window shifts where it has them)."""
+    me = extra.get("moments_every", 0)
+    se = extra.get("shift_every", 0)
+    every = me or se
+    if not every:
+        h.step(k)
+        return
+    t = 0
+    while t < k:
+        nxt = min(k - t, every - (done + t) % every)
+        h.step(nxt)
+        t += nxt
+        if (done + t) % every == 0:
+            if me:
+                h.accumulate_moments(reset=(done + t) == me)
+            else:
+                h.shift_window(1)
+
+
+def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps):
+    import torch
+    from paper_2502_02236_amd import asd as A
+
     prec = A.ASD_FP32 if precision_name == "fp32" else A.ASD_FP64
     kern = {"auto": A.ASD_KERNEL_AUTO, "plain": A.ASD_KERNEL_PLAIN,
             "fused": A.ASD_KERNEL_FUSED}[kernel_name]
-    w = W.c2_granular_slab()
-    h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_PLAIN, graph_steps=graph_steps)
-    lab = h.labels()
-    S0 = W.initial_spins(len(lab), w.seed + 100)
-    S0[:, lab < 0] = 0
-    h.set_spins(S0)
+    w, h, S0s, n_mag, n_sites, extra = build_workload(args.workload, prec, graph_steps)
     if kern == A.ASD_KERNEL_AUTO:
         os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
         h.autotune(os.path.join(ROOT, "_build", "asd_tune.json"))
-        h.set_spins(S0)
+        for k, S0 in enumerate(S0s):
+            h.set_spins(S0, k)
         h.set_step(0)
     elif kern == A.ASD_KERNEL_FUSED:
         h.set_variant(A.ASD_KERNEL_FUSED, max(args.tile, 0))
     elif args.tile >= 0:
         h.set_variant(A.ASD_KERNEL_PLAIN, args.tile)
     kernel_used, tile_used = h.variant()
-    n_mag = int((lab >= 0).sum())
-    n_sites = len(lab)
-    h.step(warmup)
+    kname = h.variant_name()
+    run_steps(h, warmup, extra, 0)
     torch.cuda.synchronize()
-    t = time_steps(torch, h, steps)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(h.stream)
+    run_steps(h, steps, extra, warmup)
+    stop.record(h.stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    t = start.elapsed_time(stop) / 1e3
     med, mean = kernel_duration(torch, h, min(200, steps))
-    S = h.get_spins().astype(np.float64)
-    norm_err = float(np.max(np.abs(np.sqrt((S[:, lab >= 0] ** 2).sum(0)) - 1)))
+    S = h.get_spins(0).astype(np.float64)
+    mag = np.abs(S).sum(0) > 0
+    norm_err = float(np.max(np.abs(np.sqrt((S[:, mag] ** 2).sum(0)) - 1)))
     h.close()
     return dict(w=w, t=t, n_mag=n_mag, n_sites=n_sites, steps=steps, kernel=kernel_used,
-                tile=tile_used, step_med=med, step_mean=mean, norm_err=norm_err)
+                tile=tile_used, step_med=med, step_mean=mean, norm_err=norm_err, kname=kname)
 
 
 def cpu_baseline(target_s=15.0, steps=0):
@@ -155,9 +252,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     value = r["n_mag"] * r["steps"] / r["t"]
-    bps = bytes_per_site(args.precision, "fused" if r["kernel"] == 2 else "plain")
+    bps = bytes_per_site(args.precision, args.workload)
     alg_bytes = bps * r["n_sites"]
-    achieved = alg_bytes / r["step_mean"] / 1e9
+    # average launch duration of the step kernel over the timed region (kernels
+    # back to back on the handle's stream; includes the gaps between them)
+    launch_s = r["t"] / r["steps"]
+    achieved = alg_bytes / launch_s / 1e9
+    traffic, traffic_src = measured_traffic(r["kname"], args.workload, args.precision)
     out = {
         "metric": "atomistic spin-updates/s (spins x Heun steps)",
         "value": value,
@@ -171,23 +272,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": r["w"].name, "lattice": "sc", "sites": r["n_sites"],
+        "config": {"workload": r["w"].name, "lattice": "l10" if args.workload == "l10" else "sc",
+                   "sites": r["n_sites"],
                    "magnetic_sites": r["n_mag"], "dt_fs": 1.0, "precision": args.precision,
                    "kernel": {1: "plain", 2: "fused"}.get(r["kernel"], "?"), "tile": r["tile"],
                    "graph_steps": args.graph_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "heun step (predictor + corrector kernels)" if r["kernel"] != 2
-                     else "k_fused_sc", "bytes_per_site": bps,
-                     "step_ms_mean": 1e3 * r["step_mean"], "step_ms_median": 1e3 * r["step_med"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": r["kname"], "bytes_per_site": bps,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "launch_us_mean": 1e6 * launch_s,
+                     "launch_us_eager_events_median": 1e6 * r["step_med"],
+                     "traffic_source": traffic_src},
         "max_norm_error": r["norm_err"],
     }
-    if not args.no_fp64_compare and args.precision == "fp32":
+    if not args.no_fp64_compare and args.precision == "fp32" and args.workload == "slab":
         r64 = gpu_run(args, "fp64", "plain", max(200, args.steps // 10), 20, 0)
         v64 = r64["n_mag"] * r64["steps"] / r64["t"]
         out["fp64_plain_value"] = v64
         out["speedup_vs_fp64_plain"] = value / v64
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "slab":
         out["cpu_baseline"] = cpu_baseline(steps=args.cpu_steps)
     print(json.dumps(out), flush=True)
 

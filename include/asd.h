@@ -231,6 +231,9 @@ int asd_autotune(asd_t *h, const char *cache_path);
 /* Force a variant: kernel ASD_KERNEL_*, tile index (0 = default). */
 int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile);
 int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile);
+/* Name of the step kernel(s) the current variant launches (as profilers list
+ * them), NUL-terminated into buf[len]; ASD_EINVAL if it does not fit. */
+int asd_variant_name(asd_t *h, char *buf, size_t len);
 
 const char *asd_strerror(int code);
 const char *asd_last_error(const asd_t *h);

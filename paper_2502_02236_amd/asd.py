@@ -29,7 +29,8 @@ SYMBOLS = [
     "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
     "asd_neighbour_count", "asd_get_neighbours", "asd_get_state", "asd_set_step", "asd_philox",
-    "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_strerror", "asd_last_error",
+    "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_name", "asd_strerror",
+    "asd_last_error",
 ]
 
 
@@ -99,6 +100,7 @@ def lib():
         L.asd_autotune.argtypes = [h, C.c_char_p]
         L.asd_set_variant.argtypes = [h, C.c_int32, C.c_int32]
         L.asd_get_variant.argtypes = [h, P(C.c_int32), P(C.c_int32)]
+        L.asd_variant_name.argtypes = [h, C.c_char_p, C.c_size_t]
         L.asd_strerror.argtypes = [C.c_int]
         L.asd_strerror.restype = C.c_char_p
         L.asd_last_error.argtypes = [h]
@@ -310,6 +312,11 @@ class Handle:
 
     def variant(self):
         return asd_get_variant(self.h)
+
+    def variant_name(self) -> str:
+        buf = C.create_string_buffer(256)
+        _check(lib().asd_variant_name(self.h, buf, 256), self.h)
+        return buf.value.decode()
 
     def autotune(self, cache_path=None):
         asd_autotune(self.h, cache_path)

@@ -1137,6 +1137,25 @@ int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile)
     return ASD_OK;
 }
 
+int asd_variant_name(asd_t *h, char *buf, size_t len)
+{
+    if (!h || !buf || len == 0) return fail(h, ASD_EINVAL, "bad argument");
+    const bool fp64 = h->p.precision == ASD_FP64;
+    const char *T = fp64 ? "double" : "float";
+    char tmp[256];
+    if (h->kernel == ASD_KERNEL_FUSED) {
+        const FusedVariant f = fused_variant(fp64, h->tile_cfg);
+        snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d>", T, f.txe, f.waves, f.rows);
+    } else if (h->tile_cfg == 1) {
+        snprintf(tmp, sizeof tmp, "k_plain_predictor<%s, true>+k_stash_corrector<%s>", T, T);
+    } else {
+        snprintf(tmp, sizeof tmp, "k_plain_predictor<%s, false>+k_plain_corrector<%s>", T, T);
+    }
+    if (strlen(tmp) + 1 > len) return fail(h, ASD_EINVAL, "buffer too small");
+    memcpy(buf, tmp, strlen(tmp) + 1);
+    return ASD_OK;
+}
+
 // ------------------------------------------------------------------ autotuning
 static std::string tune_key(const asd_t *h)
 {
