@@ -313,6 +313,17 @@ class Handle:
     def variant(self):
         return asd_get_variant(self.h)
 
+    def variant_count(self, kernel: int) -> int:
+        """Number of variants of a kernel family (probed through asd_set_variant)."""
+        cur = self.variant()
+        n = 0
+        while True:
+            if lib().asd_set_variant(self.h, kernel, n) != ASD_OK:
+                break
+            n += 1
+        asd_set_variant(self.h, *cur)
+        return n
+
     def variant_name(self) -> str:
         buf = C.create_string_buffer(256)
         _check(lib().asd_variant_name(self.h, buf, 256), self.h)

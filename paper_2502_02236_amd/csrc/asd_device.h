@@ -17,7 +17,7 @@
 //   exp x (x <= 0): k = floor(x/ln2 + 1/2), r = (x - k ln2_hi) - k ln2_lo,
 //          Taylor through r^13 (Horner), scaled by 2^k; 0 below -700.
 // FP32 uses the hardware transcendentals (v_log_f32, v_exp_f32, v_sin_f32,
-// v_cos_f32, v_sqrt_f32).
+// v_cos_f32, v_sqrt_f32) and folds sigma into the Box-Muller radius.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,8 +35,9 @@ __device__ __forceinline__ void philox_round(uint32_t k0, uint32_t k1, uint32_t 
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
     uint64_t p0 = (uint64_t)M0 * c0;
     uint64_t p1 = (uint64_t)M1 * c2;
-    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    // three-way xor in one v_bitop3_b32 (truth table 0x96)
+    uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+    uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -202,27 +203,37 @@ __device__ __forceinline__ void box_muller(uint32_t wr, uint32_t wt, double &gc,
 // ---------------------------------------------------------------- FP32
 namespace f32 {
 
-// ln u = ln2 * log2 u (v_log_f32); u_r = w 2^-32 + 2^-33 rounded to FP32.
-__device__ __forceinline__ void box_muller(uint32_t wr, uint32_t wt, float &gc, float &gs)
+// Thermal-field Box-Muller pair in FP32 with sigma folded into the radius:
+// sigma r = sqrt(sigma^2 (-2 ln u_r)) = sqrt(ns2 log2 u_r) with
+// ns2 = -2 ln2 sigma^2; u_r = w 2^-32 + 2^-33 rounded to FP32; v_log_f32 is
+// log2, v_sqrt_f32 the hardware square root (about 1 ulp), and v_sin_f32 /
+// v_cos_f32 take their argument in revolutions.
+__device__ __forceinline__ void box_muller_scaled(uint32_t wr, uint32_t wt, float ns2, float &gc,
+                                                  float &gs)
 {
     const float TWO_M32 = 2.3283064365386962890625e-10f;
     const float TWO_M33 = 1.16415321826934814453125e-10f;
     float ur = __builtin_fmaf((float)wr, TWO_M32, TWO_M33);
     float ut = (float)wt * TWO_M32;
-    float r = __builtin_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(ur));
-    // v_sin_f32 / v_cos_f32 take their argument in revolutions
+    float r = __builtin_amdgcn_sqrtf(ns2 * __builtin_amdgcn_logf(ur));
     gc = r * __builtin_amdgcn_cosf(ut);
     gs = r * __builtin_amdgcn_sinf(ut);
 }
 
-__device__ __forceinline__ float box_muller_cos(uint32_t wr, uint32_t wt)
+__device__ __forceinline__ float box_muller_scaled_cos(uint32_t wr, uint32_t wt, float ns2)
 {
     const float TWO_M32 = 2.3283064365386962890625e-10f;
     const float TWO_M33 = 1.16415321826934814453125e-10f;
     float ur = __builtin_fmaf((float)wr, TWO_M32, TWO_M33);
     float ut = (float)wt * TWO_M32;
-    float r = __builtin_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(ur));
+    float r = __builtin_amdgcn_sqrtf(ns2 * __builtin_amdgcn_logf(ur));
     return r * __builtin_amdgcn_cosf(ut);
+}
+
+// -2 ln 2 sigma^2 with sigma^2 = cth T
+__device__ __forceinline__ float neg2ln2_sigma2(float cth, float T)
+{
+    return -1.38629436111989061883f * (cth * T);
 }
 
 // exp(x) = 2^(x log2 e) on v_exp_f32

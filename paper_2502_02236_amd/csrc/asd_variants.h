@@ -15,14 +15,16 @@ struct FusedVariant {
     int txe, waves, rows, lz;
 };
 
-inline int fused_variant_count(bool fp64) { return fp64 ? 4 : 8; }
+inline int fused_variant_count(bool fp64) { return fp64 ? 6 : 12; }
 
 inline FusedVariant fused_variant(bool fp64, int v)
 {
-    static const FusedVariant f32v[8] = {
-        {64, 8, 4, 0}, {64, 4, 2, 0}, {32, 4, 2, 11}, {32, 4, 2, 0},
-        {32, 8, 2, 8}, {16, 4, 2, 11}, {64, 4, 4, 0}, {32, 4, 1, 11}};
-    static const FusedVariant f64v[4] = {{64, 4, 2, 0}, {32, 4, 2, 11}, {32, 4, 1, 0}, {32, 8, 1, 11}};
+    static const FusedVariant f32v[12] = {
+        {64, 8, 4, 0},  {64, 4, 2, 0},  {32, 4, 2, 11}, {32, 4, 2, 0},
+        {32, 8, 2, 8},  {16, 4, 2, 11}, {64, 4, 4, 0},  {32, 4, 1, 11},
+        {32, 8, 1, 11}, {32, 4, 1, 17}, {32, 8, 1, 17}, {32, 8, 1, 0}};
+    static const FusedVariant f64v[6] = {{64, 4, 2, 0},  {32, 4, 2, 11}, {32, 4, 1, 0},
+                                         {32, 8, 1, 11}, {32, 4, 1, 11}, {32, 8, 1, 17}};
     const int n = fused_variant_count(fp64);
     if (v < 0 || v >= n) v = 0;
     return fp64 ? f64v[v] : f32v[v];

@@ -302,11 +302,16 @@ def test_fp64_identical_across_kernels_and_tiles(name, w, shifts):
     a = ref.get_spins()
     h, _, _ = run_gpu(w, A.ASD_FP64, 100, kernel=A.ASD_KERNEL_PLAIN, tile=1, S0=S0, shifts=shifts)
     np.testing.assert_array_equal(h.get_spins(), a)
-    for tile in range(4):
+    n64 = ref.variant_count(A.ASD_KERNEL_FUSED)
+    assert n64 >= 4
+    for tile in range(n64):
         h, _, _ = run_gpu(w, A.ASD_FP64, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
                           shifts=shifts)
         np.testing.assert_array_equal(h.get_spins(), a)
-    for tile in range(8):
+    h32 = bridge.make_handle(w, A.ASD_FP32)
+    n32 = h32.variant_count(A.ASD_KERNEL_FUSED)
+    assert n32 >= 8
+    for tile in range(n32):
         h, _, _ = run_gpu(w, A.ASD_FP32, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
                           shifts=shifts)
         assert maxdiff(h.get_spins(), a) <= TOL[A.ASD_FP32]
