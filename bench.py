@@ -51,15 +51,15 @@ def parse():
     return ap.parse_args()
 
 
-def bytes_per_site(precision: str, workload: str) -> int:
+def bytes_per_site(precision: str, workload: str, kernel_name: str) -> int:
     """Algorithmic HBM bytes per lattice site and step: read S once, write S once
-    (+2 B grain label where k_u varies per grain; +72 B of neighbour indices for
-    the L1_0 table)."""
+    (+2 B grain label where k_u varies per grain; +72 B of neighbour indices when
+    the L1_0 two-pass kernels read the neighbour table)."""
     e = 8 if precision == "fp64" else 4
     b = 2 * 3 * e
     if workload == "track":
         b += 2
-    if workload == "l10":
+    if workload == "l10" and not kernel_name.startswith("k_fused"):
         b += 4 * 18
     return b
 
@@ -252,7 +252,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     value = r["n_mag"] * r["steps"] / r["t"]
-    bps = bytes_per_site(args.precision, args.workload)
+    bps = bytes_per_site(args.precision, args.workload, r["kname"])
     alg_bytes = bps * r["n_sites"]
     # average launch duration of the step kernel over the timed region (kernels
     # back to back on the handle's stream; includes the gaps between them)

@@ -355,10 +355,11 @@ static void fused_tiles_of(const asd_params *p, const asd_system_desc *d, int ti
                            int *ty, int *tz = nullptr, int *lz = nullptr)
 {
     int bx, by;
-    fused_tile_interior(p->precision == ASD_FP64, tile_cfg, &bx, &by);
+    const bool l10 = p->lattice == ASD_L10;
+    fused_tile_interior(p->precision == ASD_FP64, tile_cfg, &bx, &by, l10);
     *tx = (d->nx + bx - 1) / bx;
     *ty = (d->ny + by - 1) / by;
-    const FusedVariant f = fused_variant(p->precision == ASD_FP64, tile_cfg);
+    const FusedVariant f = fused_pick(l10, p->precision == ASD_FP64, tile_cfg);
     const int len = f.lz > 0 ? std::min(f.lz, d->nz) : d->nz;
     if (lz) *lz = len;
     if (tz) *tz = (d->nz + len - 1) / len;
@@ -390,7 +391,7 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         tiles += (int32_t)((nw + kPlainTile - 1) / kPlainTile);
         int fx = 0, fy = 0, fz = 0;
         int maxf = 0;
-        for (int v = 0; v < fused_variant_count(p->precision == ASD_FP64); ++v) {
+        for (int v = 0; v < fused_count(p->lattice == ASD_L10, p->precision == ASD_FP64); ++v) {
             fused_tiles_of(p, d, v, &fx, &fy, &fz);
             maxf = std::max(maxf, fx * fy * fz);
         }
@@ -781,6 +782,7 @@ static StepArgs<T> make_args(const asd_t *h, int cur, int step_off)
     a.zero_site = L.zero_site;
     a.step_off = step_off;
     a.tile_cfg = h->tile_cfg;
+    a.lattice = h->p.lattice;
     a.c = make_consts(h);
     return a;
 }
@@ -1080,7 +1082,6 @@ int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out
 // reason the fused kernel cannot serve this handle, or NULL
 static const char *fused_unsupported(const asd_t *h)
 {
-    if (h->p.lattice != ASD_SC) return "the fused kernel covers the SC lattice only";
     for (const HostSys &hs : h->sys)
         if (hs.desc.bc_z != ASD_BC_OPEN) return "the fused kernel marches z between open surfaces";
     return nullptr;
@@ -1114,8 +1115,9 @@ int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile)
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
     if (kernel != ASD_KERNEL_PLAIN && kernel != ASD_KERNEL_FUSED)
         return fail(h, ASD_EINVAL, "kernel must be PLAIN or FUSED");
-    const int nvar = kernel == ASD_KERNEL_PLAIN ? kPlainVariants
-                                                : fused_variant_count(h->p.precision == ASD_FP64);
+    const int nvar = kernel == ASD_KERNEL_PLAIN
+                         ? kPlainVariants
+                         : fused_count(h->p.lattice == ASD_L10, h->p.precision == ASD_FP64);
     if (tile < 0 || tile >= nvar) return fail(h, ASD_EINVAL, "variant out of range");
     if (kernel == ASD_KERNEL_FUSED) {
         const char *why = fused_unsupported(h);
@@ -1144,8 +1146,10 @@ int asd_variant_name(asd_t *h, char *buf, size_t len)
     const char *T = fp64 ? "double" : "float";
     char tmp[256];
     if (h->kernel == ASD_KERNEL_FUSED) {
-        const FusedVariant f = fused_variant(fp64, h->tile_cfg);
-        snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d>", T, f.txe, f.waves, f.rows);
+        const bool l10 = h->p.lattice == ASD_L10;
+        const FusedVariant f = fused_pick(l10, fp64, h->tile_cfg);
+        snprintf(tmp, sizeof tmp, "k_fused_%s<%s, %d, %d, %d>", l10 ? "l10" : "sc", T, f.txe, f.waves,
+                 f.rows);
     } else if (h->tile_cfg == 1) {
         snprintf(tmp, sizeof tmp, "k_plain_predictor<%s, true>+k_stash_corrector<%s>", T, T);
     } else {
@@ -1270,7 +1274,7 @@ int asd_autotune(asd_t *h, const char *cache_path)
     std::vector<Cand> cands;
     for (int v = 0; v < kPlainVariants; ++v) cands.push_back({ASD_KERNEL_PLAIN, v});
     if (!fused_unsupported(h))
-        for (int v = 0; v < fused_variant_count(h->p.precision == ASD_FP64); ++v)
+        for (int v = 0; v < fused_count(h->p.lattice == ASD_L10, h->p.precision == ASD_FP64); ++v)
             cands.push_back({ASD_KERNEL_FUSED, v});
     double best = 1e30;
     Cand pick = cands[0];

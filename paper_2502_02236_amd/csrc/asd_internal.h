@@ -74,6 +74,7 @@ struct StepArgs {
     int32_t step_off;         // step = *step_base + step_off
     int32_t tile_cfg;         // tile variant
     int32_t n_blocks;         // blocks of the launch (XCD-contiguous tile order)
+    int32_t lattice;          // ASD_SC / ASD_L10
     StepConsts c;
 };
 

@@ -2,6 +2,7 @@
 // FP32; spot position and time in FP64).
 #include "asd_step.inc"
 #include "asd_fused.inc"
+#include "asd_fused_l10.inc"
 
 namespace asd {
 
@@ -12,6 +13,7 @@ int launch_plain_step_f32(const StepArgs<float> &a, int n_blocks, void *stream)
 
 int launch_fused_step_f32(const StepArgs<float> &a, int n_blocks, void *stream)
 {
+    if (a.lattice == ASD_L10) return launch_fused_l10<float>(a, n_blocks, stream);
     return launch_fused<float>(a, n_blocks, stream);
 }
 

@@ -3,6 +3,7 @@
 // fixed order of asd_step.inc.
 #include "asd_step.inc"
 #include "asd_fused.inc"
+#include "asd_fused_l10.inc"
 
 namespace asd {
 
@@ -13,6 +14,7 @@ int launch_plain_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)
 
 int launch_fused_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)
 {
+    if (a.lattice == ASD_L10) return launch_fused_l10<double>(a, n_blocks, stream);
     return launch_fused<double>(a, n_blocks, stream);
 }
 

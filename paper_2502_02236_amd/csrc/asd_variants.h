@@ -30,9 +30,32 @@ inline FusedVariant fused_variant(bool fp64, int v)
     return fp64 ? f64v[v] : f32v[v];
 }
 
-inline void fused_tile_interior(bool fp64, int v, int *tx, int *ty)
+// Fused L1_0 kernel variants (cell tiles, both sublattices per column).
+inline int fused_l10_variant_count(bool fp64) { return fp64 ? 3 : 5; }
+
+inline FusedVariant fused_l10_variant(bool fp64, int v)
 {
-    FusedVariant f = fused_variant(fp64, v);
+    static const FusedVariant f32v[5] = {{32, 4, 1, 9}, {32, 4, 1, 0}, {32, 8, 1, 9}, {16, 4, 1, 9},
+                                         {32, 8, 1, 0}};
+    static const FusedVariant f64v[3] = {{32, 4, 1, 9}, {32, 4, 1, 0}, {16, 4, 1, 9}};
+    const int n = fused_l10_variant_count(fp64);
+    if (v < 0 || v >= n) v = 0;
+    return fp64 ? f64v[v] : f32v[v];
+}
+
+inline int fused_count(bool l10, bool fp64)
+{
+    return l10 ? fused_l10_variant_count(fp64) : fused_variant_count(fp64);
+}
+
+inline FusedVariant fused_pick(bool l10, bool fp64, int v)
+{
+    return l10 ? fused_l10_variant(fp64, v) : fused_variant(fp64, v);
+}
+
+inline void fused_tile_interior(bool fp64, int v, int *tx, int *ty, bool l10 = false)
+{
+    FusedVariant f = fused_pick(l10, fp64, v);
     *tx = f.txe - 2;
     *ty = f.waves * f.rows * 64 / f.txe - 2;
 }

@@ -163,8 +163,6 @@ VARIANTS = [(A.ASD_KERNEL_PLAIN, 0), (A.ASD_KERNEL_PLAIN, 1), (A.ASD_KERNEL_FUSE
 @pytest.mark.parametrize("name,w,shifts,ku_spread", CASES)
 def test_trajectory_parity(name, w, shifts, ku_spread, precision, kernel, tile):
     steps = 100
-    if kernel == A.ASD_KERNEL_FUSED and w.kind != W.SC:
-        pytest.skip("the fused kernel covers the SC lattice")
     say("trajectory", name, "fp64" if precision == A.ASD_FP64 else "fp32",
         "fused" if kernel == A.ASD_KERNEL_FUSED else "plain", tile)
     ku = None
@@ -292,6 +290,7 @@ def test_full_size_c2_few_steps_against_oracle(kernel, tmp_path):
 
 
 @pytest.mark.parametrize("name,w,shifts", [("c2_crop", c2_crop(nz=25), ()),
+                                           ("c3_crop_tall", c3_crop(nz=20), ()),
                                            ("c5_crop", c5_crop(ku_spread=0.0), ((40, 2),)),
                                            ("c1", W.c1_plain_sc(), ())])
 def test_fp64_identical_across_kernels_and_tiles(name, w, shifts):
@@ -303,14 +302,14 @@ def test_fp64_identical_across_kernels_and_tiles(name, w, shifts):
     h, _, _ = run_gpu(w, A.ASD_FP64, 100, kernel=A.ASD_KERNEL_PLAIN, tile=1, S0=S0, shifts=shifts)
     np.testing.assert_array_equal(h.get_spins(), a)
     n64 = ref.variant_count(A.ASD_KERNEL_FUSED)
-    assert n64 >= 4
+    assert n64 >= 3
     for tile in range(n64):
         h, _, _ = run_gpu(w, A.ASD_FP64, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
                           shifts=shifts)
         np.testing.assert_array_equal(h.get_spins(), a)
     h32 = bridge.make_handle(w, A.ASD_FP32)
     n32 = h32.variant_count(A.ASD_KERNEL_FUSED)
-    assert n32 >= 8
+    assert n32 >= 5
     for tile in range(n32):
         h, _, _ = run_gpu(w, A.ASD_FP32, 100, kernel=A.ASD_KERNEL_FUSED, tile=tile, S0=S0,
                           shifts=shifts)
