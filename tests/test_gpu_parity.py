@@ -392,27 +392,31 @@ def test_curie_temperature_from_binder_crossing():
     (no anisotropy, no field) of L = 8 and 16; the Binder cumulants
     U4 = 1 - <m^4> / (3 <m^2>^2) cross at T_C = 1.443 J/kB (classical Heisenberg model,
     Monte-Carlo literature; the same value the paper's mean-field correction
-    eps_SC = 0.72 of Eq. 8 implies, 1.44 J/kB).  Tolerance 3 % (finite size, Heun
-    time-step bias, statistics)."""
+    eps_SC = 0.72 of Eq. 8 implies, 1.44 J/kB).  Run at the paper's damping 0.1 and
+    dt = 1 fs, where the Heun time-step bias of the stationary state is ~0.4 %;
+    tolerance 2 % (finite size, bias, statistics)."""
     J = 6.7e-21
     Tc = 1.443 * J / W.KB
-    ratios = [0.94, 0.97, 1.0, 1.03, 1.06]
-    Ls, reps = (8, 16), 6
-    w0 = W.Workload("cube", bc=(1, 1, 1), J=(J,), ku=0.0, B=(0.0, 0.0, 0.0), alpha=1.0,
+    ratios = [0.9, 0.95, 1.0, 1.05, 1.1]
+    Ls, reps = (8, 16), 8
+    w0 = W.Workload("cube", bc=(1, 1, 1), J=(J,), ku=0.0, B=(0.0, 0.0, 0.0), alpha=0.1,
                     seed=31, dt=1e-15)
     ins, meta = [], []
     for L in Ls:
         for r in ratios:
             for k in range(reps):
                 ins.append(bridge.SystemInputs(w0.scaled(nx=L, ny=L, nz=L), T_system=r * Tc))
-                meta.append((L, r))
-    h = A.Handle(bridge.params_for(w0, A.ASD_FP32), [i.desc for i in ins])
+                meta.append((L, r, k))
+    h = A.Handle(bridge.params_for(w0, A.ASD_FP32, graph_steps=1000), [i.desc for i in ins])
     dr, _ = bridge.drive_for(w0, T_amb=0.0)
     h.set_drive(dr)
-    for k, (L, _) in enumerate(meta):
-        h.set_spins(np.stack([np.zeros(L ** 3), np.zeros(L ** 3), np.ones(L ** 3)]), k)
-    h.step(20000)
-    every, n_samp = 10, 4000
+    # half of the replicas start ordered, half disordered
+    for i, (L, _, k) in enumerate(meta):
+        S = (W.random_spins(L ** 3, 100 + i) if k % 2 else
+             np.stack([np.zeros(L ** 3), np.zeros(L ** 3), np.ones(L ** 3)]))
+        h.set_spins(S, i)
+    h.step(100000)
+    every, n_samp = 10, 20000
     for s in range(n_samp):
         h.step(every)
         h.accumulate_moments(reset=(s == 0))
@@ -420,17 +424,17 @@ def test_curie_temperature_from_binder_crossing():
     U = {}
     for L in Ls:
         for r in ratios:
-            idx = [k for k, m in enumerate(meta) if m == (L, r)]
+            idx = [i for i, m in enumerate(meta) if m[:2] == (L, r)]
             m2 = st[idx, 2].sum() / st[idx, 0].sum()
             m4 = st[idx, 3].sum() / st[idx, 0].sum()
             U[(L, r)] = 1 - m4 / (3 * m2 * m2)
     d = np.array([U[(Ls[0], r)] - U[(Ls[1], r)] for r in ratios])
-    say("  U4 L=8 ", [round(U[(8, r)], 4) for r in ratios])
-    say("  U4 L=16", [round(U[(16, r)], 4) for r in ratios])
+    say("  U4 L=8 ", [round(float(U[(8, r)]), 4) for r in ratios])
+    say("  U4 L=16", [round(float(U[(16, r)]), 4) for r in ratios])
     # the larger lattice has the larger cumulant below T_C and the smaller above
     assert d[0] < 0 and d[-1] > 0
     k = int(np.argmax(d > 0))
     r0, r1 = ratios[k - 1], ratios[k]
     cross = r0 + (r1 - r0) * (-d[k - 1]) / (d[k] - d[k - 1])
     say(f"  Binder crossing at T/Tc = {cross:.4f}  ({cross * Tc:.1f} K)")
-    assert abs(cross - 1.0) < 0.03
+    assert abs(cross - 1.0) < 0.02
