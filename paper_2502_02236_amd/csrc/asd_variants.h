@@ -15,14 +15,15 @@ struct FusedVariant {
     int txe, waves, rows, lz;
 };
 
-inline int fused_variant_count(bool fp64) { return fp64 ? 6 : 12; }
+inline int fused_variant_count(bool fp64) { return fp64 ? 6 : 14; }
 
 inline FusedVariant fused_variant(bool fp64, int v)
 {
-    static const FusedVariant f32v[12] = {
+    static const FusedVariant f32v[14] = {
         {64, 8, 4, 0},  {64, 4, 2, 0},  {32, 4, 2, 11}, {32, 4, 2, 0},
         {32, 8, 2, 8},  {16, 4, 2, 11}, {64, 4, 4, 0},  {32, 4, 1, 11},
-        {32, 8, 1, 11}, {32, 4, 1, 17}, {32, 8, 1, 17}, {32, 8, 1, 0}};
+        {32, 8, 1, 11}, {32, 4, 1, 17}, {32, 8, 1, 17}, {32, 8, 1, 0},
+        {64, 8, 2, 0},  {64, 8, 2, 17}};
     static const FusedVariant f64v[6] = {{64, 4, 2, 0},  {32, 4, 2, 11}, {32, 4, 1, 0},
                                          {32, 8, 1, 11}, {32, 4, 1, 11}, {32, 8, 1, 17}};
     const int n = fused_variant_count(fp64);
