@@ -56,6 +56,7 @@ struct Layout {
     int32_t n_ftiles = 0;  // fused tiles
     size_t off_S[3] = {0, 0, 0};
     size_t off_F0 = 0, off_Bt = 0;  // stash buffers of the two-pass variant 1
+    size_t off_can32 = 0;
     size_t off_label = 0, off_ell = 0, off_sys = 0, off_tile = 0, off_ftile = 0, off_can = 0,
            off_ku = 0, off_gsys = 0, off_gptr = 0, off_gsites = 0, off_step = 0, off_origin = 0,
            off_bits = 0, off_gout = 0, off_sout = 0, off_mom = 0, off_epart = 0, off_eout = 0;
@@ -419,6 +420,7 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
     L.off_tile = take((size_t)std::max(tiles, 1) * sizeof(int32_t));
     L.off_ftile = take((size_t)std::max(ftiles, 1) * sizeof(int32_t));
     L.off_can = take((size_t)std::max(g, 1) * sizeof(double));
+    L.off_can32 = take((size_t)std::max(g, 1) * sizeof(float));
     L.off_ku = take((size_t)std::max(g, 1) * sizeof(double));
     L.off_gsys = take((size_t)std::max(g, 1) * sizeof(int32_t));
     L.off_gptr = take((size_t)(g + 1) * sizeof(int64_t));
@@ -523,6 +525,7 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
     h->dev.resize(n_sys);
     std::vector<int32_t> tile_sys, gsys;
     std::vector<double> can, ku;
+    std::vector<float> can32;
     std::vector<int64_t> gptr(1, 0);
     std::vector<int32_t> gsites;
     std::vector<uint16_t> lab((size_t)L.ncs, kNoGrain);
@@ -587,6 +590,9 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
                              hipMemcpyHostToDevice, st));
     if (!can.empty()) {
         HIP_OK(h, hipMemcpyAsync(w + L.off_can, can.data(), can.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, st));
+        can32.assign(can.begin(), can.end());
+        HIP_OK(h, hipMemcpyAsync(w + L.off_can32, can32.data(), can32.size() * sizeof(float),
                                  hipMemcpyHostToDevice, st));
         HIP_OK(h, hipMemcpyAsync(w + L.off_ku, ku.data(), ku.size() * sizeof(double),
                                  hipMemcpyHostToDevice, st));
@@ -776,6 +782,7 @@ static StepArgs<T> make_args(const asd_t *h, int cur, int step_off)
     a.ell = h->p.lattice == ASD_L10 ? (const int32_t *)(w + L.off_ell) : nullptr;
     a.label = (const uint16_t *)(w + L.off_label);
     a.can_grain = (const double *)(w + L.off_can);
+    a.can_grain32 = (const float *)(w + L.off_can32);
     a.step_base = (const int64_t *)(w + L.off_step);
     a.origin = (const int32_t *)(w + L.off_origin);
     a.bits = (const uint8_t *)(w + L.off_bits);

@@ -67,6 +67,7 @@ struct StepArgs {
     const int32_t *ell;       // L1_0 neighbours [kL10Degree][ncs] (absent: zero_site)
     const uint16_t *label;    // local grain label per stored site
     const double *can_grain;  // 2 k_u,g / mu_s per global grain
+    const float *can_grain32; // the same rounded to FP32 (FP32 kernels)
     const int64_t *step_base; // device step counter
     const int32_t *origin;    // window origin per system
     const uint8_t *bits;      // polarity bits
