@@ -213,6 +213,14 @@ int asd_get_grain_labels(asd_t *h, int32_t sys, int32_t *labels);
 int asd_neighbour_count(asd_t *h, int32_t sys, int64_t *n_entries);
 int asd_get_neighbours(asd_t *h, int32_t sys, int64_t *row_ptr, int32_t *col, int8_t *shell);
 
+/* Host-only versions of the two tables above, computed from descriptors
+ * without a device or handle (same code as asd_create uses): labels[n_stored]
+ * and the CSR neighbour table.  asd_host_neighbours with NULL arrays only
+ * writes the entry count to *n_entries. */
+int asd_host_grain_labels(const asd_params *p, const asd_system_desc *sys, int32_t *labels);
+int asd_host_neighbours(const asd_params *p, const asd_system_desc *sys, int64_t *n_entries,
+                        int64_t *row_ptr, int32_t *col, int8_t *shell);
+
 /* Step counter and window origin of system sys (host copies). */
 int asd_get_state(asd_t *h, int32_t sys, int64_t *step, int32_t *origin);
 /* Set the step counter (resume from a checkpoint). */

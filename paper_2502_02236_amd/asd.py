@@ -28,7 +28,8 @@ SYMBOLS = [
     "asd_set_spins", "asd_get_spins", "asd_step", "asd_shift_window",
     "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
-    "asd_neighbour_count", "asd_get_neighbours", "asd_get_state", "asd_set_step", "asd_philox",
+    "asd_neighbour_count", "asd_get_neighbours", "asd_host_grain_labels", "asd_host_neighbours",
+    "asd_get_state", "asd_set_step", "asd_philox",
     "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_name", "asd_strerror",
     "asd_last_error",
 ]
@@ -94,6 +95,8 @@ def lib():
         L.asd_get_grain_labels.argtypes = [h, C.c_int32, vp]
         L.asd_neighbour_count.argtypes = [h, C.c_int32, P(C.c_int64)]
         L.asd_get_neighbours.argtypes = [h, C.c_int32, vp, vp, vp]
+        L.asd_host_grain_labels.argtypes = [P(asd_params), P(asd_system_desc), vp]
+        L.asd_host_neighbours.argtypes = [P(asd_params), P(asd_system_desc), P(C.c_int64), vp, vp, vp]
         L.asd_get_state.argtypes = [h, C.c_int32, P(C.c_int64), P(C.c_int32)]
         L.asd_set_step.argtypes = [h, C.c_int64]
         L.asd_philox.argtypes = [C.c_uint64, C.c_int32, vp, vp, C.c_int64, vp]
@@ -179,6 +182,30 @@ def asd_get_moment_stats(h, out):
 def asd_philox(seed, rounds, ctr_ptr, out_ptr, n, stream_ptr):
     _check(lib().asd_philox(seed, rounds, C.c_void_p(ctr_ptr), C.c_void_p(out_ptr), n,
                             C.c_void_p(stream_ptr)))
+
+
+def asd_host_grain_labels(params, system, n_stored):
+    """Grain labels built on the host (no device)."""
+    out = np.empty(n_stored, dtype=np.int32)
+    rc = lib().asd_host_grain_labels(C.byref(params), C.byref(system), _np_ptr(out))
+    if rc not in (ASD_OK, ASD_EUNSUPPORTED):
+        _check(rc)
+    return out
+
+
+def asd_host_neighbours(params, system):
+    """CSR neighbour table built on the host (no device)."""
+    n = C.c_int64()
+    _check(lib().asd_host_neighbours(C.byref(params), C.byref(system), C.byref(n), None, None, None))
+    per = 1 if params.lattice == ASD_SC else 2
+    sx = system.track_nx if system.bc_x == ASD_BC_TRACK else system.nx
+    ns = per * sx * system.ny * system.nz
+    row = np.empty(ns + 1, dtype=np.int64)
+    col = np.empty(max(n.value, 1), dtype=np.int32)
+    sh = np.empty(max(n.value, 1), dtype=np.int8)
+    _check(lib().asd_host_neighbours(C.byref(params), C.byref(system), C.byref(n), _np_ptr(row),
+                                     _np_ptr(col), _np_ptr(sh)))
+    return row, col[:n.value], sh[:n.value]
 
 
 def asd_set_variant(h, kernel, tile):

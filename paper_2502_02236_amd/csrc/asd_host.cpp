@@ -1058,6 +1058,49 @@ int asd_get_neighbours(asd_t *h, int32_t s, int64_t *row_ptr, int32_t *col, int8
     return ASD_OK;
 }
 
+int asd_host_grain_labels(const asd_params *p, const asd_system_desc *sys, int32_t *labels)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!sys || !labels) return fail(nullptr, ASD_EINVAL, "NULL argument");
+    if ((rc = check_system(p, sys, 0))) return rc;
+    HostSys hs;
+    rc = build_system(p, sys, 0, hs);
+    if (rc && rc != ASD_EUNSUPPORTED) return rc;
+    std::memcpy(labels, hs.labels.data(), hs.labels.size() * sizeof(int32_t));
+    return rc;
+}
+
+int asd_host_neighbours(const asd_params *p, const asd_system_desc *sys, int64_t *n_entries,
+                        int64_t *row_ptr, int32_t *col, int8_t *shell)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!sys || !n_entries) return fail(nullptr, ASD_EINVAL, "NULL argument");
+    if ((rc = check_system(p, sys, 0))) return rc;
+    HostSys hs;
+    hs.desc = *sys;
+    hs.desc.seeds_xy = nullptr;
+    hs.desc.labels = nullptr;
+    hs.sx = sys->bc_x == ASD_BC_TRACK ? sys->track_nx : sys->nx;
+    hs.n_stored = (p->lattice == ASD_SC ? 1 : 2) * (int64_t)hs.sx * sys->ny * sys->nz;
+    const int slots = n_neighbour_slots(p);
+    int64_t c = 0;
+    for (int64_t i = 0; i < hs.n_stored; ++i) {
+        if (row_ptr) row_ptr[i] = c;
+        for (int k = 0; k < slots; ++k) {
+            int64_t j = slot_neighbour(p, hs, i, k);
+            if (j < 0) continue;
+            if (col) col[c] = (int32_t)j;
+            if (shell) shell[c] = (int8_t)slot_shell(p, k);
+            ++c;
+        }
+    }
+    if (row_ptr) row_ptr[hs.n_stored] = c;
+    *n_entries = c;
+    return ASD_OK;
+}
+
 int asd_get_state(asd_t *h, int32_t s, int64_t *step, int32_t *origin)
 {
     if (!h || s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad argument");

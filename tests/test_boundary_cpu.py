@@ -86,3 +86,19 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "asd_oracle" not in text, f
+
+
+def test_fast_division_helper(tmp_path):
+    """The kernels' division by a precomputed multiplier equals integer division."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "fastdiv")
+    subprocess.run([hipcc, "-O2", "-I", os.path.join(ROOT, "paper_2502_02236_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "helpers", "fastdiv_check.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+    out = subprocess.run([exe], capture_output=True, text=True)
+    checked, bad = map(int, out.stdout.split())
+    assert out.returncode == 0 and bad == 0 and checked > 4_000_000
