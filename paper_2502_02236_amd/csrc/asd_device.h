@@ -62,6 +62,22 @@ __device__ __forceinline__ Words4 philox4x32(int rounds, uint32_t k0, uint32_t k
     return Words4{c0, c1, c2, c3};
 }
 
+// The step kernels run 10 rounds (the generator's standard count) or 7; the
+// first seven are shared, so there is one uniform branch and no loop.
+__device__ __forceinline__ Words4 philox4x32_7or10(int rounds, uint32_t k0, uint32_t k1,
+                                                   uint32_t c0, uint32_t c1, uint32_t c2,
+                                                   uint32_t c3)
+{
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 7; ++r) philox_round(k0 + r * W0, k1 + r * W1, c0, c1, c2, c3);
+    if (rounds != 7) {
+#pragma unroll
+        for (int r = 7; r < 10; ++r) philox_round(k0 + r * W0, k1 + r * W1, c0, c1, c2, c3);
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
 // Division by a run-time divisor d >= 1 for 32-bit unsigned dividends with a
 // precomputed multiplier (Granlund and Montgomery, PLDI 1994, Fig. 4.1):
 // l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,

@@ -557,6 +557,12 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
         d.n_window = hs.n_window;
         for (int64_t i = 0; i < hs.n_stored; ++i)
             lab[(size_t)(base + i)] = hs.labels[i] < 0 ? kNoGrain : (uint16_t)hs.labels[i];
+        d.columnar = 1;
+        {
+            const int64_t pn = (p->lattice == ASD_SC ? 1 : 2) * (int64_t)hs.sx * hs.desc.ny;
+            for (int64_t i = pn; i < hs.n_stored && d.columnar; ++i)
+                if (hs.labels[i] != hs.labels[i % pn]) d.columnar = 0;
+        }
         // grain site lists, ascending site index within each grain
         std::vector<int64_t> cnt(hs.n_grains + 1, 0);
         for (int64_t i = 0; i < hs.n_stored; ++i)
@@ -1132,8 +1138,18 @@ int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out
 // reason the fused kernel cannot serve this handle, or NULL
 static const char *fused_unsupported(const asd_t *h)
 {
-    for (const HostSys &hs : h->sys)
+    const int64_t elem = h->p.precision == ASD_FP64 ? 8 : 4;
+    for (const HostSys &hs : h->sys) {
         if (hs.desc.bc_z != ASD_BC_OPEN) return "the fused kernel marches z between open surfaces";
+        if (hs.n_stored * elem > 0x7FFFFFFF)
+            return "the fused kernel addresses a system with 32-bit byte offsets (2 GiB per component)";
+    }
+    bool per_grain = false;
+    for (const HostSys &hs : h->sys)
+        if (!hs.ku_grain.empty()) per_grain = true;
+    if (per_grain)
+        for (const SysDev &d : h->dev)
+            if (!d.columnar) return "per-grain anisotropy in the fused kernel needs grains that span whole z columns";
     return nullptr;
 }
 

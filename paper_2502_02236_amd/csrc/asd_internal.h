@@ -28,6 +28,7 @@ struct SysDev {
     int32_t ftile_base;       // first tile of this system (fused kernel)
     int32_t ftiles_x, ftiles_y, ftiles_z;
     int32_t fz_len;           // z planes per fused tile
+    int32_t columnar;         // 1 when every stored column lies in one grain
     uint32_t sys_id;          // Philox counter word 2
     FastDivH fd_nx, fd_ny;    // division by nx, ny (window)
     FastDivH fd_ftx, fd_fty;  // division by ftiles_x, ftiles_y
