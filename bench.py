@@ -13,9 +13,10 @@ each at its own temperature, moment statistics every 10 steps), track
 per-grain anisotropy spread and bit-timed write field).
 
 Prints one JSON line: spin-updates/s (magnetic sites x steps / s) with the
-roofline of the dominant kernel (algorithmic bytes per launch / its average
-duration from HIP events on the handle's stream) and the FP64 CPU oracle
-timed on a bounded sample.
+roofline of the dominant kernel (algorithmic VALU work or bytes per launch /
+its average duration from HIP events on the handle's stream; the FP32 path is
+bound by VALU issue and reports the HBM fraction beside it) and the FP64 CPU
+oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -31,6 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one non-packed FP32
+# or INT32 operation per lane per cycle (quarter-rate transcendentals take 4)
+VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 
 
 def parse():
@@ -62,6 +66,19 @@ def bytes_per_site(precision: str, workload: str, kernel_name: str) -> int:
     if workload == "l10" and not kernel_name.startswith("k_fused"):
         b += 4 * 18
     return b
+
+
+def alu_cycles_per_site(precision: str, workload: str):
+    """Algorithmic VALU lane-cycles per magnetic site and Heun step of the FP32
+    path (nothing recomputed, no halo): Philox4x32-10 40 (20 64-bit products, 20
+    three-way xors), uniforms 8, Box-Muller radii 6 and angles 3, scaling 3;
+    per stage exchange 18 (SC) or 54 (L1_0, four shells), field assembly 4 (+3
+    once), LL right-hand side 18; predictor update 10, corrector update 13.
+    166 operations of which 9 transcendental (4 cycles each): 193 for SC, 265
+    for L1_0.  None for FP64 (software transcendentals; reported against HBM)."""
+    if precision != "fp32":
+        return None
+    return 265 if workload == "l10" else 193
 
 
 def kernel_sources_hash():
@@ -259,6 +276,24 @@ def main():
     launch_s = r["t"] / r["steps"]
     achieved = alg_bytes / launch_s / 1e9
     traffic, traffic_src = measured_traffic(r["kname"], args.workload, args.precision)
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
+           "algorithmic_bytes_per_launch": alg_bytes}
+    cyc = alu_cycles_per_site(args.precision, args.workload)
+    if cyc is not None:
+        # the kernel is bound by VALU issue, not by HBM: report that roofline,
+        # with the HBM fraction beside it
+        alu_ach = cyc * r["n_mag"] / launch_s / 1e12
+        roof = {"bound": "alu", "achieved": alu_ach, "peak": VALU_PEAK_T,
+                "unit": "T VALU lane-cycles/s", "frac": alu_ach / VALU_PEAK_T,
+                "alu_cycles_per_magnetic_site": cyc, "hbm": hbm}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
+                "algorithmic_bytes_per_launch": alg_bytes}
+    roof.update({"traffic": traffic, "traffic_source": traffic_src, "kernel": r["kname"],
+                 "launch_us_mean": 1e6 * launch_s,
+                 "launch_us_eager_events_median": 1e6 * r["step_med"]})
     out = {
         "metric": "atomistic spin-updates/s (spins x Heun steps)",
         "value": value,
@@ -277,13 +312,8 @@ def main():
                    "magnetic_sites": r["n_mag"], "dt_fs": 1.0, "precision": args.precision,
                    "kernel": {1: "plain", 2: "fused"}.get(r["kernel"], "?"), "tile": r["tile"],
                    "graph_steps": args.graph_steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": r["kname"], "bytes_per_site": bps,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "launch_us_mean": 1e6 * launch_s,
-                     "launch_us_eager_events_median": 1e6 * r["step_med"],
-                     "traffic_source": traffic_src},
+        "roofline": roof,
+        "lattice_site_updates_per_s": r["n_sites"] * r["steps"] / r["t"],
         "max_norm_error": r["norm_err"],
     }
     if not args.no_fp64_compare and args.precision == "fp32" and args.workload == "slab":

@@ -1233,8 +1233,15 @@ static std::string tune_key(const asd_t *h)
     int64_t sites = 0;
     for (const HostSys &hs : h->sys) sites += hs.n_window;
     const asd_system_desc &d = h->sys[0].desc;
-    snprintf(buf, sizeof buf, "lat%d_prec%d_%dx%dx%d_n%zu_w%lld", h->p.lattice, h->p.precision, d.nx,
-             d.ny, d.nz, h->sys.size(), (long long)sites);
+    // the variant table is part of the key: an entry names a variant by index
+    const bool l10 = h->p.lattice == ASD_L10, fp64 = h->p.precision == ASD_FP64;
+    uint32_t tab = 2166136261u;  // FNV-1a over (txe, waves, rows, lz) of every variant
+    for (int v = 0; v < fused_count(l10, fp64); ++v) {
+        const FusedVariant f = fused_pick(l10, fp64, v);
+        for (int x : {f.txe, f.waves, f.rows, f.lz}) tab = (tab ^ (uint32_t)x) * 16777619u;
+    }
+    snprintf(buf, sizeof buf, "lat%d_prec%d_%dx%dx%d_n%zu_w%lld_t%08x", h->p.lattice, h->p.precision,
+             d.nx, d.ny, d.nz, h->sys.size(), (long long)sites, tab);
     return buf;
 }
 

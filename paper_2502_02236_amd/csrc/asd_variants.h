@@ -15,17 +15,20 @@ struct FusedVariant {
     int txe, waves, rows, lz;
 };
 
-inline int fused_variant_count(bool fp64) { return fp64 ? 6 : 14; }
+inline int fused_variant_count(bool fp64) { return fp64 ? 7 : 13; }
 
+// Variant 0 is the default before any tuning (narrow tiles, z-chunks of 11:
+// enough workgroups for ~1M-site lattices); the others cover wider tiles for
+// large batches and the R = 2 and 16-lane shapes.
 inline FusedVariant fused_variant(bool fp64, int v)
 {
-    static const FusedVariant f32v[14] = {
-        {64, 8, 4, 0},  {64, 4, 2, 0},  {32, 4, 2, 11}, {32, 4, 2, 0},
-        {32, 8, 2, 8},  {16, 4, 2, 11}, {64, 4, 4, 0},  {32, 4, 1, 11},
-        {32, 8, 1, 11}, {32, 4, 1, 17}, {32, 8, 1, 17}, {32, 8, 1, 0},
-        {64, 8, 2, 0},  {64, 8, 2, 17}};
-    static const FusedVariant f64v[6] = {{64, 4, 2, 0},  {32, 4, 2, 11}, {32, 4, 1, 0},
-                                         {32, 8, 1, 11}, {32, 4, 1, 11}, {32, 8, 1, 17}};
+    static const FusedVariant f32v[13] = {
+        {32, 4, 1, 11}, {64, 4, 2, 0},  {16, 4, 2, 11}, {32, 8, 1, 11}, {32, 4, 1, 17},
+        {32, 8, 1, 17}, {32, 8, 1, 0},  {32, 4, 2, 11}, {64, 8, 2, 17}, {16, 4, 1, 11},
+        {16, 8, 1, 11}, {16, 8, 1, 0},  {32, 8, 2, 8}};
+    static const FusedVariant f64v[7] = {{32, 4, 1, 11}, {64, 4, 2, 0},  {32, 8, 1, 17},
+                                         {32, 4, 1, 0},  {32, 8, 1, 11}, {16, 4, 1, 11},
+                                         {32, 4, 2, 11}};
     const int n = fused_variant_count(fp64);
     if (v < 0 || v >= n) v = 0;
     return fp64 ? f64v[v] : f32v[v];
