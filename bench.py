@@ -84,22 +84,23 @@ def alu_cycles_per_site(precision: str, workload: str):
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("asd_device.h", "asd_step.inc", "asd_fused.inc", "asd_variants.h", "asd_internal.h"):
+    for f in ("asd_device.h", "asd_step.inc", "asd_fused.inc", "asd_fused_l10.inc", "asd_variants.h",
+              "asd_internal.h"):
         with open(os.path.join(ROOT, "paper_2502_02236_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name, workload, precision):
+def measured_traffic(kernel_name, workload, precision, tile):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary, if it was
-    taken on this kernel, workload and precision with the current kernel sources."""
+    taken on this kernel variant, workload and precision with the current kernel sources."""
     import glob
     for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
         with open(path) as f:
             t = json.load(f)
         if (t.get("kernel", "").split("(")[0].replace("void asd::", "") == kernel_name
                 and t.get("workload") == workload and t.get("precision") == precision
-                and t.get("source_hash") == kernel_sources_hash()):
+                and t.get("tile") == tile and t.get("source_hash") == kernel_sources_hash()):
             return t["traffic_bytes"], os.path.basename(path)
     return None, None
 
@@ -212,6 +213,7 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps):
         h.set_variant(A.ASD_KERNEL_PLAIN, args.tile)
     kernel_used, tile_used = h.variant()
     kname = h.variant_name()
+    h.prepare()  # capture the step graphs before the warm-up (untimed)
     run_steps(h, warmup, extra, 0)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -275,7 +277,7 @@ def main():
     # back to back on the handle's stream; includes the gaps between them)
     launch_s = r["t"] / r["steps"]
     achieved = alg_bytes / launch_s / 1e9
-    traffic, traffic_src = measured_traffic(r["kname"], args.workload, args.precision)
+    traffic, traffic_src = measured_traffic(r["kname"], args.workload, args.precision, r["tile"])
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
            "algorithmic_bytes_per_launch": alg_bytes}

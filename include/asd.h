@@ -178,6 +178,12 @@ int asd_get_spins(asd_t *h, int32_t sys, void *dst, int32_t on_device);
  * the same thermal field, write field and temperature.  Asynchronous. */
 int asd_step(asd_t *h, int64_t n);
 
+/* Capture the step graphs now (one per ping-pong parity) when graph_steps >
+ * 0, so the next graph segment of asd_step does not pay for capture and
+ * instantiation.  Enqueues nothing.  Changing the drive or the kernel
+ * variant drops the graphs again; asd_step then captures them on use. */
+int asd_prepare(asd_t *h);
+
 /* Move the window of every track system by `columns` >= 0 along +x: the
  * leaving columns freeze with their current spins, the entering ones are
  * taken from the track (Sec. II window shift).  ASD_ESTATE if a window

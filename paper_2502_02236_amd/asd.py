@@ -25,7 +25,7 @@ ASD_KERNEL_AUTO, ASD_KERNEL_PLAIN, ASD_KERNEL_FUSED = 0, 1, 2
 
 SYMBOLS = [
     "asd_workspace_bytes", "asd_create", "asd_destroy", "asd_set_field_temperature",
-    "asd_set_spins", "asd_get_spins", "asd_step", "asd_shift_window",
+    "asd_set_spins", "asd_get_spins", "asd_step", "asd_prepare", "asd_shift_window",
     "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
     "asd_neighbour_count", "asd_get_neighbours", "asd_host_grain_labels", "asd_host_neighbours",
@@ -85,6 +85,7 @@ def lib():
         L.asd_set_spins.argtypes = [h, C.c_int32, vp, C.c_int32]
         L.asd_get_spins.argtypes = [h, C.c_int32, vp, C.c_int32]
         L.asd_step.argtypes = [h, C.c_int64]
+        L.asd_prepare.argtypes = [h]
         L.asd_shift_window.argtypes = [h, C.c_int32]
         L.asd_reduce_magnetization.argtypes = [h, vp, vp]
         L.asd_reduce_energy.argtypes = [h, vp]
@@ -157,6 +158,11 @@ def asd_get_spins(h, sys, ptr, on_device):
 
 def asd_step(h, n):
     _check(lib().asd_step(h, int(n)), h)
+
+
+def asd_prepare(h):
+    """Capture the step graphs now (no work is enqueued)."""
+    _check(lib().asd_prepare(h), h)
 
 
 def asd_shift_window(h, columns):
@@ -284,6 +290,9 @@ class Handle:
 
     def step(self, n: int):
         asd_step(self.h, n)
+
+    def prepare(self):
+        asd_prepare(self.h)
 
     def shift_window(self, columns: int):
         asd_shift_window(self.h, columns)

@@ -877,6 +877,19 @@ int asd_step(asd_t *h, int64_t n)
     return ASD_OK;
 }
 
+int asd_prepare(asd_t *h)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (h->graph_steps <= 0) return ASD_OK;
+    if (h->graph_kernel != h->kernel || h->graph_tile != h->tile_cfg) drop_graphs(h);
+    for (int c = 0; c < 2; ++c)
+        if (!h->graph[c]) {
+            int rc = capture_graph(h, c);
+            if (rc) return rc;
+        }
+    return ASD_OK;
+}
+
 int asd_shift_window(asd_t *h, int32_t columns)
 {
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
@@ -1349,16 +1362,36 @@ int asd_autotune(asd_t *h, const char *cache_path)
     if (!fused_unsupported(h))
         for (int v = 0; v < fused_count(h->p.lattice == ASD_L10, h->p.precision == ASD_FP64); ++v)
             cands.push_back({ASD_KERNEL_FUSED, v});
+    // pass 1: every candidate for 20 steps; pass 2: the three fastest, three
+    // interleaved rounds of 60 steps each, ranked by their median
     double best = 1e30;
     Cand pick = cands[0];
     int rc = ASD_OK;
-    for (const Cand &c : cands) {
-        if ((rc = asd_set_variant(h, c.kernel, c.tile))) break;
+    std::vector<std::pair<double, size_t>> first;
+    for (size_t i = 0; i < cands.size() && !rc; ++i) {
         double ms = 0;
+        if ((rc = asd_set_variant(h, cands[i].kernel, cands[i].tile))) break;
         if ((rc = time_variant(h, 20, &ms))) break;
-        if (ms < best) {
-            best = ms;
-            pick = c;
+        first.push_back({ms, i});
+    }
+    std::sort(first.begin(), first.end());
+    const size_t nf = std::min<size_t>(3, first.size());
+    std::vector<std::vector<double>> rounds(nf);
+    for (int rd = 0; rd < 3 && !rc; ++rd)
+        for (size_t j = 0; j < nf && !rc; ++j) {
+            double ms = 0;
+            const Cand &c = cands[first[j].second];
+            if ((rc = asd_set_variant(h, c.kernel, c.tile))) break;
+            if ((rc = time_variant(h, 60, &ms))) break;
+            rounds[j].push_back(ms);
+        }
+    for (size_t j = 0; j < nf && !rc; ++j) {
+        std::vector<double> v = rounds[j];
+        std::sort(v.begin(), v.end());
+        const double med = v[v.size() / 2];
+        if (med < best) {
+            best = med;
+            pick = cands[first[j].second];
         }
     }
     h->graph_steps = gsteps;

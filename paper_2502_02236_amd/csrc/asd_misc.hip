@@ -125,16 +125,22 @@ int launch_mask_spins(int prec, void *buf, int64_t ncs, const uint16_t *label, c
 // One block per grain walks the grain's site list (ascending site index),
 // keeps the sites inside the window, accumulates in FP64 per thread, and
 // reduces the block in a fixed tree order: deterministic, no atomics.
-constexpr int kRedBlock = 256;
+constexpr int kRedBlock = 1024;
+constexpr int kRedUnroll = 4;  // sites per thread and pass (independent loads)
 
-__device__ __forceinline__ bool site_in_window(const SysDev &d, int org, int64_t local)
+__device__ __forceinline__ bool site_in_window(const SysDev &d, int org, int32_t local)
 {
     if (!d.track) return true;
-    int64_t cell = d.kind == ASD_SC ? local : (local >> 1);
-    int32_t X = (int32_t)(cell % d.sx);
+    const uint32_t cell = d.kind == ASD_SC ? (uint32_t)local : ((uint32_t)local >> 1);
+    const int32_t X = (int32_t)(cell % (uint32_t)d.sx);
     return X >= org && X < org + d.nx;
 }
 
+// One workgroup per grain.  Each pass covers kRedUnroll * kRedBlock sites of
+// the grain's list: thread t takes sites t, t + kRedBlock, ... (coalesced),
+// loads them all, then adds them in that order; the workgroup then sums its
+// threads in a fixed tree.  The order depends only on the site list, so the
+// FP64 result is the same in every run.
 template <typename T>
 __global__ __launch_bounds__(kRedBlock) void k_reduce_grains(RedArgs a)
 {
@@ -143,15 +149,34 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_grains(RedArgs a)
     const SysDev d = a.sys[s];
     const int org = d.track ? a.origin[s] : 0;
     const T *S = (const T *)a.S;
+    const int64_t k0 = a.grain_ptr[g], k1 = a.grain_ptr[g + 1];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t k = a.grain_ptr[g] + threadIdx.x; k < a.grain_ptr[g + 1]; k += kRedBlock) {
-        int64_t local = a.grain_sites[k];
-        if (!site_in_window(d, org, local)) continue;
-        int64_t i = d.base + local;
-        acc[0] += (double)S[i];
-        acc[1] += (double)S[a.ncs + i];
-        acc[2] += (double)S[2 * a.ncs + i];
-        acc[3] += 1.0;
+    for (int64_t base = k0; base < k1; base += (int64_t)kRedUnroll * kRedBlock) {
+        int32_t loc[kRedUnroll];
+        bool ok[kRedUnroll];
+#pragma unroll
+        for (int j = 0; j < kRedUnroll; ++j) {
+            const int64_t k = base + threadIdx.x + (int64_t)j * kRedBlock;
+            ok[j] = k < k1;
+            loc[j] = ok[j] ? a.grain_sites[k] : 0;
+        }
+        T v[kRedUnroll][3];
+#pragma unroll
+        for (int j = 0; j < kRedUnroll; ++j) {
+            ok[j] = ok[j] && site_in_window(d, org, loc[j]);
+            const int64_t i = d.base + loc[j];
+            v[j][0] = ok[j] ? S[i] : T(0);
+            v[j][1] = ok[j] ? S[a.ncs + i] : T(0);
+            v[j][2] = ok[j] ? S[2 * a.ncs + i] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kRedUnroll; ++j)
+            if (ok[j]) {
+                acc[0] += (double)v[j][0];
+                acc[1] += (double)v[j][1];
+                acc[2] += (double)v[j][2];
+                acc[3] += 1.0;
+            }
     }
     __shared__ double red[4][kRedBlock];
     for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];

@@ -256,6 +256,15 @@ def test_graph_capture_equals_eager_and_resume_is_exact(kernel):
         # run-to-run determinism
         h5, _, _ = run_gpu(w, precision, 100, S0=S0, kernel=kernel, tile=tile)
         np.testing.assert_array_equal(h5.get_spins(), a)
+        # graphs captured up front; odd eager runs switch between the two
+        # buffer parities, so both captured graphs are replayed
+        h6 = bridge.make_handle(w, precision, graph_steps=10)
+        h6.set_variant(kernel, tile)
+        h6.prepare()
+        h6.set_spins(S0)
+        for n in (3, 20, 7, 70):
+            h6.step(n)
+        np.testing.assert_array_equal(h6.get_spins(), a)
     say("graph/resume/determinism ok")
 
 
