@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+import golden
 import oracle
 import workloads as W
 from oracle_build import oracle_labels, oracle_system, window_mask
@@ -115,6 +116,14 @@ def test_philox_export_bit_exact(gpu):
         got = dev_out.cpu().numpy().view(np.uint32)
         ref = oracle.philox(ctr, seed, rounds=rounds)
         np.testing.assert_array_equal(got, ref)
+    # the generator's published known-answer vectors
+    kc, kseeds, kout = golden.philox_kat()
+    for c, sd, o in zip(kc, kseeds, kout):
+        d_in = torch.from_numpy(c[None, :].view(np.int32).copy()).cuda()
+        d_out = torch.empty_like(d_in)
+        A.asd_philox(sd, 10, d_in.data_ptr(), d_out.data_ptr(), 1, 0)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(d_out.cpu().numpy().view(np.uint32)[0], o)
     say("philox ok")
 
 

@@ -17,6 +17,7 @@ import pytest
 from scipy import integrate
 from scipy.spatial import cKDTree
 
+import golden
 import oracle
 import workloads as W
 from oracle_build import free_spins_system, oracle_labels, oracle_system
@@ -53,6 +54,13 @@ def test_philox_matches_rocrand_engine(rocrand_ref):
         ref = rocrand_ref([seed] * len(ctr), ctr)
         got = oracle.philox(ctr, seed, rounds=10)
         np.testing.assert_array_equal(got, ref)
+
+
+def test_philox_known_answers():
+    """The generator's published known-answer vectors (tests/golden)."""
+    ctr, seeds, out = golden.philox_kat()
+    for c, sd, o in zip(ctr, seeds, out):
+        np.testing.assert_array_equal(oracle.philox(c[None, :], sd, rounds=10)[0], o)
 
 
 def test_philox_statistics():
@@ -436,10 +444,13 @@ def test_heisenberg_chain_nearest_neighbour_correlation():
 
 
 def test_eq8_exchange_from_curie_temperature():
-    """Eq. 8 worked numbers (Sec. III): J = 3 kB T_C / (eps z)."""
-    Tc = 710.0
-    assert abs(3 * W.KB * Tc / (0.72 * 6) / 6.8e-21 - 1) < 2e-3
-    assert abs(3 * W.KB * Tc / (0.78 * 10) / 3.77e-21 - 1) < 1e-3
+    """Eq. 8 with the numbers the paper prints (Sec. III, tests/golden): the
+    workloads' Boltzmann constant reproduces J_SC and J_L10 to their printed
+    precision."""
+    rows = golden.eq8_rows()
+    assert [r[0] for r in rows] == ["SC", "L10"]
+    for _, Tc, eps, z, J in rows:
+        assert abs(3 * W.KB * Tc / (eps * z) / J - 1) < 2e-3
 
 
 def test_noise_depends_on_absolute_site_step_and_system():
