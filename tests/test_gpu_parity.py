@@ -159,6 +159,7 @@ CASES = [
     ("c2_crop_plusB", c2_crop(B=(0.0, 0.0, 0.8), seed=12), (), False),
     ("c2_crop_tall", c2_crop(nz=25, seed=13), (), False),
     ("c3_crop", c3_crop(), (), False),
+    ("c3_crop_ku", c3_crop(seed=17, ku_spread=0.05), (), True),
     ("c5_crop_shift", c5_crop(), ((40, 2), (70, 1)), True),
 ]
 
@@ -211,6 +212,39 @@ def test_reductions_match_oracle(precision):
     assert rel(pg, opg) < 1e-12
     assert rel(ps[0], ots) < 1e-12
     assert np.max(np.abs(E - oE) / np.abs(oE[3])) < 1e-12
+
+
+@pytest.mark.parametrize("lattice", ["sc", "l10"])
+def test_layered_grains_with_per_grain_anisotropy_run_two_pass(lattice):
+    """Grains stacked along z (labels vary within a column) with per-grain k_u:
+    the fused kernels look the anisotropy up once per column, so the handle
+    refuses them and AUTO runs the two-pass kernels, bit-identical to the
+    oracle in FP64."""
+    base = W.c1_plain_sc() if lattice == "sc" else c3_crop()
+    w = base.scaled(nx=12, ny=10, nz=7, bc=(W.BC_PERIODIC, W.BC_PERIODIC, W.BC_OPEN), grains=False,
+                    seed=21)
+    per = 1 if lattice == "sc" else 2
+    lab = np.zeros((w.nz, per * w.ny * w.nx), dtype=np.int32)
+    lab[3:] = 1
+    lab[3] = -1  # a non-magnetic layer separates the two grains
+    lab = lab.reshape(-1)
+    ku = W.grain_ku(2, w.ku, 0.05, w.seed)
+    say("layered grains", lattice)
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        si = bridge.SystemInputs(w, labels=lab, ku_grain=ku)
+        h = A.Handle(bridge.params_for(w, precision, kernel=A.ASD_KERNEL_AUTO), [si.desc])
+        dr, _ = bridge.drive_for(w)
+        h.set_drive(dr)
+        assert h.variant()[0] == A.ASD_KERNEL_PLAIN
+        with pytest.raises(A.AsdError):
+            h.set_variant(A.ASD_KERNEL_FUSED, 0)
+        S0 = initial_state(w, lab)
+        h.set_spins(S0)
+        h.step(60)
+        _, So = run_oracle(w, lab, S0, 60, ku=ku)
+        err = maxdiff(h.get_spins(), So)
+        assert err <= TOL[precision], err
+        h.close()
 
 
 def test_batched_uneven_systems_match_single_runs():
