@@ -102,3 +102,23 @@ def test_fast_division_helper(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True)
     checked, bad = map(int, out.stdout.split())
     assert out.returncode == 0 and bad == 0 and checked > 4_000_000
+
+
+def test_plain_c_client_compiles_and_links(tmp_path):
+    """include/asd.h is a C header: a C11 client compiles with gcc and links
+    against the library (it is run against the GPU in the parity tests)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("gcc or the HIP headers are not available")
+    pkg = os.path.join(ROOT, "paper_2502_02236_amd")
+    exe = str(tmp_path / "abi_c_client")
+    r = subprocess.run([gcc, "-O1", "-std=c11", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                        "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
+                        os.path.join(ROOT, "tests", "helpers", "abi_c_client.c"), "-o", exe,
+                        "-L", pkg, "-lasd", "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath," + pkg],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    u = subprocess.run([exe], capture_output=True, text=True)
+    assert u.returncode == 2 and "usage" in u.stderr

@@ -247,6 +247,44 @@ def test_layered_grains_with_per_grain_anisotropy_run_two_pass(lattice):
         h.close()
 
 
+def test_plain_c_client_matches_oracle(tmp_path):
+    """A C program (no Python, no torch) owns the workspace and the stream,
+    builds the 16x16x8 lattice, captures graphs and steps 100 times: FP64
+    spins are bit-identical to the oracle, the FP64 magnetisation agrees."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    pkg = os.path.join(root, "paper_2502_02236_amd")
+    exe = str(tmp_path / "abi_c_client")
+    subprocess.run([gcc, "-O1", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    "-I", os.path.join(root, "include"), os.path.join(here, "helpers", "abi_c_client.c"),
+                    "-o", exe, "-L", pkg, "-lasd", "-L/opt/rocm/lib", "-lamdhip64",
+                    "-Wl,-rpath," + pkg], check=True, capture_output=True)
+    w = W.c1_plain_sc()
+    steps = 100
+    out = str(tmp_path / "spins.bin")
+    args = [w.nx, w.ny, w.nz, w.a, w.J[0], w.mu_s, w.alpha, w.gamma, w.dt, w.ku, w.B[2], w.T_amb,
+            w.seed, steps, out]
+    r = subprocess.run([exe] + [repr(a) if isinstance(a, float) else str(a) for a in args],
+                       capture_output=True, text=True, timeout=120)
+    say(r.stdout.strip(), r.stderr.strip())
+    assert r.returncode == 0
+    n = w.n_sites
+    data = np.fromfile(out, dtype=np.float64)
+    Sg, M = data[:3 * n].reshape(3, n), data[3 * n:]
+    lab = np.zeros(n, dtype=np.int32)
+    S0 = np.zeros((3, n))
+    S0[2] = 1.0
+    sysm, So = run_oracle(w, lab, S0, steps)
+    assert maxdiff(Sg, So) <= TOL[A.ASD_FP64]
+    _, tot = sysm.magnetisation(So, 1)
+    assert np.max(np.abs(M - np.asarray(tot).reshape(-1)[:4]) / np.maximum(np.abs(M), 1.0)) < 1e-12
+
+
 def test_batched_uneven_systems_match_single_runs():
     """Uneven isolated grains, each at its own temperature, in one launch: system k
     equals the oracle run with system id k."""
