@@ -191,6 +191,40 @@ def test_trajectory_parity(name, w, shifts, ku_spread, precision, kernel, tile):
         1e-15 if precision == A.ASD_FP64 else 1e-6)
 
 
+EDGE_CASES = [
+    ("sc_monolayer", W.c1_plain_sc().scaled(nz=1, seed=31)),
+    ("sc_bilayer", W.c1_plain_sc().scaled(nz=2, seed=32)),
+    ("sc_3x3_periodic", W.c1_plain_sc().scaled(nx=3, ny=3, nz=4, seed=33)),
+    ("sc_open_ragged", W.c1_plain_sc().scaled(nx=37, ny=5, nz=3, bc=(0, 0, 0), seed=34)),
+    ("l10_monolayer", c3_crop(nz=1, seed=35)),
+    ("l10_3x3_periodic", c3_crop(nx=3, ny=3, nz=2, grains=False, bc=(W.BC_PERIODIC,) * 2 + (W.BC_OPEN,),
+                                 seed=36)),
+]
+
+
+@pytest.mark.parametrize("name,w", EDGE_CASES)
+def test_degenerate_lattices(name, w):
+    """Monolayers and bilayers (the march has one or two planes), lattices
+    narrower than a tile (the periodic image wraps several times across one
+    tile) and open ragged boxes: every fused variant agrees with the oracle."""
+    steps = 40
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        n_var = None
+        tile = 0
+        while True:
+            say("edge", name, precision, tile)
+            h, lab, S0 = run_gpu(w, precision, steps, kernel=A.ASD_KERNEL_FUSED, tile=tile)
+            if n_var is None:
+                n_var = h.variant_count(A.ASD_KERNEL_FUSED)
+                _, So = run_oracle(w, lab, S0, steps)
+            err = maxdiff(h.get_spins(), So)
+            h.close()
+            assert err <= TOL[precision], (tile, err)
+            tile += 1
+            if tile >= n_var:
+                break
+
+
 @pytest.mark.parametrize("precision", [A.ASD_FP64, A.ASD_FP32])
 def test_reductions_match_oracle(precision):
     w = c5_crop()
