@@ -281,6 +281,40 @@ def test_layered_grains_with_per_grain_anisotropy_run_two_pass(lattice):
         h.close()
 
 
+def test_error_paths_leave_the_handle_usable():
+    """Invalid calls fail with their codes before anything is enqueued and
+    leave the handle's state as it was: afterwards the handle still steps
+    exactly like a fresh one."""
+    w = c5_crop()
+    h, lab, S0 = run_gpu(w, A.ASD_FP32, 0, kernel=A.ASD_KERNEL_FUSED, tile=0)
+
+    def code(fn, *args):
+        with pytest.raises(A.AsdError) as e:
+            fn(*args)
+        return e.value.code
+
+    assert code(h.step, -1) == A.ASD_EINVAL
+    assert code(h.shift_window, -1) == A.ASD_EINVAL
+    assert code(h.shift_window, w.track_nx - w.nx + 1) == A.ASD_ESTATE
+    assert h.state() == (0, 0)
+    assert code(h.set_step, 1 << 32) == A.ASD_EINVAL
+    h.set_step((1 << 32) - 5)
+    assert code(h.step, 10) == A.ASD_ESTATE
+    assert h.state()[0] == (1 << 32) - 5
+    assert code(h.set_spins, S0, 1) == A.ASD_EINVAL
+    assert code(h.set_variant, A.ASD_KERNEL_FUSED, 999) == A.ASD_EINVAL
+    dr, _ = bridge.drive_for(w)
+    dr.B[2] = float("nan")
+    assert code(h.set_drive, dr) == A.ASD_EINVAL
+    h.set_step(0)
+    h.set_spins(S0)
+    h.step(20)
+    h2, _, _ = run_gpu(w, A.ASD_FP32, 20, kernel=A.ASD_KERNEL_FUSED, tile=0, S0=S0)
+    np.testing.assert_array_equal(h.get_spins(), h2.get_spins())
+    h.close()
+    h2.close()
+
+
 def test_plain_c_client_matches_oracle(tmp_path):
     """A C program (no Python, no torch) owns the workspace and the stream,
     builds the 16x16x8 lattice, captures graphs and steps 100 times: FP64
