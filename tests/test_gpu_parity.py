@@ -160,6 +160,8 @@ CASES = [
     ("c2_crop_tall", c2_crop(nz=25, seed=13), (), False),
     ("c3_crop", c3_crop(), (), False),
     ("c3_crop_ku", c3_crop(seed=17, ku_spread=0.05), (), True),
+    ("c1_periodic_z", W.c1_plain_sc().scaled(bc=(W.BC_PERIODIC,) * 3, seed=41), (), False),
+    ("c2_crop_tall_periodic_z", c2_crop(nz=25, bc=(W.BC_PERIODIC,) * 3, seed=42), (), False),
     ("c5_crop_shift", c5_crop(), ((40, 2), (70, 1)), True),
 ]
 
@@ -195,6 +197,7 @@ EDGE_CASES = [
     ("sc_monolayer", W.c1_plain_sc().scaled(nz=1, seed=31)),
     ("sc_bilayer", W.c1_plain_sc().scaled(nz=2, seed=32)),
     ("sc_3x3_periodic", W.c1_plain_sc().scaled(nx=3, ny=3, nz=4, seed=33)),
+    ("sc_periodic_z_3", W.c1_plain_sc().scaled(nz=3, bc=(W.BC_PERIODIC,) * 3, seed=37)),
     ("sc_open_ragged", W.c1_plain_sc().scaled(nx=37, ny=5, nz=3, bc=(0, 0, 0), seed=34)),
     ("l10_monolayer", c3_crop(nz=1, seed=35)),
     ("l10_3x3_periodic", c3_crop(nx=3, ny=3, nz=2, grains=False, bc=(W.BC_PERIODIC,) * 2 + (W.BC_OPEN,),
