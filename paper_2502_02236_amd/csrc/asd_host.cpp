@@ -1153,8 +1153,8 @@ static const char *fused_unsupported(const asd_t *h)
 {
     const int64_t elem = h->p.precision == ASD_FP64 ? 8 : 4;
     for (const HostSys &hs : h->sys) {
-        if (hs.desc.bc_z != ASD_BC_OPEN && (h->p.lattice != ASD_SC || hs.desc.bc_z != ASD_BC_PERIODIC))
-            return "the fused L1_0 kernel marches z between open surfaces";
+        if (hs.desc.bc_z != ASD_BC_OPEN && hs.desc.bc_z != ASD_BC_PERIODIC)
+            return "the fused kernels march z with open or periodic ends";
         if (hs.n_stored * elem > 0x7FFFFFFF)
             return "the fused kernel addresses a system with 32-bit byte offsets (2 GiB per component)";
     }

@@ -162,6 +162,7 @@ CASES = [
     ("c3_crop_ku", c3_crop(seed=17, ku_spread=0.05), (), True),
     ("c1_periodic_z", W.c1_plain_sc().scaled(bc=(W.BC_PERIODIC,) * 3, seed=41), (), False),
     ("c2_crop_tall_periodic_z", c2_crop(nz=25, bc=(W.BC_PERIODIC,) * 3, seed=42), (), False),
+    ("c3_crop_tall_periodic_z", c3_crop(nz=21, bc=(W.BC_PERIODIC,) * 3, seed=43), (), False),
     ("c5_crop_shift", c5_crop(), ((40, 2), (70, 1)), True),
 ]
 
@@ -200,6 +201,7 @@ EDGE_CASES = [
     ("sc_periodic_z_3", W.c1_plain_sc().scaled(nz=3, bc=(W.BC_PERIODIC,) * 3, seed=37)),
     ("sc_open_ragged", W.c1_plain_sc().scaled(nx=37, ny=5, nz=3, bc=(0, 0, 0), seed=34)),
     ("l10_monolayer", c3_crop(nz=1, seed=35)),
+    ("l10_periodic_z_3", c3_crop(nz=3, bc=(W.BC_PERIODIC,) * 3, seed=38)),
     ("l10_3x3_periodic", c3_crop(nx=3, ny=3, nz=2, grains=False, bc=(W.BC_PERIODIC,) * 2 + (W.BC_OPEN,),
                                  seed=36)),
 ]
