@@ -78,7 +78,8 @@ extern "C" {
 
 #define ASD_KERNEL_AUTO 0  /* fused kernel where available, else two-pass */
 #define ASD_KERNEL_PLAIN 1 /* two-pass: predictor kernel, corrector kernel */
-#define ASD_KERNEL_FUSED 2 /* one kernel per step, LDS tiles with recomputed halo */
+#define ASD_KERNEL_FUSED 2 /* one kernel per step, LDS tiles with recomputed halo
+                              (open or periodic z; see asd_set_variant) */
 
 typedef struct asd_t asd_t; /* opaque handle */
 
@@ -242,9 +243,18 @@ int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out
  * unchanged).  cache_path: JSON file read if it holds an entry for this
  * shape, written otherwise (NULL: no cache). */
 int asd_autotune(asd_t *h, const char *cache_path);
-/* Force a variant: kernel ASD_KERNEL_*, tile index (0 = default). */
+/* Force a variant: kernel ASD_KERNEL_PLAIN or ASD_KERNEL_FUSED, tile index
+ * 0 .. asd_variant_count - 1 (0 = default), else ASD_EINVAL.  The fused
+ * kernels return ASD_EUNSUPPORTED (the handle keeps its variant) for a
+ * system whose spins exceed 2 GiB per component, or when the anisotropy
+ * varies per grain and some stored column crosses grains (labels varying
+ * along z); the two-pass kernels take every system.  Drops captured graphs. */
 int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile);
 int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile);
+/* Number of tile variants of a kernel family for this handle's lattice and
+ * precision (the fused count is returned even where the fused kernels
+ * cannot serve the handle). */
+int asd_variant_count(asd_t *h, int32_t kernel, int32_t *count);
 /* Name of the step kernel(s) the current variant launches (as profilers list
  * them), NUL-terminated into buf[len]; ASD_EINVAL if it does not fit. */
 int asd_variant_name(asd_t *h, char *buf, size_t len);

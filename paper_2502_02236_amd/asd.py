@@ -30,7 +30,8 @@ SYMBOLS = [
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
     "asd_neighbour_count", "asd_get_neighbours", "asd_host_grain_labels", "asd_host_neighbours",
     "asd_get_state", "asd_set_step", "asd_philox",
-    "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_name", "asd_strerror",
+    "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_count", "asd_variant_name",
+    "asd_strerror",
     "asd_last_error",
 ]
 
@@ -104,6 +105,7 @@ def lib():
         L.asd_autotune.argtypes = [h, C.c_char_p]
         L.asd_set_variant.argtypes = [h, C.c_int32, C.c_int32]
         L.asd_get_variant.argtypes = [h, P(C.c_int32), P(C.c_int32)]
+        L.asd_variant_count.argtypes = [h, C.c_int32, P(C.c_int32)]
         L.asd_variant_name.argtypes = [h, C.c_char_p, C.c_size_t]
         L.asd_strerror.argtypes = [C.c_int]
         L.asd_strerror.restype = C.c_char_p
@@ -350,15 +352,10 @@ class Handle:
         return asd_get_variant(self.h)
 
     def variant_count(self, kernel: int) -> int:
-        """Number of variants of a kernel family (probed through asd_set_variant)."""
-        cur = self.variant()
-        n = 0
-        while True:
-            if lib().asd_set_variant(self.h, kernel, n) != ASD_OK:
-                break
-            n += 1
-        asd_set_variant(self.h, *cur)
-        return n
+        """Number of tile variants of a kernel family."""
+        n = C.c_int32()
+        _check(lib().asd_variant_count(self.h, kernel, C.byref(n)), self.h)
+        return n.value
 
     def variant_name(self) -> str:
         buf = C.create_string_buffer(256)

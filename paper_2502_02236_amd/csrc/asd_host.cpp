@@ -1211,6 +1211,18 @@ int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile)
     return ASD_OK;
 }
 
+int asd_variant_count(asd_t *h, int32_t kernel, int32_t *count)
+{
+    if (!h || !count) return fail(h, ASD_EINVAL, "NULL argument");
+    if (kernel == ASD_KERNEL_PLAIN)
+        *count = kPlainVariants;
+    else if (kernel == ASD_KERNEL_FUSED)
+        *count = fused_count(h->p.lattice == ASD_L10, h->p.precision == ASD_FP64);
+    else
+        return fail(h, ASD_EINVAL, "kernel must be PLAIN or FUSED");
+    return ASD_OK;
+}
+
 int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile)
 {
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
