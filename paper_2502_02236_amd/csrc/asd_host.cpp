@@ -796,6 +796,8 @@ static StepArgs<T> make_args(const asd_t *h, int cur, int step_off)
     a.step_off = step_off;
     a.tile_cfg = h->tile_cfg;
     a.lattice = h->p.lattice;
+    for (const HostSys &hs : h->sys)
+        if (hs.desc.bc_z == ASD_BC_PERIODIC) a.any_zper = 1;
     a.c = make_consts(h);
     return a;
 }
@@ -1240,8 +1242,14 @@ int asd_variant_name(asd_t *h, char *buf, size_t len)
     if (h->kernel == ASD_KERNEL_FUSED) {
         const bool l10 = h->p.lattice == ASD_L10;
         const FusedVariant f = fused_pick(l10, fp64, h->tile_cfg);
-        snprintf(tmp, sizeof tmp, "k_fused_%s<%s, %d, %d, %d>", l10 ? "l10" : "sc", T, f.txe, f.waves,
-                 f.rows);
+        bool zper = false;
+        for (const HostSys &hs : h->sys)
+            if (hs.desc.bc_z == ASD_BC_PERIODIC) zper = true;
+        if (l10)
+            snprintf(tmp, sizeof tmp, "k_fused_l10<%s, %d, %d, %d>", T, f.txe, f.waves, f.rows);
+        else
+            snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d, %s>", T, f.txe, f.waves, f.rows,
+                     zper ? "true" : "false");
     } else if (h->tile_cfg == 1) {
         snprintf(tmp, sizeof tmp, "k_plain_predictor<%s, true>+k_stash_corrector<%s>", T, T);
     } else {

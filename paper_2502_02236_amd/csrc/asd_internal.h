@@ -77,6 +77,7 @@ struct StepArgs {
     int32_t tile_cfg;         // tile variant
     int32_t n_blocks;         // blocks of the launch (XCD-contiguous tile order)
     int32_t lattice;          // ASD_SC / ASD_L10
+    int32_t any_zper;         // some system is periodic along z
     StepConsts c;
 };
 
