@@ -323,6 +323,9 @@ def main():
         v64 = r64["n_mag"] * r64["steps"] / r64["t"]
         out["fp64_plain_value"] = v64
         out["speedup_vs_fp64_plain"] = value / v64
+        # the FP64 fused kernel (bit-identical to the FP64 oracle), autotuned
+        r64f = gpu_run(args, "fp64", "auto", max(200, args.steps // 10), 20, args.graph_steps)
+        out["fp64_fused_value"] = r64f["n_mag"] * r64f["steps"] / r64f["t"]
     if not args.no_cpu_baseline and args.workload == "slab":
         out["cpu_baseline"] = cpu_baseline(steps=args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -7,7 +7,8 @@ library ``paper_2502_02236_amd``; it loads its own C file ``asd_oracle.c``
 
 Paper: Gija et al., arXiv 2502.02236 -- Eq. 1 (sLLG), Sec. II thermal field,
 Eq. 2 (exchange), Eq. 3 (anisotropy), Sec. III (spot, write field, Voronoi
-track), Appendix A (L1_0 Fe sublattice), Eq. 6 (moment sums).
+track), Appendix A (L1_0 Fe sublattice), Eq. 6 (moment sums; the window-end
+transfer to and from a coarse grid with cone thermalisation, Sec. II).
 """
 from __future__ import annotations
 
@@ -88,6 +89,15 @@ def _declare(L):
     L.orc_heun_steps.restype = C.c_int
     L.orc_magnetisation.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int, f64p, f64p]
     L.orc_energy.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int64, f64p]
+    L.orc_coarse_grain.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p, f64p, f64p,
+                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
+    L.orc_cone_theta_max.argtypes = [C.c_double]
+    L.orc_cone_theta_max.restype = C.c_double
+    L.orc_cone_spin.argtypes = [f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                f64p]
+    L.orc_cone_columns.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p, f64p, f64p,
+                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p, C.c_int,
+                                   C.c_uint64, C.c_uint32, C.c_uint32]
 
 
 def _ptr(a, t):
@@ -246,3 +256,45 @@ class System:
         lib().orc_energy(C.byref(self._s), _ptr(Sx, f64p), _ptr(Sy, f64p), _ptr(Sz, f64p), step,
                          _ptr(out, f64p))
         return out
+
+
+# ---------------------------------------------------------------- window-end transfer (Eq. 6)
+def coarse_cells(ncols: int, ny: int, nz: int, cx: int, cy: int, cz: int) -> int:
+    return -(-ncols // cx) * -(-ny // cy) * -(-nz // cz)
+
+
+def coarse_grain(kind, sx, ny, nz, label, S, x0, ncols, cx, cy, cz) -> np.ndarray:
+    """Per coarse cell (sum mx, sum my, sum mz, N magnetic sites) over stored
+    columns [x0, x0 + ncols); cells of cx x cy x cz lattice cells."""
+    S = np.ascontiguousarray(S, dtype=np.float64).reshape(3, -1)
+    Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+    lab = np.ascontiguousarray(label, dtype=np.int32)
+    out = np.zeros((coarse_cells(ncols, ny, nz, cx, cy, cz), 4))
+    lib().orc_coarse_grain(kind, sx, ny, nz, _ptr(lab, i32p), _ptr(Sx, f64p), _ptr(Sy, f64p),
+                           _ptr(Sz, f64p), x0, ncols, cx, cy, cz, _ptr(out, f64p))
+    return out
+
+
+def cone_theta_max(m: float) -> float:
+    return lib().orc_cone_theta_max(float(m))
+
+
+def cone_spin(mvec, rounds, seed, site, step, sys) -> np.ndarray:
+    mv = np.ascontiguousarray(mvec, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_cone_spin(_ptr(mv, f64p), rounds, seed, site, step, sys, _ptr(out, f64p))
+    return out
+
+
+def cone_columns(kind, sx, ny, nz, label, S, x0, ncols, cx, cy, cz, mcell, rounds, seed, step,
+                 sys) -> np.ndarray:
+    """S with the magnetic sites of columns [x0, x0 + ncols) replaced by cone
+    spins around the reduced magnetisation of their coarse cell."""
+    S = np.array(S, dtype=np.float64).reshape(3, -1)
+    Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+    lab = np.ascontiguousarray(label, dtype=np.int32)
+    mc = np.ascontiguousarray(mcell, dtype=np.float64).reshape(-1, 3)
+    lib().orc_cone_columns(kind, sx, ny, nz, _ptr(lab, i32p), _ptr(Sx, f64p), _ptr(Sy, f64p),
+                           _ptr(Sz, f64p), x0, ncols, cx, cy, cz, _ptr(mc, f64p), rounds, seed,
+                           step, sys)
+    return np.stack([Sx, Sy, Sz])

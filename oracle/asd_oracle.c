@@ -637,3 +637,118 @@ void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const d
     out[2] = nval(&ze);
     out[3] = (out[0] + out[1]) + out[2];
 }
+
+/* ------------------------------------------------------------------ */
+/* Window-end transfer between the atomistic lattice and a coarse     */
+/* (micromagnetic) grid (Sec. II, Eq. 6).  Cells are boxes of         */
+/* cx x cy x cz lattice cells over the stored columns [x0, x0+ncols)  */
+/* of a lattice of sx x ny x nz cells, numbered i + ncx (j + ncy k)   */
+/* with ncx = ceil(ncols/cx), ncy = ceil(ny/cy); both L1_0 sites of a */
+/* lattice cell belong to its coarse cell.                            */
+/* ------------------------------------------------------------------ */
+static int64_t coarse_cell(int kind, int sx, int ny, int64_t site, int x0, int ncols, int cx,
+                           int cy, int cz)
+{
+    int64_t cell = kind == ORC_SC ? site : site / 2;
+    int64_t x = cell % sx, y = (cell / sx) % ny, z = cell / ((int64_t)sx * ny);
+    if (x < x0 || x >= x0 + ncols) return -1;
+    int64_t ncx = (ncols + cx - 1) / cx, ncy = (ny + cy - 1) / cy;
+    return (x - x0) / cx + ncx * (y / cy + ncy * (z / cz));
+}
+
+/* Eq. 6 read forwards: per coarse cell the sum of the unit spins of its
+ * magnetic sites and their number, out[ncell][4] = (sum mx, sum my, sum mz,
+ * N).  M = mu_s / V * sum m, and M / M_S^0 = |sum m| / N (all N aligned). */
+void orc_coarse_grain(int kind, int sx, int ny, int nz, const int32_t *label, const double *Sx,
+                      const double *Sy, const double *Sz, int x0, int ncols, int cx, int cy,
+                      int cz, double *out)
+{
+    int64_t ncell = (int64_t)((ncols + cx - 1) / cx) * ((ny + cy - 1) / cy) * ((nz + cz - 1) / cz);
+    int64_t n = (kind == ORC_SC ? 1 : 2) * (int64_t)sx * ny * nz;
+    for (int64_t k = 0; k < 4 * ncell; ++k) out[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (label[i] < 0) continue;
+        int64_t c = coarse_cell(kind, sx, ny, i, x0, ncols, cx, cy, cz);
+        if (c < 0) continue;
+        out[4 * c + 0] += Sx[i];
+        out[4 * c + 1] += Sy[i];
+        out[4 * c + 2] += Sz[i];
+        out[4 * c + 3] += 1.0;
+    }
+}
+
+/* Maximum polar angle of the cone that rebuilds a reduced magnetisation m
+ * (Sec. II, inverse transfer), as printed:
+ * (5 pi / 9) sqrt(1 - sqrt(1 + 6 (m - 1) / 5)).  The expression is real on
+ * [1/6, 1]; m is clamped to that range (reading: below 1/6 the widest cone,
+ * 100 degrees). */
+double orc_cone_theta_max(double m)
+{
+    if (m > 1.0) m = 1.0;
+    if (m < 1.0 / 6.0) m = 1.0 / 6.0;
+    double t = 1.0 + (6.0 * (m - 1.0)) / 5.0;
+    if (t < 0.0) t = 0.0;
+    return 1.7453292519943295 * sqrt(1.0 - sqrt(t));
+}
+
+/* One spin drawn in the cone around the unit direction n (n = z when the
+ * coarse magnetisation vanishes): polar angle uniform on [0, theta_max(m)],
+ * azimuth uniform, from Philox words (w0, w1) of counter (site, step,
+ * system, 1) with u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32.  The azimuth is
+ * measured in the orthonormal basis of Duff, Burgess, Christensen, Hery,
+ * Kensler, Liani and Villemin, "Building an orthonormal basis, revisited"
+ * (JCGT 2017): s = sign(n_z) (+1 at 0), a = -1 / (s + n_z), b = n_x n_y a,
+ * b1 = (1 + s n_x^2 a, s b, -s n_x), b2 = (b, s + n_y^2 a, -n_y). */
+void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t site, uint32_t step,
+                   uint32_t sys, double out[3])
+{
+    double m = sqrt((mvec[0] * mvec[0] + mvec[1] * mvec[1]) + mvec[2] * mvec[2]);
+    double nx = 0.0, ny = 0.0, nz = 1.0;
+    if (m > 0.0) {
+        nx = mvec[0] / m;
+        ny = mvec[1] / m;
+        nz = mvec[2] / m;
+    }
+    uint32_t ctr[4] = {site, step, sys, 1u};
+    uint32_t w[4];
+    orc_philox4x32(rounds, (uint32_t)seed, (uint32_t)(seed >> 32), ctr, w);
+    double u1 = ((double)w[0] + 0.5) * TWO_M32;
+    double u2 = (double)w[1] * TWO_M32;
+    double th = u1 * orc_cone_theta_max(m);
+    double st, ct, sp, cp;
+    orc_sincos2pi(th / 6.283185307179586, &st, &ct);
+    orc_sincos2pi(u2, &sp, &cp);
+    double s = nz >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (s + nz);
+    double b = (nx * ny) * a;
+    double b1[3] = {1.0 + ((s * nx) * nx) * a, s * b, -s * nx};
+    double b2[3] = {b, s + (ny * ny) * a, -ny};
+    double ex = st * cp, ey = st * sp;
+    double v[3];
+    for (int k = 0; k < 3; ++k) v[k] = (ex * b1[k] + ey * b2[k]) + ct * (k == 0 ? nx : (k == 1 ? ny : nz));
+    normalise(v);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+}
+
+/* Eq. 6 read backwards: the magnetic sites of columns [x0, x0+ncols) take
+ * cone spins around the reduced magnetisation mcell[3 c .. 3 c + 2] of
+ * their coarse cell c (|m| <= 1); other sites are left as they are.
+ * Counter word 0 is the stored site index. */
+void orc_cone_columns(int kind, int sx, int ny, int nz, const int32_t *label, double *Sx,
+                      double *Sy, double *Sz, int x0, int ncols, int cx, int cy, int cz,
+                      const double *mcell, int rounds, uint64_t seed, uint32_t step, uint32_t sys)
+{
+    int64_t n = (kind == ORC_SC ? 1 : 2) * (int64_t)sx * ny * nz;
+    for (int64_t i = 0; i < n; ++i) {
+        if (label[i] < 0) continue;
+        int64_t c = coarse_cell(kind, sx, ny, i, x0, ncols, cx, cy, cz);
+        if (c < 0) continue;
+        double v[3];
+        orc_cone_spin(mcell + 3 * c, rounds, seed, (uint32_t)i, step, sys, v);
+        Sx[i] = v[0];
+        Sy[i] = v[1];
+        Sz[i] = v[2];
+    }
+}

@@ -77,6 +77,17 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
                    int64_t nsteps);
 void orc_magnetisation(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                        int n_grains, double *per_grain, double tot[4]);
+/* window-end transfer (Sec. II, Eq. 6): coarse cells of cx x cy x cz
+ * lattice cells over stored columns [x0, x0 + ncols) */
+void orc_coarse_grain(int kind, int sx, int ny, int nz, const int32_t *label, const double *Sx,
+                      const double *Sy, const double *Sz, int x0, int ncols, int cx, int cy,
+                      int cz, double *out);
+double orc_cone_theta_max(double m);
+void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t site, uint32_t step,
+                   uint32_t sys, double out[3]);
+void orc_cone_columns(int kind, int sx, int ny, int nz, const int32_t *label, double *Sx,
+                      double *Sy, double *Sz, int x0, int ncols, int cx, int cy, int cz,
+                      const double *mcell, int rounds, uint64_t seed, uint32_t step, uint32_t sys);
 void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                 int64_t step, double out[4]);
 

@@ -462,3 +462,100 @@ def test_noise_depends_on_absolute_site_step_and_system():
     g4 = oracle.gauss3(np.arange(10), 5, 0, 2)
     for other in (g2, g3, g4):
         assert np.all(np.abs(g1 - other) > 0)
+
+
+# ------------------------------------------------------------------ window-end transfer (Eq. 6)
+def test_cone_theta_max_printed_formula():
+    """theta_max of the inverse transfer (Sec. II) as printed: zero for a
+    saturated cell, the 5 pi / 9 prefactor at the lower end of its domain
+    m = 1/6 (clamped below), decreasing in between, and near saturation
+    theta_max^2 / (1 - m) -> (5 pi / 9)^2 * 3 / 5 (first order of the
+    printed expression)."""
+    assert oracle.cone_theta_max(1.0) == 0.0
+    assert oracle.cone_theta_max(1.5) == 0.0
+    assert abs(oracle.cone_theta_max(1.0 / 6.0) - 5 * math.pi / 9) < 1e-15
+    assert oracle.cone_theta_max(0.05) == oracle.cone_theta_max(1.0 / 6.0)
+    ms = np.linspace(1.0 / 6.0, 1.0, 200)
+    th = np.array([oracle.cone_theta_max(m) for m in ms])
+    assert np.all(np.diff(th) < 0)
+    for d in (1e-6, 1e-8):
+        assert abs(oracle.cone_theta_max(1.0 - d) ** 2 / d / ((5 * math.pi / 9) ** 2 * 0.6) - 1) < 1e-4
+
+
+@pytest.mark.parametrize("mvec", [(0.0, 0.0, 0.7), (0.0, 0.0, -0.7), (0.7, 0.0, 0.0),
+                                  (-0.2, 0.5, -0.4), (0.0, 0.0, 0.0), (0.3, -0.3, 0.2)])
+def test_cone_spins_polar_angle_uniform_in_cone(mvec):
+    """Cone spins (Sec. II): unit length, polar angle to the cell direction
+    uniform on [0, theta_max(|m|)] (Kolmogorov-Smirnov), azimuth uniform
+    around it, mean cos of the polar angle = sin(theta_max) / theta_max."""
+    from scipy import stats
+    m = float(np.linalg.norm(mvec))
+    n = np.array(mvec) / m if m > 0 else np.array([0.0, 0.0, 1.0])
+    tmax = oracle.cone_theta_max(m)
+    N = 6000
+    S = np.array([oracle.cone_spin(mvec, 10, 99, i, 5, 2) for i in range(N)])
+    assert np.max(np.abs(np.linalg.norm(S, axis=1) - 1)) < 1e-15
+    c = np.clip(S @ n, -1, 1)
+    th = np.arccos(c)
+    assert th.max() <= tmax + 1e-7
+    assert stats.kstest(th / tmax, "uniform").pvalue > 1e-3
+    # azimuth in any fixed frame around n
+    a = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(n, a)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(n, e1)
+    phi = np.arctan2(S @ e2, S @ e1) % (2 * math.pi)
+    assert stats.kstest(phi / (2 * math.pi), "uniform").pvalue > 1e-3
+    expect = math.sin(tmax) / tmax
+    assert abs(c.mean() - expect) < 5 * c.std() / math.sqrt(N)
+
+
+@pytest.mark.parametrize("kind", [oracle.SC, oracle.L10])
+def test_coarse_grain_partitions_the_columns(kind):
+    """Eq. 6 sums: the coarse cells partition the magnetic sites of the
+    column range (ragged cells at the ends included), each cell's sum equals
+    a direct sum over the sites whose lattice coordinates fall in it, and
+    one cell over everything gives the total moment."""
+    rng = np.random.default_rng(3)
+    sx, ny, nz, per = 11, 7, 5, 1 if kind == oracle.SC else 2
+    n = per * sx * ny * nz
+    S = rng.normal(size=(3, n))
+    S /= np.linalg.norm(S, axis=0)
+    lab = rng.integers(-1, 3, size=n).astype(np.int32)
+    S[:, lab < 0] = 0.0
+    cell = np.arange(n) // per
+    x, y, z = cell % sx, (cell // sx) % ny, cell // (sx * ny)
+    x0, ncols, cx, cy, cz = 2, 8, 3, 2, 2
+    out = oracle.coarse_grain(kind, sx, ny, nz, lab, S, x0, ncols, cx, cy, cz)
+    ncx, ncy = -(-ncols // cx), -(-ny // cy)
+    inrange = (x >= x0) & (x < x0 + ncols) & (lab >= 0)
+    assert out[:, 3].sum() == inrange.sum()
+    for c in range(len(out)):
+        i, j, k = c % ncx, (c // ncx) % ncy, c // (ncx * ncy)
+        sel = inrange & ((x - x0) // cx == i) & (y // cy == j) & (z // cz == k)
+        np.testing.assert_allclose(out[c, :3], S[:, sel].sum(1), rtol=0, atol=1e-13)
+        assert out[c, 3] == sel.sum()
+    one = oracle.coarse_grain(kind, sx, ny, nz, lab, S, 0, sx, sx, ny, nz)
+    np.testing.assert_allclose(one[0, :3], S.sum(1), atol=1e-12)
+
+
+def test_cone_columns_round_trip():
+    """Thermalised columns coarse-grained again: each cell's direction is
+    recovered and its reduced magnetisation equals the cone mean
+    sin(theta_max)/theta_max of the printed theta_max (which is not m
+    itself: the printed cone is narrower than the uniform-angle cone that
+    would reproduce m)."""
+    sx, ny, nz = 12, 40, 40
+    n = sx * ny * nz
+    lab = np.zeros(n, np.int32)
+    S0 = np.zeros((3, n))
+    mcell = np.array([[0.0, 0.0, 0.9], [0.5, 0.0, -0.5], [0.0, -0.3, 0.0]])
+    S = oracle.cone_columns(oracle.SC, sx, ny, nz, lab, S0, 3, 6, 2, ny, nz, mcell, 10, 7, 11, 0)
+    assert np.all(S[:, :].reshape(3, nz, ny, sx)[:, :, :, :3] == 0)
+    out = oracle.coarse_grain(oracle.SC, sx, ny, nz, lab, S, 3, 6, 2, ny, nz)
+    for c in range(3):
+        m = np.linalg.norm(mcell[c])
+        d = out[c, :3] / out[c, 3]
+        tmax = oracle.cone_theta_max(m)
+        assert abs(np.linalg.norm(d) - math.sin(tmax) / tmax) < 0.02  # ~4 sigma at N = 3200
+        assert np.dot(d / np.linalg.norm(d), mcell[c] / m) > 0.999
