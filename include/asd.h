@@ -228,6 +228,37 @@ int asd_host_grain_labels(const asd_params *p, const asd_system_desc *sys, int32
 int asd_host_neighbours(const asd_params *p, const asd_system_desc *sys, int64_t *n_entries,
                         int64_t *row_ptr, int32_t *col, int8_t *shell);
 
+/* Window-end transfer to a coarse (micromagnetic) grid: Eq. 6 read
+ * forwards (Sec. II).  The stored columns [x0, x0 + ncols) of system sys are
+ * cut into coarse cells of cx x cy x cz lattice cells, numbered
+ * c = i + ncx (j + ncy k) with ncx = ceil(ncols / cx), ncy = ceil(ny / cy)
+ * (cells at the far ends may be partial; both L1_0 sites of a lattice cell
+ * belong to its coarse cell).  out[4 c .. 4 c + 3] = (sum mx, sum my,
+ * sum mz, N): the FP64 sum of the unit spins of the cell's magnetic sites
+ * and their number, so M = mu_s / V sum m and M / M_S^0 = |sum m| / N.
+ * out: caller-owned device pointer to ncx ncy ceil(nz / cz) x 4 doubles.
+ * Reads the current spins; sums run in a fixed order (the same result every
+ * run).  Asynchronous.  ASD_EINVAL for a bad system, column range or cell. */
+int asd_coarse_grain(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int32_t cx, int32_t cy,
+                     int32_t cz, double *out);
+
+/* Window-end transfer from a coarse grid: Eq. 6 read backwards (Sec. II).
+ * Every magnetic site of the stored columns [x0, x0 + ncols) of system sys
+ * takes a spin drawn in the cone around the reduced magnetisation
+ * m_c = mcell[3 c .. 3 c + 2] (M / M_S^0, |m_c| <= 1) of its coarse cell c
+ * (cells as in asd_coarse_grain): polar angle uniform on [0, theta_max] with
+ * theta_max = (5 pi / 9) sqrt(1 - sqrt(1 + 6 (|m_c| - 1) / 5)), |m_c|
+ * clamped to [1/6, 1] (the expression is real there); azimuth uniform,
+ * measured in the orthonormal basis of Duff et al., "Building an
+ * orthonormal basis, revisited" (JCGT 2017) around m_c (z when m_c = 0).
+ * Random words: Philox4x32 of counter (stored site index, step, system, 1),
+ * u1 = (w0 + 1/2) 2^-32 sets the polar angle, u2 = w1 2^-32 the azimuth.
+ * Computed in FP64, stored in the handle precision into both spin buffers
+ * (like asd_set_spins).  mcell: caller-owned device pointer, [ncell][3]
+ * doubles.  Asynchronous.  ASD_EINVAL as asd_coarse_grain. */
+int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int32_t cx,
+                           int32_t cy, int32_t cz, const double *mcell, uint32_t step);
+
 /* Step counter and window origin of system sys (host copies). */
 int asd_get_state(asd_t *h, int32_t sys, int64_t *step, int32_t *origin);
 /* Set the step counter (resume from a checkpoint). */

@@ -29,6 +29,7 @@ SYMBOLS = [
     "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
     "asd_neighbour_count", "asd_get_neighbours", "asd_host_grain_labels", "asd_host_neighbours",
+    "asd_coarse_grain", "asd_thermalise_columns",
     "asd_get_state", "asd_set_step", "asd_philox",
     "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_count", "asd_variant_name",
     "asd_strerror",
@@ -105,6 +106,10 @@ def lib():
         L.asd_autotune.argtypes = [h, C.c_char_p]
         L.asd_set_variant.argtypes = [h, C.c_int32, C.c_int32]
         L.asd_get_variant.argtypes = [h, P(C.c_int32), P(C.c_int32)]
+        L.asd_coarse_grain.argtypes = [h, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_int32, vp]
+        L.asd_thermalise_columns.argtypes = [h, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                             C.c_int32, C.c_int32, vp, C.c_uint32]
         L.asd_variant_count.argtypes = [h, C.c_int32, P(C.c_int32)]
         L.asd_variant_name.argtypes = [h, C.c_char_p, C.c_size_t]
         L.asd_strerror.argtypes = [C.c_int]
@@ -295,6 +300,34 @@ class Handle:
 
     def prepare(self):
         asd_prepare(self.h)
+
+    def coarse_cells(self, sys: int, ncols: int, cx: int, cy: int, cz: int) -> int:
+        d = self.systems[sys]
+        return -(-ncols // cx) * -(-d.ny // cy) * -(-d.nz // cz)
+
+    def coarse_grain(self, sys: int, x0: int, ncols: int, cx: int, cy: int, cz: int, out=None):
+        """Eq. 6 sums per coarse cell: [ncell, 4] (sum m, N), float64 device tensor
+        (complete when this returns)."""
+        torch = self.torch
+        n = self.coarse_cells(sys, ncols, cx, cy, cz)
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float64, device=self.device)
+        _check(lib().asd_coarse_grain(self.h, sys, x0, ncols, cx, cy, cz, out.data_ptr()), self.h)
+        self.stream.synchronize()
+        return out
+
+    def thermalise_columns(self, sys: int, x0: int, ncols: int, cx: int, cy: int, cz: int, mcell,
+                           step: int):
+        """Cone spins around the reduced magnetisation mcell [ncell, 3] (host array or
+        device tensor) of each coarse cell (complete when this returns)."""
+        torch = self.torch
+        m = torch.as_tensor(mcell, dtype=torch.float64, device=self.device).contiguous()
+        if m.numel() != 3 * self.coarse_cells(sys, ncols, cx, cy, cz):
+            raise ValueError("mcell must hold 3 values per coarse cell")
+        torch.cuda.current_stream(self.device).synchronize()  # the upload is complete
+        _check(lib().asd_thermalise_columns(self.h, sys, x0, ncols, cx, cy, cz, m.data_ptr(),
+                                            step), self.h)
+        self.stream.synchronize()
 
     def shift_window(self, columns: int):
         asd_shift_window(self.h, columns)

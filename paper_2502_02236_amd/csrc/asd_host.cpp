@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1119,6 +1120,65 @@ int asd_host_neighbours(const asd_params *p, const asd_system_desc *sys, int64_t
     }
     if (row_ptr) row_ptr[hs.n_stored] = c;
     *n_entries = c;
+    return ASD_OK;
+}
+
+// coarse cells over stored columns [x0, x0 + ncols) of system s
+static int transfer_args(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32_t cx, int32_t cy,
+                         int32_t cz, TransferArgs *a)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad system index");
+    const SysDev &d = h->dev[s];
+    if (x0 < 0 || ncols < 1 || (int64_t)x0 + ncols > d.sx)
+        return fail(h, ASD_EINVAL, "columns [%d, %d) outside the %d stored columns", x0, x0 + ncols, d.sx);
+    if (cx < 1 || cy < 1 || cz < 1) return fail(h, ASD_EINVAL, "coarse cells need cx, cy, cz >= 1");
+    std::memset(a, 0, sizeof *a);
+    a->prec = h->p.precision;
+    a->S[0] = h->ws + h->L.off_S[h->cur];
+    a->S[1] = h->ws + h->L.off_S[1 - h->cur];
+    a->ncs = h->L.ncs;
+    a->d = d;
+    a->label = (const uint16_t *)(h->ws + h->L.off_label);
+    a->x0 = x0;
+    a->ncols = ncols;
+    a->cx = cx;
+    a->cy = cy;
+    a->cz = cz;
+    a->ncx = (ncols + cx - 1) / cx;
+    a->ncy = (d.ny + cy - 1) / cy;
+    const int64_t ncell = (int64_t)a->ncx * a->ncy * ((d.nz + cz - 1) / cz);
+    if (ncell > INT32_MAX) return fail(h, ASD_EINVAL, "too many coarse cells");
+    a->ncell = (int32_t)ncell;
+    a->per = h->p.lattice == ASD_SC ? 1 : 2;
+    return ASD_OK;
+}
+
+int asd_coarse_grain(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32_t cx, int32_t cy,
+                     int32_t cz, double *out)
+{
+    TransferArgs a;
+    int rc = transfer_args(h, s, x0, ncols, cx, cy, cz, &a);
+    if (rc) return rc;
+    if (!out) return fail(h, ASD_EINVAL, "NULL output");
+    a.out = out;
+    if (launch_coarse_grain(a, h->stream)) return fail(h, ASD_EHIP, "coarse-grain launch failed");
+    return ASD_OK;
+}
+
+int asd_thermalise_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32_t cx,
+                           int32_t cy, int32_t cz, const double *mcell, uint32_t step)
+{
+    TransferArgs a;
+    int rc = transfer_args(h, s, x0, ncols, cx, cy, cz, &a);
+    if (rc) return rc;
+    if (!mcell) return fail(h, ASD_EINVAL, "NULL cell magnetisation");
+    a.mcell = mcell;
+    a.k0 = (uint32_t)h->p.seed;
+    a.k1 = (uint32_t)(h->p.seed >> 32);
+    a.step = step;
+    a.rounds = h->p.philox_rounds;
+    if (launch_cone_columns(a, h->stream)) return fail(h, ASD_EHIP, "cone launch failed");
     return ASD_OK;
 }
 

@@ -122,6 +122,23 @@ struct EnergyArgs {
     double mu_s, ku;          // J/T, J
     const double *ku_grain;   // per global grain (J) when has_can_grain
 };
+// window-end transfer to and from a coarse grid (Eq. 6): cells of cx x cy
+// x cz lattice cells over stored columns [x0, x0 + ncols) of system d
+struct TransferArgs {
+    int prec;                 // ASD_FP64 / ASD_FP32
+    void *S[2];               // both spin buffers [3][ncs] (coarse-grain reads S[0])
+    int64_t ncs;
+    SysDev d;
+    const uint16_t *label;    // global label array
+    int32_t x0, ncols, cx, cy, cz, ncx, ncy, ncell;
+    int32_t per;              // sites per lattice cell (1 SC, 2 L1_0)
+    double *out;              // coarse-grain: [ncell][4]
+    const double *mcell;      // cone: [ncell][3]
+    uint32_t k0, k1, step;    // cone: Philox key and counter word 1
+    int32_t rounds;
+};
+int launch_coarse_grain(const TransferArgs &a, void *stream);
+int launch_cone_columns(const TransferArgs &a, void *stream);
 // sum the energy partials of each system's tiles in order -> [S][4]
 int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, double *sys_out,
                          void *stream);

@@ -1,5 +1,6 @@
 // asd_misc.hip -- Philox export, step-counter and window bookkeeping,
-// column freezing for window shifts, and the FP64 reductions.
+// column freezing for window shifts, the FP64 reductions, and the window-end
+// transfer to and from a coarse (micromagnetic) grid.
 #include "asd_device.h"
 #include "asd_internal.h"
 #include "asd.h"
@@ -251,6 +252,145 @@ int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, do
 {
     hipLaunchKernelGGL(k_energy_finish, dim3((n_sys + 63) / 64), dim3(64), 0, (hipStream_t)stream,
                        partial, sys, n_sys, sys_out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------- transfer
+// Eq. 6 read forwards (Sec. II): one workgroup per coarse cell sums the unit
+// spins of its magnetic sites in FP64 (sites in index order per thread,
+// threads in a fixed tree: the same result every run).
+constexpr int kXferBlock = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kXferBlock) void k_coarse_grain(TransferArgs a)
+{
+    const int c = blockIdx.x;
+    const int i = c % a.ncx, j = (c / a.ncx) % a.ncy, k = c / (a.ncx * a.ncy);
+    const int xb = a.x0 + i * a.cx, yb = j * a.cy, zb = k * a.cz;
+    const int wx = min(a.cx, a.x0 + a.ncols - xb), wy = min(a.cy, a.d.ny - yb),
+              wz = min(a.cz, a.d.nz - zb);
+    const int64_t n_in = (int64_t)a.per * wx * wy * wz;
+    const T *S = (const T *)a.S[0];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t q = threadIdx.x; q < n_in; q += kXferBlock) {
+        const int s = (int)(q % a.per);
+        int64_t r = q / a.per;
+        const int xx = (int)(r % wx);
+        r /= wx;
+        const int yy = (int)(r % wy), zz = (int)(r / wy);
+        const int64_t site =
+            a.per * ((int64_t)(xb + xx) + (int64_t)a.d.sx * ((yb + yy) + (int64_t)a.d.ny * (zb + zz))) + s;
+        const int64_t g = a.d.base + site;
+        if (a.label[g] == kNoGrain) continue;
+        acc[0] += (double)S[g];
+        acc[1] += (double)S[a.ncs + g];
+        acc[2] += (double)S[2 * a.ncs + g];
+        acc[3] += 1.0;
+    }
+    __shared__ double red[4][kXferBlock];
+    for (int m = 0; m < 4; ++m) red[m][threadIdx.x] = acc[m];
+    __syncthreads();
+    for (int off = kXferBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int m = 0; m < 4; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int m = 0; m < 4; ++m) a.out[4 * (int64_t)c + m] = red[m][0];
+}
+
+int launch_coarse_grain(const TransferArgs &a, void *stream)
+{
+    if (a.ncell == 0) return 0;
+    if (a.prec == ASD_FP64)
+        hipLaunchKernelGGL(k_coarse_grain<double>, dim3(a.ncell), dim3(kXferBlock), 0,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_coarse_grain<float>, dim3(a.ncell), dim3(kXferBlock), 0,
+                           (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Widest cone of the inverse transfer (Sec. II), as printed: (5 pi / 9)
+// sqrt(1 - sqrt(1 + 6 (m - 1) / 5)) with m clamped to [1/6, 1].
+__device__ __forceinline__ double cone_theta_max(double m)
+{
+    if (m > 1.0) m = 1.0;
+    if (m < 1.0 / 6.0) m = 1.0 / 6.0;
+    double t = 1.0 + (6.0 * (m - 1.0)) / 5.0;
+    if (t < 0.0) t = 0.0;
+    return 1.7453292519943295 * sqrt(1.0 - sqrt(t));
+}
+
+// Eq. 6 read backwards (Sec. II): each magnetic site of the columns takes a
+// spin in the cone around its coarse cell's reduced magnetisation: polar
+// angle uniform on [0, theta_max], azimuth uniform, measured in the
+// orthonormal basis of Duff et al. (JCGT 2017) around the cell direction.
+// FP64 throughout; both spin buffers receive the result.
+template <typename T>
+__global__ void k_cone_columns(TransferArgs a)
+{
+    const int64_t n = (int64_t)a.per * a.ncols * a.d.ny * a.d.nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int s = (int)(t % a.per);
+    int64_t r = t / a.per;
+    const int xx = (int)(r % a.ncols);
+    r /= a.ncols;
+    const int y = (int)(r % a.d.ny), z = (int)(r / a.d.ny);
+    const int64_t site = a.per * ((int64_t)(a.x0 + xx) + (int64_t)a.d.sx * (y + (int64_t)a.d.ny * z)) + s;
+    const int64_t g = a.d.base + site;
+    if (a.label[g] == kNoGrain) return;
+    const int c = xx / a.cx + a.ncx * (y / a.cy + a.ncy * (z / a.cz));
+    const double mx = a.mcell[3 * (int64_t)c], my = a.mcell[3 * (int64_t)c + 1],
+                 mz = a.mcell[3 * (int64_t)c + 2];
+    const double m = sqrt((mx * mx + my * my) + mz * mz);
+    double nx = 0.0, ny = 0.0, nz = 1.0;
+    if (m > 0.0) {
+        nx = mx / m;
+        ny = my / m;
+        nz = mz / m;
+    }
+    const Words4 w = philox4x32(a.rounds, a.k0, a.k1, (uint32_t)site, a.step, a.d.sys_id, 1u);
+    const double TWO_M32 = 2.3283064365386962890625e-10;
+    const double u1 = ((double)w.w0 + 0.5) * TWO_M32;
+    const double u2 = (double)w.w1 * TWO_M32;
+    const double th = u1 * cone_theta_max(m);
+    double st, ct, sp, cp;
+    f64::sincos2pi(th / 6.283185307179586, st, ct);
+    f64::sincos2pi(u2, sp, cp);
+    const double sg = nz >= 0.0 ? 1.0 : -1.0;
+    const double aa = -1.0 / (sg + nz);
+    const double b = (nx * ny) * aa;
+    const double b1x = 1.0 + ((sg * nx) * nx) * aa, b1y = sg * b, b1z = -sg * nx;
+    const double b2x = b, b2y = sg + (ny * ny) * aa, b2z = -ny;
+    const double ex = st * cp, ey = st * sp;
+    double vx = (ex * b1x + ey * b2x) + ct * nx;
+    double vy = (ex * b1y + ey * b2y) + ct * ny;
+    double vz = (ex * b1z + ey * b2z) + ct * nz;
+    const double nn = sqrt((vx * vx + vy * vy) + vz * vz);
+    vx = vx / nn;
+    vy = vy / nn;
+    vz = vz / nn;
+    for (int b2 = 0; b2 < 2; ++b2) {
+        T *S = (T *)a.S[b2];
+        S[g] = (T)vx;
+        S[a.ncs + g] = (T)vy;
+        S[2 * a.ncs + g] = (T)vz;
+    }
+}
+
+int launch_cone_columns(const TransferArgs &a, void *stream)
+{
+    const int64_t n = (int64_t)a.per * a.ncols * a.d.ny * a.d.nz;
+    if (n == 0) return 0;
+    const int64_t blocks = (n + 255) / 256;
+    if (a.prec == ASD_FP64)
+        hipLaunchKernelGGL(k_cone_columns<double>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_cone_columns<float>, dim3((unsigned)blocks), dim3(256), 0,
+                           (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

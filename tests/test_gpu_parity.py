@@ -286,6 +286,48 @@ def test_layered_grains_with_per_grain_anisotropy_run_two_pass(lattice):
         h.close()
 
 
+@pytest.mark.parametrize("name,w", [("sc_track", c5_crop()), ("l10", c3_crop()),
+                                    ("sc_slab", c2_crop(seed=44))])
+def test_window_end_transfer_matches_oracle(name, w):
+    """Eq. 6 both ways (Sec. II): coarse-grain sums over ragged cells agree with
+    the oracle to FP64 rounding (exact counts); cone thermalisation is
+    bit-identical to the oracle in FP64 and to its FP32 rounding in FP32,
+    leaves other columns untouched and lands in both spin buffers."""
+    kind = oracle.SC if w.kind == W.SC else oracle.L10
+    sx = w.track_nx or w.nx
+    rng = np.random.default_rng(5)
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        say("transfer", name, precision)
+        h, lab, _ = run_gpu(w, precision, 30)
+        S = h.get_spins().astype(np.float64)
+        x0, ncols, cx, cy, cz = 3, sx - 5, 4, 3, 2
+        got = h.coarse_grain(0, x0, ncols, cx, cy, cz).cpu().numpy()
+        ref = oracle.coarse_grain(kind, sx, w.ny, w.nz, lab, S, x0, ncols, cx, cy, cz)
+        np.testing.assert_array_equal(got[:, 3], ref[:, 3])
+        assert np.max(np.abs(got[:, :3] - ref[:, :3])) < 1e-12 * max(1.0, np.abs(ref).max())
+        # thermalise columns (outside the window for the track: frozen there)
+        tx0 = w.nx + 5 if w.track_nx else 2
+        tn = min(10, sx - tx0)
+        nc = h.coarse_cells(0, tn, 3, 4, 2)
+        mcell = rng.normal(size=(nc, 3))
+        mcell *= (rng.uniform(0, 1, nc) / np.linalg.norm(mcell, axis=1))[:, None]
+        mcell[0] = 0.0
+        h.thermalise_columns(0, tx0, tn, 3, 4, 2, mcell, 77)
+        Sg = h.get_spins()
+        So = oracle.cone_columns(kind, sx, w.ny, w.nz, lab, S, tx0, tn, 3, 4, 2, mcell, 10, w.seed,
+                                 77, 0)
+        if precision == A.ASD_FP64:
+            np.testing.assert_array_equal(Sg, So)
+        else:
+            np.testing.assert_array_equal(Sg, So.astype(np.float32))
+        if w.track_nx:
+            h.step(1)  # the window moves on; the frozen thermalised columns stay
+            cell = np.arange(Sg.shape[1])
+            frozen = (cell % sx) >= w.nx
+            np.testing.assert_array_equal(h.get_spins()[:, frozen], Sg[:, frozen])
+        h.close()
+
+
 def test_error_paths_leave_the_handle_usable():
     """Invalid calls fail with their codes before anything is enqueued and
     leave the handle's state as it was: afterwards the handle still steps
