@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track"], default="slab")
+    ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track", "transfer"],
+                    default="slab")
     ap.add_argument("--kernel", choices=["auto", "plain", "fused"], default="auto")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--graph-steps", type=int, default=100)
@@ -233,6 +234,58 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps):
                 tile=tile_used, step_med=med, step_mean=mean, norm_err=norm_err, kname=kname)
 
 
+def transfer_run(args, cell=7, reps=20):
+    """Window-end transfer (Eq. 6 both ways) over the 16-seed track: every
+    stored column of every system coarse-grained into cells of cell^3
+    lattice cells, then every window column thermalised from a coarse field.
+    Times `reps` rounds with HIP events on the handle's stream."""
+    import ctypes as C
+    import torch
+    from paper_2502_02236_amd import asd as A
+
+    prec = A.ASD_FP32 if args.precision == "fp32" else A.ASD_FP64
+    w, h, S0s, n_mag, n_sites, extra = build_workload("track", prec, 0)
+    L = A.lib()
+    n_sys = len(S0s)
+    sx = w.track_nx
+    ncell = h.coarse_cells(0, sx, cell, cell, cell)
+    out = torch.empty((n_sys, ncell, 4), dtype=torch.float64, device=h.device)
+    nwc = h.coarse_cells(0, w.nx, cell, cell, cell)
+    mc = torch.zeros((nwc, 3), dtype=torch.float64, device=h.device)
+    mc[:, 2] = 0.8
+    torch.cuda.synchronize()
+
+    def coarse():
+        for s in range(n_sys):
+            A._check(L.asd_coarse_grain(h.h, s, 0, sx, cell, cell, cell, out[s].data_ptr()), h.h)
+
+    def cone():
+        for s in range(n_sys):
+            A._check(L.asd_thermalise_columns(h.h, s, 0, w.nx, cell, cell, cell, mc.data_ptr(),
+                                              C.c_uint32(7)), h.h)
+
+    res = {}
+    for name, fn in (("coarse_grain", coarse), ("thermalise", cone)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(h.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(h.stream)
+        e1.synchronize()
+        res[name] = e0.elapsed_time(e1) / 1e3 / reps  # s per round (n_sys launches)
+    sites_cg = n_sys * sx * w.ny * w.nz
+    sites_th = n_sys * w.nx * w.ny * w.nz
+    e = 4 if prec == A.ASD_FP32 else 8
+    cg_bytes = sites_cg * (3 * e + 2)       # spins + label read once
+    th_bytes = sites_th * (2 * 3 * e + 2)   # label read, both buffers written
+    h.close()
+    return dict(w=w, res=res, sites_cg=sites_cg, sites_th=sites_th, cg_bytes=cg_bytes,
+                th_bytes=th_bytes, e=e, cell=cell, reps=reps)
+
+
 def cpu_baseline(target_s=15.0, steps=0):
     """The FP64 oracle, single-threaded plain C, on the full lattice for a few steps."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -260,9 +313,33 @@ def cpu_baseline(target_s=15.0, steps=0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are "
-                                   "not part of this build (see DESIGN.md: sharding)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the step "
+                                   "library drives a single device, and runs over several "
+                                   "GPUs are not provided"}))
         sys.exit(2)
+    if args.workload == "transfer":
+        t = transfer_run(args)
+        cg, th = t["res"]["coarse_grain"], t["res"]["thermalise"]
+        ach = t["cg_bytes"] / cg / 1e9
+        print(json.dumps({
+            "metric": "window-end transfer: atomistic sites coarse-grained per s (Eq. 6)",
+            "value": t["sites_cg"] / cg, "unit": "sites/s", "n_gpus": 1, "steps": t["reps"],
+            "warmup": 1, "ms_per_step": 1e3 * cg, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64",
+            "data": "synthetic",
+            "config": {"workload": "transfer_track16x800x200x33", "cell": t["cell"],
+                       "precision": args.precision},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_coarse_grain", "bytes_per_site": 3 * t["e"] + 2},
+            "thermalise_sites_per_s": t["sites_th"] / th,
+            "thermalise_roofline": {"bound": "hbm", "achieved": t["th_bytes"] / th / 1e9,
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": t["th_bytes"] / th / 1e9 / HBM_PEAK_GBS,
+                                    "kernel": "k_cone_columns",
+                                    "bytes_per_site": 2 * 3 * t["e"] + 2},
+        }), flush=True)
+        return
     r = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, args.graph_steps)
     if args.copy_calibration:
         import torch

@@ -256,58 +256,67 @@ int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, do
 }
 
 // ---------------------------------------------------------------- transfer
-// Eq. 6 read forwards (Sec. II): one workgroup per coarse cell sums the unit
-// spins of its magnetic sites in FP64 (sites in index order per thread,
-// threads in a fixed tree: the same result every run).
-constexpr int kXferBlock = 256;
+// Eq. 6 read forwards (Sec. II).  A workgroup takes kCgX neighbouring
+// coarse cells along x of one (j, k) layer; thread (tx, tz) sums, for cell
+// tx, the planes tz, tz + kCgZ, ... of the cell (rows in index order, each
+// row's sites contiguous, so neighbouring threads read neighbouring
+// memory), then thread tz = 0 adds the kCgZ partial sums in order: the same
+// FP64 result every run.
+constexpr int kCgX = 32, kCgZ = 8;
 
 template <typename T>
-__global__ __launch_bounds__(kXferBlock) void k_coarse_grain(TransferArgs a)
+__global__ __launch_bounds__(kCgX * kCgZ) void k_coarse_grain(TransferArgs a)
 {
-    const int c = blockIdx.x;
-    const int i = c % a.ncx, j = (c / a.ncx) % a.ncy, k = c / (a.ncx * a.ncy);
-    const int xb = a.x0 + i * a.cx, yb = j * a.cy, zb = k * a.cz;
-    const int wx = min(a.cx, a.x0 + a.ncols - xb), wy = min(a.cy, a.d.ny - yb),
-              wz = min(a.cz, a.d.nz - zb);
-    const int64_t n_in = (int64_t)a.per * wx * wy * wz;
-    const T *S = (const T *)a.S[0];
+    const int tx = threadIdx.x % kCgX, tz = threadIdx.x / kCgX;
+    const int i = blockIdx.x * kCgX + tx;
+    const int jk = blockIdx.y;
+    const int j = jk % a.ncy, k = jk / a.ncy;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t q = threadIdx.x; q < n_in; q += kXferBlock) {
-        const int s = (int)(q % a.per);
-        int64_t r = q / a.per;
-        const int xx = (int)(r % wx);
-        r /= wx;
-        const int yy = (int)(r % wy), zz = (int)(r / wy);
-        const int64_t site =
-            a.per * ((int64_t)(xb + xx) + (int64_t)a.d.sx * ((yb + yy) + (int64_t)a.d.ny * (zb + zz))) + s;
-        const int64_t g = a.d.base + site;
-        if (a.label[g] == kNoGrain) continue;
-        acc[0] += (double)S[g];
-        acc[1] += (double)S[a.ncs + g];
-        acc[2] += (double)S[2 * a.ncs + g];
-        acc[3] += 1.0;
+    if (i < a.ncx) {
+        const int xb = a.x0 + i * a.cx, yb = j * a.cy, zb = k * a.cz;
+        const int wx = min(a.cx, a.x0 + a.ncols - xb), wy = min(a.cy, a.d.ny - yb),
+                  wz = min(a.cz, a.d.nz - zb);
+        const T *S = (const T *)a.S[0];
+        const int nq = a.per * wx;
+        for (int zz = tz; zz < wz; zz += kCgZ)
+            for (int yy = 0; yy < wy; ++yy) {
+                const int64_t row =
+                    a.d.base + a.per * ((int64_t)xb + (int64_t)a.d.sx *
+                                                          ((yb + yy) + (int64_t)a.d.ny * (zb + zz)));
+                for (int q = 0; q < nq; ++q) {
+                    const int64_t g = row + q;
+                    if (a.label[g] == kNoGrain) continue;
+                    acc[0] += (double)S[g];
+                    acc[1] += (double)S[a.ncs + g];
+                    acc[2] += (double)S[2 * a.ncs + g];
+                    acc[3] += 1.0;
+                }
+            }
     }
-    __shared__ double red[4][kXferBlock];
-    for (int m = 0; m < 4; ++m) red[m][threadIdx.x] = acc[m];
+    __shared__ double red[4][kCgZ][kCgX];
+    for (int m = 0; m < 4; ++m) red[m][tz][tx] = acc[m];
     __syncthreads();
-    for (int off = kXferBlock / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off)
-            for (int m = 0; m < 4; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + off];
-        __syncthreads();
+    if (tz == 0 && i < a.ncx) {
+        const int64_t c = i + (int64_t)a.ncx * jk;
+        for (int m = 0; m < 4; ++m) {
+            double t = red[m][0][tx];
+            for (int z = 1; z < kCgZ; ++z) t += red[m][z][tx];
+            a.out[4 * c + m] = t;
+        }
     }
-    if (threadIdx.x == 0)
-        for (int m = 0; m < 4; ++m) a.out[4 * (int64_t)c + m] = red[m][0];
 }
 
 int launch_coarse_grain(const TransferArgs &a, void *stream)
 {
     if (a.ncell == 0) return 0;
+    const int ncz = a.ncell / (a.ncx * a.ncy);
+    const dim3 grid((a.ncx + kCgX - 1) / kCgX, a.ncy * ncz);
     if (a.prec == ASD_FP64)
-        hipLaunchKernelGGL(k_coarse_grain<double>, dim3(a.ncell), dim3(kXferBlock), 0,
-                           (hipStream_t)stream, a);
+        hipLaunchKernelGGL(k_coarse_grain<double>, grid, dim3(kCgX * kCgZ), 0, (hipStream_t)stream,
+                           a);
     else
-        hipLaunchKernelGGL(k_coarse_grain<float>, dim3(a.ncell), dim3(kXferBlock), 0,
-                           (hipStream_t)stream, a);
+        hipLaunchKernelGGL(k_coarse_grain<float>, grid, dim3(kCgX * kCgZ), 0, (hipStream_t)stream,
+                           a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
