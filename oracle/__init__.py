@@ -67,6 +67,7 @@ class OrcSystem(C.Structure):
         ("steps_per_bit", C.c_int64), ("spot_mode", C.c_int), ("T_amb", C.c_double),
         ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
         ("v", C.c_double), ("seed", C.c_uint64), ("rounds", C.c_int),
+        ("dn", C.c_int * 3), ("dd", C.c_double * 3), ("dcell", i32p),
     ]
 
 
@@ -91,6 +92,8 @@ def _declare(L):
     L.orc_energy.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int64, f64p]
     L.orc_coarse_grain.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p, f64p, f64p,
                                    C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
+    L.orc_newell_tensor.argtypes = [C.c_double] * 6 + [f64p]
+    L.orc_demag_direct.argtypes = [C.c_int] * 3 + [C.c_double] * 3 + [f64p, f64p]
     L.orc_cone_theta_max.argtypes = [C.c_double]
     L.orc_cone_theta_max.restype = C.c_double
     L.orc_cone_spin.argtypes = [f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -189,7 +192,7 @@ class System:
     def __init__(self, *, row_ptr, col, shell, label, px, py, ctr0, n_shells, J, mu_s, alpha,
                  gamma, dt, ku, ku_grain=None, B=(0.0, 0.0, 0.0), bits=None, steps_per_bit=0,
                  spot_mode=SPOT_NONE, T_amb=0.0, T_peak=0.0, fwhm=0.0, x0=0.0, y0=0.0, v=0.0,
-                 seed=1, rounds=10, sys_id=0, active=None, hx=0.0, origin=0):
+                 seed=1, rounds=10, sys_id=0, active=None, hx=0.0, origin=0, demag=None):
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.shell = np.ascontiguousarray(shell, dtype=np.int8)
@@ -224,6 +227,23 @@ class System:
         s.T_amb, s.T_peak, s.fwhm, s.x0, s.y0, s.v = T_amb, T_peak, fwhm, x0, y0, v
         s.seed, s.rounds = seed, rounds
         self._s = s
+        self.set_demag(demag)
+
+    def set_demag(self, demag):
+        """demag = (dn, dd, dcell): coarse mesh (cells along x, y, z), cell
+        edges (m) and the coarse cell of every site (-1 = none); None = off."""
+        s = self._s
+        if demag is None:
+            self.dcell = None
+            s.dn[0] = s.dn[1] = s.dn[2] = 0
+            s.dcell = _ptr(None, i32p)
+            return
+        dn, dd, dcell = demag
+        self.dcell = np.ascontiguousarray(dcell, dtype=np.int32)
+        assert len(self.dcell) == len(self.label)
+        for k in range(3):
+            s.dn[k], s.dd[k] = int(dn[k]), float(dd[k])
+        s.dcell = _ptr(self.dcell, i32p)
 
     def set_active(self, active, origin=None):
         self.active = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
@@ -256,6 +276,26 @@ class System:
         lib().orc_energy(C.byref(self._s), _ptr(Sx, f64p), _ptr(Sy, f64p), _ptr(Sz, f64p), step,
                          _ptr(out, f64p))
         return out
+
+
+# ---------------------------------------------------------------- demagnetising field (Eq. 7)
+MU0 = 1.25663706212e-6  # N/A^2 (CODATA 2018)
+
+
+def newell_tensor(X, Y, Z, dx, dy, dz) -> np.ndarray:
+    """Newell's cell-averaged demagnetising tensor (xx, yy, zz, xy, xz, yz)."""
+    out = np.zeros(6)
+    lib().orc_newell_tensor(X, Y, Z, dx, dy, dz, _ptr(out, f64p))
+    return out
+
+
+def demag_direct(M, nx, ny, nz, dx, dy, dz) -> np.ndarray:
+    """Eq. 7 by direct summation: M float[3, nx*ny*nz] (A/m) -> H (A/m)."""
+    M = np.ascontiguousarray(M, dtype=np.float64).reshape(3, -1)
+    assert M.shape[1] == nx * ny * nz
+    H = np.zeros_like(M)
+    lib().orc_demag_direct(nx, ny, nz, dx, dy, dz, _ptr(M, f64p), _ptr(H, f64p))
+    return H
 
 
 # ---------------------------------------------------------------- window-end transfer (Eq. 6)

@@ -24,7 +24,10 @@
  *   - Sec. II/III Zeeman write field with bit-timed polarity and a
  *             Gaussian laser-spot temperature profile (Fig. 2).
  *   - Sec. II Voronoi construction of exchange-decoupled grains.
- *   - Eq. 6   moment sums (used here as per-grain magnetisation sums).
+ *   - Eq. 6   moment sums (per-grain magnetisation sums, coarse cells of
+ *             the window-end transfer and of the demagnetising field).
+ *   - Eq. 7   demagnetising field on coarse cells, H = -sum N M, with
+ *             Newell's cell-averaged tensor, summed directly.
  *
  * Floating point: FP64, compiled with -ffp-contract=off.  The
  * transcendentals the noise and the temperature need (ln, sin/cos of
@@ -489,7 +492,7 @@ static int evolves(const orc_system *s, int64_t i)
 /* B at site i for spin configuration (Sx,Sy,Sz): Eq. 2 grouped by shell,
  * + Eq. 3 + write field + thermal field, in this order. */
 static void field(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
-                  int64_t i, double pol, const double bth[3], double B[3])
+                  int64_t i, double pol, const double bth[3], const double *bd, double B[3])
 {
     double acc[3] = {0.0, 0.0, 0.0};
     for (int sh = 0; sh < s->n_shells; ++sh) {
@@ -512,7 +515,16 @@ static void field(const orc_system *s, const double *Sx, const double *Sy, const
     double ban[3] = {0.0, 0.0, can * Sz[i]};
     for (int k = 0; k < 3; ++k)
         B[k] = ((acc[k] + ban[k]) + pol * s->B[k]) + bth[k];
+    /* demagnetising field of the site's coarse cell, evaluated from the same
+     * configuration as the exchange and anisotropy terms */
+    if (bd && s->dcell[i] >= 0) {
+        int64_t nc = (int64_t)s->dn[0] * s->dn[1] * s->dn[2];
+        for (int k = 0; k < 3; ++k) B[k] = B[k] + bd[k * nc + s->dcell[i]];
+    }
 }
+
+static int demag_cells(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+                       double *out);
 
 int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int64_t step0,
                    int64_t nsteps)
@@ -523,8 +535,10 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
     double *Pz = (double *)malloc(sizeof(double) * (size_t)n);
     double *f0 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     double *bth = (double *)malloc(sizeof(double) * 3 * (size_t)n);
-    if (!Px || !Py || !Pz || !f0 || !bth) {
-        free(Px); free(Py); free(Pz); free(f0); free(bth);
+    int64_t nc = s->dn[0] > 0 ? (int64_t)s->dn[0] * s->dn[1] * s->dn[2] : 0;
+    double *bd = nc ? (double *)malloc(sizeof(double) * 3 * (size_t)nc) : NULL;
+    if (!Px || !Py || !Pz || !f0 || !bth || (nc && !bd)) {
+        free(Px); free(Py); free(Pz); free(f0); free(bth); free(bd);
         return -1;
     }
     double gp = -s->gamma / (1.0 + s->alpha * s->alpha);
@@ -534,6 +548,10 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
     for (int64_t t = 0; t < nsteps; ++t) {
         int64_t step = step0 + t;
         double pol = polarity(s, step);
+        if (bd && demag_cells(s, Sx, Sy, Sz, bd) != 0) {
+            free(Px); free(Py); free(Pz); free(f0); free(bth); free(bd);
+            return -1;
+        }
         /* thermal field: one Gaussian triple per site and step */
         for (int64_t i = 0; i < n; ++i) {
             if (!evolves(s, i)) continue;
@@ -552,7 +570,7 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
                 continue;
             }
             double B[3], f[3], S[3] = {Sx[i], Sy[i], Sz[i]};
-            field(s, Sx, Sy, Sz, i, pol, bth + 3 * i, B);
+            field(s, Sx, Sy, Sz, i, pol, bth + 3 * i, bd, B);
             ll_rhs(gp, s->alpha, S, B, f);
             double P[3] = {S[0] + s->dt * f[0], S[1] + s->dt * f[1], S[2] + s->dt * f[2]};
             normalise(P);
@@ -560,10 +578,14 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
             f0[3 * i + 0] = f[0]; f0[3 * i + 1] = f[1]; f0[3 * i + 2] = f[2];
         }
         /* corrector with the predicted configuration and the same noise */
+        if (bd && demag_cells(s, Px, Py, Pz, bd) != 0) {
+            free(Px); free(Py); free(Pz); free(f0); free(bth); free(bd);
+            return -1;
+        }
         for (int64_t i = 0; i < n; ++i) {
             if (!evolves(s, i)) continue;
             double B[3], f[3], Sp[3] = {Px[i], Py[i], Pz[i]};
-            field(s, Px, Py, Pz, i, pol, bth + 3 * i, B);
+            field(s, Px, Py, Pz, i, pol, bth + 3 * i, bd, B);
             ll_rhs(gp, s->alpha, Sp, B, f);
             double Q[3] = {Sx[i] + h * (f0[3 * i + 0] + f[0]), Sy[i] + h * (f0[3 * i + 1] + f[1]),
                            Sz[i] + h * (f0[3 * i + 2] + f[2])};
@@ -571,7 +593,7 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
             Sx[i] = Q[0]; Sy[i] = Q[1]; Sz[i] = Q[2];
         }
     }
-    free(Px); free(Py); free(Pz); free(f0); free(bth);
+    free(Px); free(Py); free(Pz); free(f0); free(bth); free(bd);
     return 0;
 }
 
@@ -751,4 +773,137 @@ void orc_cone_columns(int kind, int sx, int ny, int nz, const int32_t *label, do
         Sy[i] = v[1];
         Sz[i] = v[2];
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Demagnetising field, Eq. 7: H_i = -sum_j N(r_j - r_i) M_j with the  */
+/* cell-averaged tensor of Newell, Williams and Dunlop, "A generalization */
+/* of the demagnetizing tensor for nonuniform magnetization", J.      */
+/* Geophys. Res. 98, 9551 (1993).  Each component is a 27-point       */
+/* second difference (per axis: -1, 2, -1 at -d, 0, +d) of an         */
+/* auxiliary function, divided by 4 pi times the cell volume:         */
+/* f for the diagonal, g for the off-diagonal terms.                  */
+/* ------------------------------------------------------------------ */
+#define ORC_MU0 1.25663706212e-6 /* vacuum permeability, N/A^2 (CODATA 2018) */
+#define ORC_PI 3.14159265358979323846
+
+/* Newell's f.  A term whose coefficient vanishes is left out, which also
+ * keeps its inverse hyperbolic sine or arctangent away from 0/0. */
+static double newell_f(double x, double y, double z)
+{
+    double x2 = x * x, y2 = y * y, z2 = z * z;
+    double R = sqrt(x2 + y2 + z2);
+    if (R == 0.0) return 0.0;
+    double t = ((2.0 * x2 - y2) - z2) * R / 6.0;
+    if (y != 0.0 && z2 != x2) t += 0.5 * y * (z2 - x2) * asinh(y / sqrt(x2 + z2));
+    if (z != 0.0 && y2 != x2) t += 0.5 * z * (y2 - x2) * asinh(z / sqrt(x2 + y2));
+    if (x != 0.0 && y != 0.0 && z != 0.0) t -= x * y * z * atan(y * z / (x * R));
+    return t;
+}
+
+/* Newell's g (off-diagonal xy term). */
+static double newell_g(double x, double y, double z)
+{
+    double x2 = x * x, y2 = y * y, z2 = z * z;
+    double R = sqrt(x2 + y2 + z2);
+    if (R == 0.0) return 0.0;
+    double t = -(x * y * R) / 3.0;
+    if (x != 0.0 && y != 0.0 && z != 0.0) t += x * y * z * asinh(z / sqrt(x2 + y2));
+    if (y != 0.0 && 3.0 * z2 != y2) t += y / 6.0 * (3.0 * z2 - y2) * asinh(x / sqrt(y2 + z2));
+    if (x != 0.0 && 3.0 * z2 != x2) t += x / 6.0 * (3.0 * z2 - x2) * asinh(y / sqrt(x2 + z2));
+    if (z != 0.0) {
+        t -= z * z2 / 6.0 * atan(x * y / (z * R));
+        if (y != 0.0) t -= z * y2 / 2.0 * atan(x * z / (y * R));
+        if (x != 0.0) t -= z * x2 / 2.0 * atan(y * z / (x * R));
+    }
+    return t;
+}
+
+/* sum over e in {-1,0,1}^3 of w(e) F(X + ex dx, Y + ey dy, Z + ez dz),
+ * w = product over the axes of (2 if e = 0, else -1), over 4 pi dx dy dz */
+static double newell_stencil(double (*F)(double, double, double), double X, double Y, double Z,
+                             double dx, double dy, double dz)
+{
+    double acc = 0.0;
+    for (int ex = -1; ex <= 1; ++ex)
+        for (int ey = -1; ey <= 1; ++ey)
+            for (int ez = -1; ez <= 1; ++ez) {
+                double w = (ex ? -1.0 : 2.0) * (ey ? -1.0 : 2.0) * (ez ? -1.0 : 2.0);
+                acc += w * F(X + ex * dx, Y + ey * dy, Z + ez * dz);
+            }
+    return acc / (4.0 * ORC_PI * dx * dy * dz);
+}
+
+/* N_yy, N_zz follow from N_xx and N_xz, N_yz from N_xy by relabelling the
+ * axes (coordinates and cell edges together). */
+void orc_newell_tensor(double X, double Y, double Z, double dx, double dy, double dz, double N[6])
+{
+    N[0] = newell_stencil(newell_f, X, Y, Z, dx, dy, dz); /* xx */
+    N[1] = newell_stencil(newell_f, Y, X, Z, dy, dx, dz); /* yy */
+    N[2] = newell_stencil(newell_f, Z, Y, X, dz, dy, dx); /* zz */
+    N[3] = newell_stencil(newell_g, X, Y, Z, dx, dy, dz); /* xy */
+    N[4] = newell_stencil(newell_g, X, Z, Y, dx, dz, dy); /* xz */
+    N[5] = newell_stencil(newell_g, Y, Z, X, dy, dz, dx); /* yz */
+}
+
+/* Eq. 7 summed directly.  The tensor depends only on the displacement, so
+ * it is evaluated once per displacement (index (ix, iy, iz) + (n - 1)). */
+void orc_demag_direct(int nx, int ny, int nz, double dx, double dy, double dz, const double *M,
+                      double *H)
+{
+    int64_t n = (int64_t)nx * ny * nz;
+    int64_t tx = 2 * nx - 1, ty = 2 * ny - 1, tz = 2 * nz - 1;
+    double *T = (double *)malloc(sizeof(double) * 6 * (size_t)(tx * ty * tz));
+    if (!T) return;
+    for (int64_t kz = 0; kz < tz; ++kz)
+        for (int64_t ky = 0; ky < ty; ++ky)
+            for (int64_t kx = 0; kx < tx; ++kx)
+                orc_newell_tensor((double)(kx - (nx - 1)) * dx, (double)(ky - (ny - 1)) * dy,
+                                  (double)(kz - (nz - 1)) * dz, dx, dy, dz,
+                                  T + 6 * (kx + tx * (ky + ty * kz)));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ix = i % nx, iy = (i / nx) % ny, iz = i / ((int64_t)nx * ny);
+        double h[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t jx = j % nx, jy = (j / nx) % ny, jz = j / ((int64_t)nx * ny);
+            const double *N = T + 6 * ((jx - ix + nx - 1) + tx * ((jy - iy + ny - 1) +
+                                                                   ty * (jz - iz + nz - 1)));
+            double mx = M[j], my = M[n + j], mz = M[2 * n + j];
+            h[0] -= (N[0] * mx + N[3] * my) + N[4] * mz;
+            h[1] -= (N[3] * mx + N[1] * my) + N[5] * mz;
+            h[2] -= (N[4] * mx + N[5] * my) + N[2] * mz;
+        }
+        H[i] = h[0];
+        H[n + i] = h[1];
+        H[2 * n + i] = h[2];
+    }
+    free(T);
+}
+
+/* The demagnetising flux density mu0 H_d (T) per coarse cell of the evolving
+ * magnetic sites: Eq. 6 (M = mu_s sum m / V) then Eq. 7.  out [3][ncell]. */
+static int demag_cells(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+                       double *out)
+{
+    int64_t nc = (int64_t)s->dn[0] * s->dn[1] * s->dn[2];
+    double *M = (double *)calloc(3 * (size_t)nc, sizeof(double));
+    double *H = (double *)malloc(sizeof(double) * 3 * (size_t)nc);
+    if (!M || !H) {
+        free(M); free(H);
+        return -1;
+    }
+    for (int64_t i = 0; i < s->n_sites; ++i) {
+        if (!evolves(s, i) || s->dcell[i] < 0) continue;
+        int64_t c = s->dcell[i];
+        M[c] += Sx[i];
+        M[nc + c] += Sy[i];
+        M[2 * nc + c] += Sz[i];
+    }
+    double k = s->mu_s / ((s->dd[0] * s->dd[1]) * s->dd[2]);
+    for (int64_t c = 0; c < 3 * nc; ++c) M[c] = k * M[c];
+    orc_demag_direct(s->dn[0], s->dn[1], s->dn[2], s->dd[0], s->dd[1], s->dd[2], M, H);
+    for (int64_t c = 0; c < 3 * nc; ++c) out[c] = ORC_MU0 * H[c];
+    free(M);
+    free(H);
+    return 0;
 }

@@ -50,6 +50,12 @@ typedef struct orc_system {
     /* noise */
     uint64_t seed;
     int rounds;
+    /* demagnetising field of the evolving sites (Eq. 7 on the coarse cells
+     * of Eq. 6), evaluated at both Heun stages from that stage's spins;
+     * dcell[i] = coarse cell of site i or -1; dn[0] = 0 switches it off */
+    int dn[3];              /* coarse mesh, cells along x, y, z */
+    double dd[3];           /* coarse cell edges (m) */
+    const int32_t *dcell;
 } orc_system;
 
 void orc_philox4x32(int rounds, uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4]);
@@ -88,6 +94,14 @@ void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t sit
 void orc_cone_columns(int kind, int sx, int ny, int nz, const int32_t *label, double *Sx,
                       double *Sy, double *Sz, int x0, int ncols, int cx, int cy, int cz,
                       const double *mcell, int rounds, uint64_t seed, uint32_t step, uint32_t sys);
+/* demagnetising tensor (Newell, Williams, Dunlop 1993) between two cells
+ * of edges (dx, dy, dz) displaced by (X, Y, Z); N = (xx, yy, zz, xy, xz, yz) */
+void orc_newell_tensor(double X, double Y, double Z, double dx, double dy, double dz,
+                       double N[6]);
+/* Eq. 7 by direct summation on a mesh of nx*ny*nz cells (x fastest):
+ * H_i = -sum_j N(r_j - r_i) M_j, M and H [3][n] in A/m */
+void orc_demag_direct(int nx, int ny, int nz, double dx, double dy, double dz, const double *M,
+                      double *H);
 void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                 int64_t step, double out[4]);
 
