@@ -101,6 +101,13 @@ typedef struct asd_params {
     int32_t kernel;        /* ASD_KERNEL_* */
     int32_t graph_steps;   /* >0: capture segments of this many steps (even)
                               in HIP graphs; 0: launch every step eagerly */
+    int32_t demag_cell[3]; /* all > 0: add the demagnetising field of the window
+                              (Eq. 7, Newell's tensor, open boundaries) on coarse
+                              cells of demag_cell[0] x [1] x [2] lattice cells
+                              (Eq. 6), evaluated at both Heun stages; all 0: off.
+                              Needs every system to have the same window size,
+                              at most 256 coarse cells per axis, and the
+                              two-pass kernels (ASD_KERNEL_PLAIN or AUTO) */
 } asd_params;
 
 /* One lattice (one system).  A handle steps all its systems together. */
@@ -260,6 +267,16 @@ int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int
                            int32_t cy, int32_t cz, const double *mcell, uint32_t step);
 
 /* Step counter and window origin of system sys (host copies). */
+/* Demagnetising field (Eq. 7) of the current spins of every system, as
+ * the flux density mu0 H_d (T) per coarse cell: per_cell is a host array
+ * [n_sys][3][ncell] (cells numbered x fastest over the window,
+ * c = i + ncx (j + ncy k)); mesh (optional, host int32[3]) receives
+ * (ncx, ncy, ncz).  Coarse cell moment M = mu_s (sum of unit spins) / V
+ * with V the full cell volume (Eq. 6); ragged cells at the far window
+ * faces count their sites against the same V.  Synchronises the stream.
+ * ASD_ESTATE when the handle was created without demag_cell. */
+int asd_demag_field(asd_t *h, double *per_cell, int32_t *mesh);
+
 int asd_get_state(asd_t *h, int32_t sys, int64_t *step, int32_t *origin);
 /* Set the step counter (resume from a checkpoint). */
 int asd_set_step(asd_t *h, int64_t step);
@@ -279,7 +296,9 @@ int asd_autotune(asd_t *h, const char *cache_path);
  * kernels return ASD_EUNSUPPORTED (the handle keeps its variant) for a
  * system whose spins exceed 2 GiB per component, or when the anisotropy
  * varies per grain and some stored column crosses grains (labels varying
- * along z); the two-pass kernels take every system.  Drops captured graphs. */
+ * along z), or when the handle adds the demagnetising field (a whole-mesh
+ * convolution between the two Heun stages); the two-pass kernels take every
+ * system.  Drops captured graphs. */
 int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile);
 int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile);
 /* Number of tile variants of a kernel family for this handle's lattice and

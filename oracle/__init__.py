@@ -298,6 +298,20 @@ def demag_direct(M, nx, ny, nz, dx, dy, dz) -> np.ndarray:
     return H
 
 
+def demag_field(S, dcell, dn, dd, mu_s) -> np.ndarray:
+    """mu0 H_d (T) per coarse cell, float[3, ncell]: Eq. 6 (M = mu_s sum m / V over
+    the sites with dcell = c) then Eq. 7 by direct summation."""
+    S = np.asarray(S, dtype=np.float64).reshape(3, -1)
+    dcell = np.asarray(dcell)
+    nc = int(dn[0] * dn[1] * dn[2])
+    M = np.zeros((3, nc))
+    sel = dcell >= 0
+    for k in range(3):
+        np.add.at(M[k], dcell[sel], S[k, sel])
+    M *= mu_s / (dd[0] * dd[1] * dd[2])
+    return MU0 * demag_direct(M, int(dn[0]), int(dn[1]), int(dn[2]), *dd)
+
+
 # ---------------------------------------------------------------- window-end transfer (Eq. 6)
 def coarse_cells(ncols: int, ny: int, nz: int, cx: int, cy: int, cz: int) -> int:
     return -(-ncols // cx) * -(-ny // cy) * -(-nz // cz)

@@ -29,7 +29,7 @@ SYMBOLS = [
     "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
     "asd_neighbour_count", "asd_get_neighbours", "asd_host_grain_labels", "asd_host_neighbours",
-    "asd_coarse_grain", "asd_thermalise_columns",
+    "asd_coarse_grain", "asd_thermalise_columns", "asd_demag_field",
     "asd_get_state", "asd_set_step", "asd_philox",
     "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_count", "asd_variant_name",
     "asd_strerror",
@@ -48,7 +48,8 @@ class asd_params(C.Structure):
                 ("c", C.c_double), ("n_shells", C.c_int32), ("J", C.c_double * 4),
                 ("mu_s", C.c_double), ("alpha", C.c_double), ("gamma", C.c_double),
                 ("dt", C.c_double), ("k_u", C.c_double), ("seed", C.c_uint64),
-                ("philox_rounds", C.c_int32), ("kernel", C.c_int32), ("graph_steps", C.c_int32)]
+                ("philox_rounds", C.c_int32), ("kernel", C.c_int32), ("graph_steps", C.c_int32),
+                ("demag_cell", C.c_int32 * 3)]
 
 
 class asd_system_desc(C.Structure):
@@ -110,6 +111,7 @@ def lib():
                                        C.c_int32, vp]
         L.asd_thermalise_columns.argtypes = [h, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                              C.c_int32, C.c_int32, vp, C.c_uint32]
+        L.asd_demag_field.argtypes = [h, vp, vp]
         L.asd_variant_count.argtypes = [h, C.c_int32, P(C.c_int32)]
         L.asd_variant_name.argtypes = [h, C.c_char_p, C.c_size_t]
         L.asd_strerror.argtypes = [C.c_int]
@@ -328,6 +330,18 @@ class Handle:
         _check(lib().asd_thermalise_columns(self.h, sys, x0, ncols, cx, cy, cz, m.data_ptr(),
                                             step), self.h)
         self.stream.synchronize()
+
+    def demag_field(self):
+        """Demagnetising flux density mu0 H_d (T) of the current spins per coarse
+        cell: float64 [n_sys, 3, ncell], and the mesh (ncx, ncy, ncz)."""
+        p = self.params
+        cx, cy, cz = (int(v) for v in p.demag_cell)
+        d = self.systems[0]
+        ncell = -(-d.nx // cx) * -(-d.ny // cy) * -(-d.nz // cz) if cx else 0
+        out = np.zeros((len(self.systems), 3, max(ncell, 1)))
+        mesh = np.zeros(3, dtype=np.int32)
+        _check(lib().asd_demag_field(self.h, out.ctypes.data, mesh.ctypes.data), self.h)
+        return out[:, :, :ncell], tuple(int(v) for v in mesh)
 
     def shift_window(self, columns: int):
         asd_shift_window(self.h, columns)

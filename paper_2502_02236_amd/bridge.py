@@ -9,7 +9,7 @@ from . import asd as A
 
 
 def params_for(w: W.Workload, precision: int, kernel: int = A.ASD_KERNEL_PLAIN,
-               graph_steps: int = 0, rounds: int = 10) -> A.asd_params:
+               graph_steps: int = 0, rounds: int = 10, demag_cell=(0, 0, 0)) -> A.asd_params:
     p = A.asd_params()
     p.lattice = A.ASD_SC if w.kind == W.SC else A.ASD_L10
     p.precision = precision
@@ -22,6 +22,8 @@ def params_for(w: W.Workload, precision: int, kernel: int = A.ASD_KERNEL_PLAIN,
     p.philox_rounds = rounds
     p.kernel = kernel
     p.graph_steps = graph_steps
+    for k in range(3):
+        p.demag_cell[k] = demag_cell[k]
     return p
 
 
@@ -73,10 +75,11 @@ def drive_for(w: W.Workload, T_amb=None) -> tuple:
 
 def make_handle(w: W.Workload, precision: int, kernel: int = A.ASD_KERNEL_PLAIN, graph_steps=0,
                 n_systems: int = 1, seeds=None, labels=None, ku_grain=None, T_amb=None,
-                device="cuda:0") -> A.Handle:
+                device="cuda:0", demag_cell=(0, 0, 0)) -> A.Handle:
     """A handle stepping n_systems copies of workload w (same grains, system ids 0..n-1)."""
     ins = [SystemInputs(w, seeds=seeds, labels=labels, ku_grain=ku_grain) for _ in range(n_systems)]
-    h = A.Handle(params_for(w, precision, kernel, graph_steps), [i.desc for i in ins], device=device)
+    h = A.Handle(params_for(w, precision, kernel, graph_steps, demag_cell=demag_cell),
+                 [i.desc for i in ins], device=device)
     dr, bits = drive_for(w, T_amb)
     h.set_drive(dr)
     h._inputs = ins

@@ -28,10 +28,13 @@ SOURCES = [
     ("asd_step_f64.hip", ["-ffp-contract=off"]),
     ("asd_step_f32.hip", ["-ffp-contract=fast"]),
     ("asd_misc.hip", ["-ffp-contract=off"]),
+    ("asd_demag.hip", ["-ffp-contract=fast"]),
     ("asd_host.cpp", ["-ffp-contract=off"]),
+    ("asd_demag_tensor.cpp", ["-ffp-contract=off"]),
 ]
 
-HEADERS = ["asd_device.h", "asd_internal.h", "asd_step.inc", "asd_fused.inc"]
+HEADERS = ["asd_device.h", "asd_internal.h", "asd_step.inc", "asd_fused.inc", "asd_fused_l10.inc",
+           "asd_variants.h"]
 
 
 def hipcc() -> str:

@@ -22,6 +22,7 @@ using namespace asd;
 namespace {
 
 constexpr double kBoltzmann = 1.380649e-23;  // J/K (exact SI)
+constexpr double kMu0 = 1.25663706212e-6;     // vacuum permeability, N/A^2 (CODATA 2018)
 constexpr size_t kAlign = 256;
 constexpr int kMaxBits = 1 << 16;
 
@@ -61,6 +62,9 @@ struct Layout {
     size_t off_label = 0, off_ell = 0, off_sys = 0, off_tile = 0, off_ftile = 0, off_can = 0,
            off_ku = 0, off_gsys = 0, off_gptr = 0, off_gsites = 0, off_step = 0, off_origin = 0,
            off_bits = 0, off_gout = 0, off_sout = 0, off_mom = 0, off_epart = 0, off_eout = 0;
+    // demagnetising field (when asd_params.demag_cell is set)
+    DemagDev dm{};            // geometry; pointers filled at create
+    size_t off_dwx = 0, off_dwy = 0, off_dbd[2] = {0, 0}, off_dK = 0, off_dtw[3] = {0, 0, 0};
     size_t bytes = 0;
 };
 
@@ -87,6 +91,7 @@ struct asd_t {
     int graph_steps = 0;
     int graph_kernel = -1, graph_tile = -1;
     int n_ftiles = 0;         // fused tiles of the current variant
+    DemagDev dm{};            // demagnetising field (dm.on = 0: none)
 };
 
 static thread_local std::string g_err;
@@ -378,6 +383,56 @@ static FastDivH host_fastdiv(uint32_t d)
     return f;
 }
 
+static int ilog2_ceil(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+// coarse mesh and padded FFT sizes of the demagnetising field; nullptr when
+// the descriptors allow it, else the reason
+static const char *demag_geometry(const asd_params *p, const asd_system_desc *sys, int n_sys,
+                                  DemagDev *g)
+{
+    std::memset(g, 0, sizeof *g);
+    const int32_t *c = p->demag_cell;
+    if (c[0] == 0 && c[1] == 0 && c[2] == 0) return nullptr;
+    if (c[0] < 1 || c[1] < 1 || c[2] < 1) return "demag_cell must be all positive or all zero";
+    for (int s = 1; s < n_sys; ++s)
+        if (sys[s].nx != sys[0].nx || sys[s].ny != sys[0].ny || sys[s].nz != sys[0].nz)
+            return "the demagnetising field needs every system to have the same window size";
+    g->on = 1;
+    g->cx = c[0];
+    g->cy = c[1];
+    g->cz = c[2];
+    g->ncx = (sys[0].nx + c[0] - 1) / c[0];
+    g->ncy = (sys[0].ny + c[1] - 1) / c[1];
+    g->ncz = (sys[0].nz + c[2] - 1) / c[2];
+    if (g->ncx > 256 || g->ncy > 256 || g->ncz > 256)
+        return "the demagnetising mesh is limited to 256 coarse cells per axis";
+    g->ncell = g->ncx * g->ncy * g->ncz;
+    // zero padding to a power of two >= 2 n - 1 (none for a single cell)
+    g->lx = ilog2_ceil(2 * g->ncx - 1);
+    g->ly = ilog2_ceil(2 * g->ncy - 1);
+    g->lz = ilog2_ceil(2 * g->ncz - 1);
+    // lines per workgroup of the y and z passes: LDS of two buffers of
+    // at most 1024 (FP64) / 2048 (FP32) complex values
+    const int budget = p->precision == ASD_FP64 ? 1024 : 2048;
+    const int Px = 1 << g->lx, Py = 1 << g->ly, Pz = 1 << g->lz;
+    int xb = 1;
+    while (xb * 2 <= Px && xb * 2 * Py <= budget) xb *= 2;
+    g->xb_y = xb;
+    xb = 1;
+    while (xb * 2 <= Px && xb * 2 * 3 * Pz <= budget) xb *= 2;
+    g->xb_z = xb;
+    g->n_sys = n_sys;
+    g->fd_cx = host_fastdiv((uint32_t)c[0]);
+    g->fd_cy = host_fastdiv((uint32_t)c[1]);
+    g->fd_cz = host_fastdiv((uint32_t)c[2]);
+    return nullptr;
+}
+
 static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n_sys)
 {
     Layout L;
@@ -434,6 +489,19 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
     L.off_mom = take((size_t)n_sys * 5 * sizeof(double));
     L.off_epart = take((size_t)std::max(tiles, 1) * 3 * sizeof(double));
     L.off_eout = take((size_t)n_sys * 4 * sizeof(double));
+    (void)demag_geometry(p, sys, n_sys, &L.dm);
+    if (L.dm.on) {
+        const DemagDev &g = L.dm;
+        const size_t Px = (size_t)1 << g.lx, Py = (size_t)1 << g.ly, Pz = (size_t)1 << g.lz;
+        const size_t cplx = 2 * elem;
+        L.off_dwx = take((size_t)n_sys * 3 * g.ncz * g.ncy * Px * cplx);
+        L.off_dwy = take((size_t)n_sys * 3 * g.ncz * Py * Px * cplx);
+        for (int b = 0; b < 2; ++b) L.off_dbd[b] = take((size_t)n_sys * 3 * g.ncell * elem);
+        L.off_dK = take(6 * (Px / 2 + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * elem);
+        L.off_dtw[0] = take(std::max<size_t>(Px / 2, 1) * cplx);
+        L.off_dtw[1] = take(std::max<size_t>(Py / 2, 1) * cplx);
+        L.off_dtw[2] = take(std::max<size_t>(Pz / 2, 1) * cplx);
+    }
     L.bytes = off;
     return L;
 }
@@ -465,6 +533,11 @@ int asd_workspace_bytes(const asd_params *p, const asd_system_desc *sys, int32_t
     if (!sys || n_sys < 1 || !bytes) return fail(nullptr, ASD_EINVAL, "need >= 1 system and bytes");
     for (int s = 0; s < n_sys; ++s)
         if ((rc = check_system(p, &sys[s], s))) return rc;
+    DemagDev g;
+    if (const char *why = demag_geometry(p, sys, n_sys, &g)) {
+        const bool bad_arg = std::strstr(why, "must") != nullptr;
+        return fail(nullptr, bad_arg ? ASD_EINVAL : ASD_EUNSUPPORTED, "%s", why);
+    }
     *bytes = make_layout(p, sys, n_sys).bytes;
     return ASD_OK;
 }
@@ -641,6 +714,48 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
             HIP_OK(h, hipMemcpyAsync(w + L.off_S[b], S.data(), S.size(), hipMemcpyHostToDevice, st));
         HIP_OK(h, hipStreamSynchronize(st));
     }
+    if (L.dm.on) {
+        // demagnetising field: tensor spectrum and twiddles (host FP64)
+        DemagDev g = L.dm;
+        const double ex = p->a, ey = p->a, ez = p->lattice == ASD_SC ? p->a : p->c;
+        const double dx = g.cx * ex, dy = g.cy * ey, dz = g.cz * ez;
+        const int Px = 1 << g.lx, Py = 1 << g.ly, Pz = 1 << g.lz;
+        const double scale = -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)Px * Py * Pz));
+        std::vector<double> oct;
+        demag_spectrum(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly, g.lz, scale, oct);
+        std::vector<char> buf(oct.size() * h->elem);
+        for (size_t i = 0; i < oct.size(); ++i) {
+            if (h->elem == 8) ((double *)buf.data())[i] = oct[i];
+            else ((float *)buf.data())[i] = (float)oct[i];
+        }
+        HIP_OK(h, hipMemcpyAsync(w + L.off_dK, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
+        std::vector<std::vector<char>> tw(3);
+        const int lp[3] = {g.lx, g.ly, g.lz};
+        for (int ax = 0; ax < 3; ++ax) {
+            const int P = 1 << lp[ax], half = std::max(P / 2, 1);
+            tw[ax].resize((size_t)half * 2 * h->elem);
+            for (int t = 0; t < half; ++t) {
+                const double ang = -2.0 * M_PI * (double)t / (double)P;
+                if (h->elem == 8) {
+                    ((double *)tw[ax].data())[2 * t] = std::cos(ang);
+                    ((double *)tw[ax].data())[2 * t + 1] = std::sin(ang);
+                } else {
+                    ((float *)tw[ax].data())[2 * t] = (float)std::cos(ang);
+                    ((float *)tw[ax].data())[2 * t + 1] = (float)std::sin(ang);
+                }
+            }
+            HIP_OK(h, hipMemcpyAsync(w + L.off_dtw[ax], tw[ax].data(), tw[ax].size(),
+                                     hipMemcpyHostToDevice, st));
+        }
+        g.wx = w + L.off_dwx;
+        g.wy = w + L.off_dwy;
+        g.bd[0] = w + L.off_dbd[0];
+        g.bd[1] = w + L.off_dbd[1];
+        g.K = w + L.off_dK;
+        for (int ax = 0; ax < 3; ++ax) g.tw[ax] = w + L.off_dtw[ax];
+        h->dm = g;
+        HIP_OK(h, hipStreamSynchronize(st));
+    }
     h->drive = asd_drive{};
     int r2 = upload_sysdev(h);
     if (r2) {
@@ -800,6 +915,7 @@ static StepArgs<T> make_args(const asd_t *h, int cur, int step_off)
     for (const HostSys &hs : h->sys)
         if (hs.desc.bc_z == ASD_BC_PERIODIC) a.any_zper = 1;
     a.c = make_consts(h);
+    a.dm = h->dm;
     return a;
 }
 
@@ -1182,6 +1298,37 @@ int asd_thermalise_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32
     return ASD_OK;
 }
 
+int asd_demag_field(asd_t *h, double *per_cell, int32_t *mesh)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (!h->dm.on) return fail(h, ASD_ESTATE, "the handle has no demagnetising field");
+    if (!per_cell) return fail(h, ASD_EINVAL, "per_cell is NULL");
+    const DemagDev &g = h->dm;
+    const char *w = h->ws;
+    const size_t n = (size_t)g.n_sys * 3 * g.ncell;
+    int rc;
+    if (h->elem == 8)
+        rc = launch_demag(g, (const double *)(w + h->L.off_S[h->cur]), h->L.ncs,
+                          (const SysDev *)(w + h->L.off_sys), (const int32_t *)(w + h->L.off_origin),
+                          0, h->stream);
+    else
+        rc = launch_demag(g, (const float *)(w + h->L.off_S[h->cur]), h->L.ncs,
+                          (const SysDev *)(w + h->L.off_sys), (const int32_t *)(w + h->L.off_origin),
+                          0, h->stream);
+    if (rc) return fail(h, ASD_EHIP, "demag launch failed: %s", hipGetErrorString(hipGetLastError()));
+    std::vector<char> buf(n * h->elem);
+    HIP_OK(h, hipMemcpyAsync(buf.data(), g.bd[0], buf.size(), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i < n; ++i)
+        per_cell[i] = h->elem == 8 ? ((const double *)buf.data())[i] : (double)((const float *)buf.data())[i];
+    if (mesh) {
+        mesh[0] = g.ncx;
+        mesh[1] = g.ncy;
+        mesh[2] = g.ncz;
+    }
+    return ASD_OK;
+}
+
 int asd_get_state(asd_t *h, int32_t s, int64_t *step, int32_t *origin)
 {
     if (!h || s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad argument");
@@ -1213,6 +1360,9 @@ int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out
 // reason the fused kernel cannot serve this handle, or NULL
 static const char *fused_unsupported(const asd_t *h)
 {
+    if (h->dm.on)
+        return "the demagnetising field is a whole-mesh convolution between the two Heun "
+               "stages; the fused kernels run both stages in one launch";
     const int64_t elem = h->p.precision == ASD_FP64 ? 8 : 4;
     for (const HostSys &hs : h->sys) {
         if (hs.desc.bc_z != ASD_BC_OPEN && hs.desc.bc_z != ASD_BC_PERIODIC)

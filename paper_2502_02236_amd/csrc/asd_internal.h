@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace asd {
 
 struct FastDivH {            // mirror of the device FastDiv (d, multiplier, shift)
@@ -55,6 +57,25 @@ struct StepConsts {
     int32_t pad;
 };
 
+// Demagnetising field (Eq. 7) of every system's window on a coarse mesh of
+// cx x cy x cz lattice cells (Eq. 6), by zero-padded FFT convolution.  All
+// systems share the window size, so they share the mesh and the tensor.
+struct DemagDev {
+    int32_t on;               // 0: no demagnetising field
+    int32_t cx, cy, cz;       // lattice cells per coarse cell
+    int32_t ncx, ncy, ncz;    // coarse cells per axis (last ones ragged)
+    int32_t ncell;            // ncx * ncy * ncz
+    int32_t lx, ly, lz;       // log2 of the padded sizes Px, Py, Pz
+    int32_t xb_y, xb_z;       // x lines per workgroup in the y and z passes
+    int32_t n_sys;
+    FastDivH fd_cx, fd_cy, fd_cz;
+    void *wx;                 // complex [S][3][ncz][ncy][Px]
+    void *wy;                 // complex [S][3][ncz][Py][Px]
+    void *bd[2];              // field (T) per coarse cell, [S][3][ncell], one per Heun stage
+    const void *K;            // tensor spectrum, octant [6][Pz/2+1][Py/2+1][Px/2+1]
+    const void *tw[3];        // twiddles exp(-2 pi i t / P), t < P / 2, per axis
+};
+
 template <typename T>
 struct StepArgs {
     const T *S;               // current spins [3][ncs]
@@ -79,7 +100,27 @@ struct StepArgs {
     int32_t lattice;          // ASD_SC / ASD_L10
     int32_t any_zper;         // some system is periodic along z
     StepConsts c;
+    DemagDev dm;
 };
+
+// demagnetising field of spins S (both [3][ncs]) into dm.bd[stage]
+int launch_demag_f64(const DemagDev &dm, const double *S, int64_t ncs, const SysDev *sys,
+                     const int32_t *origin, int stage, void *stream);
+int launch_demag_f32(const DemagDev &dm, const float *S, int64_t ncs, const SysDev *sys,
+                     const int32_t *origin, int stage, void *stream);
+inline int launch_demag(const DemagDev &dm, const double *S, int64_t ncs, const SysDev *sys,
+                        const int32_t *origin, int stage, void *stream)
+{
+    return launch_demag_f64(dm, S, ncs, sys, origin, stage, stream);
+}
+inline int launch_demag(const DemagDev &dm, const float *S, int64_t ncs, const SysDev *sys,
+                        const int32_t *origin, int stage, void *stream)
+{
+    return launch_demag_f32(dm, S, ncs, sys, origin, stage, stream);
+}
+// host set-up (asd_demag_tensor.cpp): tensor spectrum octant, times scale
+void demag_spectrum(int ncx, int ncy, int ncz, double dx, double dy, double dz, int lx, int ly,
+                    int lz, double scale, std::vector<double> &octant);
 
 // launchers (asd_step_f64.hip / asd_step_f32.hip)
 int launch_plain_step_f64(const StepArgs<double> &a, int n_blocks, void *stream);

@@ -59,3 +59,21 @@ def free_spins_system(n: int, *, mu_s, alpha, gamma, dt, ku, B, T, seed=7, sys_i
         ctr0=np.arange(n, dtype=np.uint32), n_shells=0, J=(), mu_s=mu_s, alpha=alpha,
         gamma=gamma, dt=dt, ku=ku, B=B, spot_mode=oracle.SPOT_NONE, T_amb=T, seed=seed,
         sys_id=sys_id)
+
+
+def demag_cells(w: W.Workload, cell, origin: int = 0):
+    """(dn, dd, dcell) of the demagnetising mesh of the window: coarse cells of
+    cell[0] x cell[1] x cell[2] lattice cells in the window frame, numbered x
+    fastest; dcell = -1 for stored sites outside the window."""
+    nx = w.track_nx or w.nx
+    n = oracle.lattice_sites(w.kind, nx, w.ny, w.nz)
+    idx = np.arange(n)
+    lc = idx if w.kind == W.SC else idx // 2
+    x, y, z = lc % nx - origin, (lc // nx) % w.ny, lc // (nx * w.ny)
+    cx, cy, cz = cell
+    dn = (-(-w.nx // cx), -(-w.ny // cy), -(-w.nz // cz))
+    zc = w.a if w.kind == W.SC else w.c
+    dd = (cx * w.a, cy * w.a, cz * zc)
+    inwin = (x >= 0) & (x < w.nx)
+    dcell = np.where(inwin, x // cx + dn[0] * (y // cy + dn[1] * (z // cz)), -1).astype(np.int32)
+    return dn, dd, dcell

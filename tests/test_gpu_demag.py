@@ -1,0 +1,221 @@
+"""GPU parity of the demagnetising field (Eq. 7 on the coarse cells of Eq. 6).
+
+The library convolves by zero-padded FFTs with the spectrum of Newell's tensor;
+the oracle sums Eq. 7 directly.  Bars:
+  * the field per coarse cell: FP64 within 1e-11 of mu0 Ms, FP32 within 5e-7 of
+    mu0 Ms.  The FP64 bar is set by the tensor itself: each entry is a 27-term
+    difference of Newell's functions, whose terms grow like R^3 while the entry
+    falls like R^-3, so two correct evaluations in a different order differ by
+    ~27 eps (R/d)^3 / 4 pi per entry: ~1e-14 at the R <= 10 cells of these
+    meshes, summed over at most a few hundred cells.  FP32: the cell sums
+    and log2(P) radix-2 stages each round at ~6e-8 relative.
+  * spins after Heun steps with the field: the FP64 and FP32 bars of the
+    other parity tests (1e-12, 1e-4 per component).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle_build import demag_cells, oracle_labels, oracle_system, window_mask
+from paper_2502_02236_amd import asd as A
+from paper_2502_02236_amd import bridge
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = {A.ASD_FP64: 1e-11, A.ASD_FP32: 5e-7}
+SPIN_TOL = {A.ASD_FP64: 1e-12, A.ASD_FP32: 1e-4}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    A.lib()
+    return torch
+
+
+def mu0_ms(w):
+    zc = w.a if w.kind == W.SC else w.c
+    per = 1 if w.kind == W.SC else 2
+    return oracle.MU0 * w.mu_s * per / (w.a * w.a * zc)
+
+
+def sc_slab(**kw):
+    w = W.c2_granular_slab().scaled(nx=37, ny=29, nz=7, x0=5e-9, y0=4e-9, grain_pitch=4.0e-9,
+                                    steps=40)
+    return w.scaled(**kw)
+
+
+def l10_slab(**kw):
+    w = W.c3_l10_window().scaled(nx=13, ny=11, nz=6, x0=2e-9, y0=2e-9, grain_pitch=3.0e-9,
+                                 steps=40)
+    return w.scaled(**kw)
+
+
+def track(**kw):
+    w = W.c5_track_window().scaled(nx=30, ny=20, nz=5, track_nx=48, steps_per_bit=25,
+                                   x0=4.5e-9, y0=3e-9, grain_pitch=3.0e-9)
+    return w.scaled(**kw)
+
+
+# (name, workload, coarse cell, systems)
+FIELD_CASES = [
+    ("sc_4x4x2_ragged", sc_slab(), (4, 4, 2), 1),
+    ("sc_1x1x1_atomistic", sc_slab(nx=9, ny=7, nz=4), (1, 1, 1), 1),
+    ("sc_single_layer", sc_slab(), (5, 3, 7), 2),
+    ("sc_one_cell", sc_slab(nx=8, ny=6, nz=3), (8, 6, 3), 1),
+    ("l10_3x3x2", l10_slab(), (3, 3, 2), 2),
+    ("track_window_5x4x5", track(), (5, 4, 5), 2),
+]
+
+
+def random_state(w, labels, seed):
+    S = W.random_spins(len(labels), seed)
+    S[:, labels < 0] = 0.0
+    return S
+
+
+@pytest.mark.parametrize("prec", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("name,w,cell,n_sys", FIELD_CASES, ids=[c[0] for c in FIELD_CASES])
+def test_demag_field_matches_direct_sum(name, w, cell, n_sys, prec):
+    say(f"[demag field] {name} cell={cell} systems={n_sys} prec={prec}")
+    h = bridge.make_handle(w, prec, n_systems=n_sys, demag_cell=cell)
+    lab = h.labels()
+    states = [random_state(w, lab, 11 + s) for s in range(n_sys)]
+    if name.startswith("track"):
+        h.shift_window(7)  # the mesh follows the window
+    for s, S in enumerate(states):
+        h.set_spins(S, s)
+    got, mesh = h.demag_field()
+    dn, dd, dcell = demag_cells(w, cell, origin=7 if name.startswith("track") else 0)
+    assert mesh == tuple(dn)
+    scale = mu0_ms(w)
+    for s, S in enumerate(states):
+        ref = oracle.demag_field(S, dcell, dn, dd, w.mu_s)
+        err = float(np.max(np.abs(got[s] - ref))) / scale
+        say(f"  system {s}: max |B_gpu - B_oracle| / mu0 Ms = {err:.3e} (|B| max {np.max(np.abs(ref)):.3f} T)")
+        assert err <= FIELD_TOL[prec], (name, s, err)
+    h.close()
+
+
+def test_demag_uniform_plate_is_minus_mu0_ms():
+    """Saturated thin plate, one coarse cell per lattice cell across a wide window:
+    far from the edges the field is close to -mu0 Ms along z (thin-film limit)."""
+    w = sc_slab(nx=64, ny=64, nz=1, grains=False, bc=(0, 0, 0))
+    h = bridge.make_handle(w, A.ASD_FP64, demag_cell=(1, 1, 1))
+    got, mesh = h.demag_field()  # spins start at +z
+    B = got[0].reshape(3, 1, 64, 64)
+    centre = B[2, 0, 28:36, 28:36]
+    assert np.all(centre < -0.9 * mu0_ms(w)) and np.all(centre > -mu0_ms(w))
+    h.close()
+
+
+# (name, workload, coarse cell, systems, precision)
+STEP_CASES = [
+    ("sc_fp64", sc_slab(), (4, 4, 2), 1, A.ASD_FP64),
+    ("sc_fp32", sc_slab(), (4, 4, 2), 2, A.ASD_FP32),
+    ("l10_fp64", l10_slab(), (3, 3, 2), 1, A.ASD_FP64),
+    ("l10_fp32", l10_slab(), (3, 3, 3), 1, A.ASD_FP32),
+]
+
+
+@pytest.mark.parametrize("variant", [0, 1], ids=["recompute", "stash"])
+@pytest.mark.parametrize("name,w,cell,n_sys,prec", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_heun_with_demag_matches_oracle(name, w, cell, n_sys, prec, variant):
+    steps = 40
+    say(f"[demag heun] {name} cell={cell} variant={variant} steps={steps}")
+    h = bridge.make_handle(w, prec, n_systems=n_sys, demag_cell=cell)
+    h.set_variant(A.ASD_KERNEL_PLAIN, variant)
+    lab = h.labels()
+    S0 = [random_state(w, lab, 21 + s) for s in range(n_sys)]
+    for s in range(n_sys):
+        h.set_spins(S0[s], s)
+    h.step(steps)
+    dn, dd, dcell = demag_cells(w, cell)
+    for s in range(n_sys):
+        sysm = oracle_system(w, labels=oracle_labels(w), sys_id=s)
+        sysm.set_demag((dn, dd, dcell))
+        ref = sysm.heun(S0[s], 0, steps)
+        err = float(np.max(np.abs(h.get_spins(s).astype(np.float64) - ref)))
+        say(f"  system {s}: max |dS| = {err:.3e}")
+        assert err <= SPIN_TOL[prec], (name, s, err)
+        # the field mattered: without it the oracle lands far from both
+        if s == 0:
+            plain = oracle_system(w, labels=oracle_labels(w), sys_id=s).heun(S0[s], 0, steps)
+            assert float(np.max(np.abs(plain - ref))) > 100 * max(err, 1e-15)
+    h.close()
+
+
+@pytest.mark.parametrize("prec", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
+def test_track_with_demag_and_shifts(prec):
+    """Moving window: the demagnetising mesh moves with the window; graph-captured
+    segments (the demag kernels are plain launches, no memset nodes) replayed."""
+    w = track()
+    cell = (5, 4, 5)
+    shifts = [(10, 1), (20, 2)]
+    steps = 40
+    h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10)
+    lab = h.labels()
+    S0 = random_state(w, lab, 5)
+    h.set_spins(S0)
+    done = 0
+    for at, cols in shifts + [(steps, 0)]:
+        h.step(at - done)
+        done = at
+        if cols:
+            h.shift_window(cols)
+    org = 0
+    sysm = oracle_system(w, labels=lab, active=window_mask(w, 0), origin=0)
+    S = np.array(S0, dtype=np.float64)
+    done = 0
+    for at, cols in shifts + [(steps, 0)]:
+        dn, dd, dcell = demag_cells(w, cell, origin=org)
+        sysm.set_demag((dn, dd, dcell))
+        S = sysm.heun(S, done, at - done)
+        done = at
+        if cols:
+            org += cols
+            sysm.set_active(window_mask(w, org), org)
+    err = float(np.max(np.abs(h.get_spins().astype(np.float64) - S)))
+    say(f"[demag track] prec={prec} max |dS| = {err:.3e}")
+    assert err <= SPIN_TOL[prec]
+    h.close()
+
+
+def test_demag_error_paths():
+    w = sc_slab()
+    with pytest.raises(A.AsdError) as e:
+        bridge.make_handle(w, A.ASD_FP32, demag_cell=(2, 0, 2))
+    assert e.value.code == A.ASD_EINVAL
+    with pytest.raises(A.AsdError) as e:
+        bridge.make_handle(w.scaled(nx=600), A.ASD_FP32, demag_cell=(2, 1, 1))
+    assert e.value.code == A.ASD_EUNSUPPORTED
+    with pytest.raises(A.AsdError) as e:
+        bridge.make_handle(w, A.ASD_FP32, kernel=A.ASD_KERNEL_FUSED, demag_cell=(2, 2, 2))
+    assert e.value.code == A.ASD_EUNSUPPORTED
+    # AUTO falls back to the two-pass kernels
+    h = bridge.make_handle(w, A.ASD_FP32, kernel=A.ASD_KERNEL_AUTO, demag_cell=(2, 2, 2))
+    assert h.variant()[0] == A.ASD_KERNEL_PLAIN
+    with pytest.raises(A.AsdError) as e:
+        h.set_variant(A.ASD_KERNEL_FUSED, 0)
+    assert e.value.code == A.ASD_EUNSUPPORTED
+    h.close()
+    h = bridge.make_handle(w, A.ASD_FP32)
+    with pytest.raises(A.AsdError) as e:
+        h.demag_field()
+    assert e.value.code == A.ASD_ESTATE
+    h.close()
+    # systems of different window sizes cannot share the mesh
+    ins = [bridge.SystemInputs(w), bridge.SystemInputs(w.scaled(nx=w.nx - 1))]
+    with pytest.raises(A.AsdError) as e:
+        A.Handle(bridge.params_for(w, A.ASD_FP32, demag_cell=(2, 2, 2)), [i.desc for i in ins])
+    assert e.value.code == A.ASD_EUNSUPPORTED
