@@ -43,8 +43,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track", "transfer"],
-                    default="slab")
+    ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track", "transfer",
+                                           "demag"], default="slab")
+    ap.add_argument("--demag-cell", type=int, nargs=3, default=[4, 4, 3],
+                    help="coarse cell of the demag workload, in lattice cells")
     ap.add_argument("--kernel", choices=["auto", "plain", "fused"], default="auto")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--graph-steps", type=int, default=100)
@@ -121,16 +123,17 @@ def kernel_duration(torch, h, k):
     return float(np.median(d)), float(np.mean(d))
 
 
-def build_workload(name, prec, graph_steps):
+def build_workload(name, prec, graph_steps, demag_cell=(0, 0, 0)):
     """Handle + per-system initial spins + window-magnetic count for a workload."""
     import workloads as W
     from paper_2502_02236_amd import asd as A
     from paper_2502_02236_amd import bridge
 
     extra = {}
-    if name in ("slab", "l10"):
-        w = W.c2_granular_slab() if name == "slab" else W.c3_l10_window()
-        h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_PLAIN, graph_steps=graph_steps)
+    if name in ("slab", "l10", "demag"):
+        w = W.c3_l10_window() if name == "l10" else W.c2_granular_slab()
+        h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_PLAIN, graph_steps=graph_steps,
+                               demag_cell=tuple(demag_cell) if name == "demag" else (0, 0, 0))
         labs = [h.labels()]
         window = [np.ones(len(labs[0]), bool)]
     elif name == "cylinders":
@@ -194,14 +197,18 @@ def run_steps(h, k, extra, done):
                 h.shift_window(1)
 
 
-def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps):
+def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps, workload=None,
+            tile=None):
     import torch
     from paper_2502_02236_amd import asd as A
 
     prec = A.ASD_FP32 if precision_name == "fp32" else A.ASD_FP64
     kern = {"auto": A.ASD_KERNEL_AUTO, "plain": A.ASD_KERNEL_PLAIN,
             "fused": A.ASD_KERNEL_FUSED}[kernel_name]
-    w, h, S0s, n_mag, n_sites, extra = build_workload(args.workload, prec, graph_steps)
+    workload = workload or args.workload
+    tile = args.tile if tile is None else tile
+    w, h, S0s, n_mag, n_sites, extra = build_workload(workload, prec, graph_steps,
+                                                      args.demag_cell)
     if kern == A.ASD_KERNEL_AUTO:
         os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
         h.autotune(os.path.join(ROOT, "_build", "asd_tune.json"))
@@ -209,9 +216,9 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps):
             h.set_spins(S0, k)
         h.set_step(0)
     elif kern == A.ASD_KERNEL_FUSED:
-        h.set_variant(A.ASD_KERNEL_FUSED, max(args.tile, 0))
-    elif args.tile >= 0:
-        h.set_variant(A.ASD_KERNEL_PLAIN, args.tile)
+        h.set_variant(A.ASD_KERNEL_FUSED, max(tile, 0))
+    elif tile >= 0:
+        h.set_variant(A.ASD_KERNEL_PLAIN, tile)
     kernel_used, tile_used = h.variant()
     kname = h.variant_name()
     h.prepare()  # capture the step graphs before the warm-up (untimed)
@@ -341,6 +348,28 @@ def main():
         }), flush=True)
         return
     r = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, args.graph_steps)
+    demag = None
+    if args.workload == "demag":
+        # the same two-pass variant without the field: the difference is the
+        # time of the two demagnetising-field evaluations of each step
+        r0 = gpu_run(args, args.precision, "plain", args.steps, args.warmup, args.graph_steps,
+                     workload="slab", tile=r["tile"])
+        per_eval = (r["t"] - r0["t"]) / (2 * r["steps"])
+        cx, cy, cz = args.demag_cell
+        w = r["w"]
+        mesh = (-(-w.nx // cx), -(-w.ny // cy), -(-w.nz // cz))
+        e = 4 if args.precision == "fp32" else 8
+        # algorithmic bytes of one evaluation: the window spins read once and
+        # the field per coarse cell written once
+        dbytes = 3 * e * r["n_sites"] + 3 * e * mesh[0] * mesh[1] * mesh[2]
+        ach = dbytes / per_eval / 1e9
+        demag = {"cell": [cx, cy, cz], "mesh": list(mesh),
+                 "padded_fft": [1 << (2 * n - 1 - 1).bit_length() if n > 1 else 1 for n in mesh],
+                 "us_per_evaluation": 1e6 * per_eval, "evaluations_per_step": 2,
+                 "step_without_demag_ms": 1e3 * r0["t"] / r0["steps"],
+                 "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                              "algorithmic_bytes_per_evaluation": dbytes}}
     if args.copy_calibration:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
@@ -395,6 +424,10 @@ def main():
         "lattice_site_updates_per_s": r["n_sites"] * r["steps"] / r["t"],
         "max_norm_error": r["norm_err"],
     }
+    if demag is not None:
+        out["metric"] = "atomistic spin-updates/s (spins x Heun steps) with the demagnetising field"
+        out["config"]["workload"] = f"{r['w'].name}+demag{cx}x{cy}x{cz}"
+        out["demag"] = demag
     if not args.no_fp64_compare and args.precision == "fp32" and args.workload == "slab":
         r64 = gpu_run(args, "fp64", "plain", max(200, args.steps // 10), 20, 0)
         v64 = r64["n_mag"] * r64["steps"] / r64["t"]
