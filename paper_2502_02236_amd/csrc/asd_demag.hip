@@ -32,32 +32,74 @@ struct Cx {
     T re, im;
 };
 
-// Stockham radix-2 over nl lines of length P = 2^lp stored line-major in
-// x; y is the second buffer.  Stage s combines pairs (j, j + P/2) with the
-// twiddle of index k = j mod 2^s and writes them to (j / 2^s) 2^(s+1) + k
-// and + 2^s, which leaves the output in natural order.  Returns the buffer
-// holding the result.  Callers synchronise before; the routine ends with a
+// twiddle exp(-+2 pi i t / P) for t < P from the half table tw (t < P/2)
+template <typename T, bool INV>
+__device__ __forceinline__ Cx<T> twiddle(const Cx<T> *__restrict__ tw, int t, int half)
+{
+    Cx<T> w = t < half ? tw[t] : Cx<T>{-tw[t - half].re, -tw[t - half].im};
+    if (INV) w.im = -w.im;
+    return w;
+}
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
+{
+    return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// Stockham autosort FFT over nl lines of length P = 2^lp, line l at
+// x + l * ls (ls >= P; an odd stride spreads lines written across lanes
+// over the LDS banks); y is the second buffer.  With Ns the length of the
+// sub-transforms done so far, a radix-R stage takes the R points
+// j + r P/R (j < P/R), twiddles point r by exp(-2 pi i r k / (R Ns)) with
+// k = j mod Ns, does an R-point DFT and writes output r to
+// (j / Ns) R Ns + k + r Ns; the output ends in natural order.  One radix-2
+// stage when lp is odd, radix-4 stages after it.  Returns the buffer
+// holding the result.  Callers synchronise before; every stage ends with a
 // barrier.
 template <typename T, bool INV>
-__device__ Cx<T> *fft_lines(Cx<T> *x, Cx<T> *y, int nl, int lp, const Cx<T> *__restrict__ tw)
+__device__ Cx<T> *fft_lines(Cx<T> *x, Cx<T> *y, int nl, int lp, int ls,
+                            const Cx<T> *__restrict__ tw)
 {
     if (lp == 0) return x;
     const int P = 1 << lp, half = P >> 1;
-    const int nb = nl * half;
-    for (int s = 0; s < lp; ++s) {
-        const int Ns = 1 << s;
-        for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-            const int line = q >> (lp - 1);
-            const int j = q & (half - 1);
+    int Ns = 1;
+    if (lp & 1) {
+        for (int q = threadIdx.x; q < nl * half; q += blockDim.x) {
+            const int line = q >> (lp - 1), j = q & (half - 1);
+            const Cx<T> a = x[line * ls + j], b = x[line * ls + j + half];
+            Cx<T> *yd = y + line * ls + 2 * j;
+            yd[0] = Cx<T>{a.re + b.re, a.im + b.im};
+            yd[1] = Cx<T>{a.re - b.re, a.im - b.im};
+        }
+        __syncthreads();
+        Cx<T> *t = x;
+        x = y;
+        y = t;
+        Ns = 2;
+    }
+    const int quarter = P >> 2;
+    for (; Ns < P; Ns <<= 2) {
+        const int lns = __ffs(Ns) - 1;
+        const int tstep = lp - 2 - lns;  // log2 of P / (4 Ns)
+        for (int q = threadIdx.x; q < nl * quarter; q += blockDim.x) {
+            const int line = q >> (lp - 2), j = q & (quarter - 1);
             const int k = j & (Ns - 1);
-            Cx<T> w = tw[k << (lp - 1 - s)];
-            if (INV) w.im = -w.im;
-            const Cx<T> *xs = x + line * P;
-            const Cx<T> a = xs[j], b = xs[j + half];
-            const T br = b.re * w.re - b.im * w.im, bi = b.re * w.im + b.im * w.re;
-            Cx<T> *yd = y + line * P + ((j >> s) << (s + 1)) + k;
-            yd[0] = Cx<T>{a.re + br, a.im + bi};
-            yd[Ns] = Cx<T>{a.re - br, a.im - bi};
+            const Cx<T> *xs = x + line * ls + j;
+            const Cx<T> v0 = xs[0];
+            const Cx<T> v1 = cmul(xs[quarter], twiddle<T, INV>(tw, k << tstep, half));
+            const Cx<T> v2 = cmul(xs[2 * quarter], twiddle<T, INV>(tw, (2 * k) << tstep, half));
+            const Cx<T> v3 = cmul(xs[3 * quarter], twiddle<T, INV>(tw, (3 * k) << tstep, half));
+            const Cx<T> a0{v0.re + v2.re, v0.im + v2.im}, a1{v0.re - v2.re, v0.im - v2.im};
+            const Cx<T> a2{v1.re + v3.re, v1.im + v3.im};
+            const T dr = v1.re - v3.re, di = v1.im - v3.im;
+            // (v1 - v3) times -i (forward) or +i (inverse)
+            const Cx<T> a3 = INV ? Cx<T>{-di, dr} : Cx<T>{di, -dr};
+            Cx<T> *yd = y + line * ls + ((j >> lns) << (lns + 2)) + k;
+            yd[0] = Cx<T>{a0.re + a2.re, a0.im + a2.im};
+            yd[Ns] = Cx<T>{a1.re + a3.re, a1.im + a3.im};
+            yd[2 * Ns] = Cx<T>{a0.re - a2.re, a0.im - a2.im};
+            yd[3 * Ns] = Cx<T>{a1.re - a3.re, a1.im - a3.im};
         }
         __syncthreads();
         Cx<T> *t = x;
@@ -74,12 +116,17 @@ __device__ __forceinline__ Cx<T> *lds_base()
     return (Cx<T> *)dm_lds;
 }
 
-// --- 1: cell sums of one (y, z) row of coarse cells, FFT along x
+// --- 1: cell sums of one (y, z) row of coarse cells, FFT along x.
+// Thread t takes cell i = t mod ncx and the lattice rows g, g + G, ... of that
+// cell (g = t / ncx, G = 256 / ncx row groups), so neighbouring lanes read
+// neighbouring cells of one lattice row; the G partial sums of a cell are
+// then added in group order.
 template <typename T>
 __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T *__restrict__ S,
                                                             int64_t ncs, const SysDev *sys,
                                                             const int32_t *origin)
 {
+    __shared__ T part[3][kDmThreads];
     const int Px = 1 << dm.lx;
     const int j = blockIdx.x % dm.ncy, k = blockIdx.x / dm.ncy, s = blockIdx.y;
     const SysDev d = sys[s];
@@ -87,30 +134,42 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T
     const int per = d.kind == ASD_SC ? 1 : 2;
     Cx<T> *x = lds_base<T>(), *y = x + 3 * Px;
     for (int q = threadIdx.x; q < 3 * Px; q += blockDim.x) x[q] = Cx<T>{T(0), T(0)};
-    __syncthreads();
     const int yb = j * dm.cy, zb = k * dm.cz;
     const int wy = min(dm.cy, d.ny - yb), wz = min(dm.cz, d.nz - zb);
-    for (int i = threadIdx.x; i < dm.ncx; i += blockDim.x) {
+    const int G = kDmThreads / dm.ncx;  // ncx <= 256
+    const int i = threadIdx.x % dm.ncx, g = threadIdx.x / dm.ncx;
+    T ax = T(0), ay = T(0), az = T(0);
+    if (g < G) {
         const int xb = i * dm.cx;
         const int nq = per * min(dm.cx, d.nx - xb);
-        T ax = T(0), ay = T(0), az = T(0);
-        for (int zz = 0; zz < wz; ++zz)
-            for (int yy = 0; yy < wy; ++yy) {
-                const int64_t row =
-                    d.base + per * ((int64_t)(org + xb) +
-                                    (int64_t)d.sx * ((yb + yy) + (int64_t)d.ny * (zb + zz)));
-                for (int q = 0; q < nq; ++q) {
-                    ax += S[row + q];
-                    ay += S[ncs + row + q];
-                    az += S[2 * ncs + row + q];
-                }
+        for (int r = g; r < wy * wz; r += G) {
+            const int zz = r / wy, yy = r - zz * wy;
+            const int64_t row = d.base + per * ((int64_t)(org + xb) +
+                                                (int64_t)d.sx * ((yb + yy) + (int64_t)d.ny * (zb + zz)));
+            for (int q = 0; q < nq; ++q) {
+                ax += S[row + q];
+                ay += S[ncs + row + q];
+                az += S[2 * ncs + row + q];
             }
-        x[i].re = ax;
-        x[Px + i].re = ay;
-        x[2 * Px + i].re = az;
+        }
+    }
+    part[0][threadIdx.x] = ax;
+    part[1][threadIdx.x] = ay;
+    part[2][threadIdx.x] = az;
+    __syncthreads();
+    if (threadIdx.x < dm.ncx) {
+        T sx = part[0][threadIdx.x], sy = part[1][threadIdx.x], sz = part[2][threadIdx.x];
+        for (int gg = 1; gg < G; ++gg) {
+            sx += part[0][gg * dm.ncx + threadIdx.x];
+            sy += part[1][gg * dm.ncx + threadIdx.x];
+            sz += part[2][gg * dm.ncx + threadIdx.x];
+        }
+        x[threadIdx.x].re = sx;
+        x[Px + threadIdx.x].re = sy;
+        x[2 * Px + threadIdx.x].re = sz;
     }
     __syncthreads();
-    const Cx<T> *r = fft_lines<T, false>(x, y, 3, dm.lx, (const Cx<T> *)dm.tw[0]);
+    const Cx<T> *r = fft_lines<T, false>(x, y, 3, dm.lx, Px, (const Cx<T> *)dm.tw[0]);
     Cx<T> *out = (Cx<T> *)dm.wx;
     for (int q = threadIdx.x; q < 3 * Px; q += blockDim.x) {
         const int c = q >> dm.lx, kx = q & (Px - 1);
@@ -134,61 +193,65 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_y(DemagDev dm)
     const int rows_in = INV ? Py : dm.ncy, rows_out = INV ? dm.ncy : Py;
     const int64_t pin = ((int64_t)s * 3 * dm.ncz + plane) * rows_in * Px;
     const int64_t pout = ((int64_t)s * 3 * dm.ncz + plane) * rows_out * Px;
-    Cx<T> *x = lds_base<T>(), *y = x + XB * Py;
+    const int ls = Py + 1;  // odd line stride: the transposed writes spread over the banks
+    Cx<T> *x = lds_base<T>(), *y = x + XB * ls;
     for (int q = threadIdx.x; q < XB * Py; q += blockDim.x) {
         const int yy = q >> lxb, xb = q & (XB - 1);
-        x[xb * Py + yy] = yy < rows_in ? src[pin + (int64_t)yy * Px + kx0 + xb] : Cx<T>{T(0), T(0)};
+        x[xb * ls + yy] = yy < rows_in ? src[pin + (int64_t)yy * Px + kx0 + xb] : Cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    const Cx<T> *r = fft_lines<T, INV>(x, y, XB, dm.ly, (const Cx<T> *)dm.tw[1]);
+    const Cx<T> *r = fft_lines<T, INV>(x, y, XB, dm.ly, ls, (const Cx<T> *)dm.tw[1]);
     for (int q = threadIdx.x; q < rows_out * XB; q += blockDim.x) {
         const int yy = q >> lxb, xb = q & (XB - 1);
-        dst[pout + (int64_t)yy * Px + kx0 + xb] = r[xb * Py + yy];
+        dst[pout + (int64_t)yy * Px + kx0 + xb] = r[xb * ls + yy];
     }
 }
 
-// --- 3: per (kx, ky) column: FFT along z, tensor product, inverse FFT
+// --- 3: per (kx, ky) column: FFT along z, tensor product, inverse FFT.
+// Line (c, xb) holds z = 0 .. Pz-1 of component c at kx0 + xb, stride Pz + 1.
 template <typename T>
 __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
 {
     const int Px = 1 << dm.lx, Py = 1 << dm.ly, Pz = 1 << dm.lz;
-    const int XB = dm.xb_z;
+    const int XB = dm.xb_z, lxb = __ffs(XB) - 1;
     const int kx0 = blockIdx.x * XB, ky = blockIdx.y, s = blockIdx.z;
     Cx<T> *w = (Cx<T> *)dm.wy;
-    const int64_t cstride = (int64_t)dm.ncz * Py * Px;  // component stride in wy
+    const int64_t plane = (int64_t)Py * Px;
+    const int64_t cstride = (int64_t)dm.ncz * plane;  // component stride in wy
     const int64_t base = (int64_t)s * 3 * cstride + (int64_t)ky * Px + kx0;
-    const int n = 3 * XB * Pz;
-    Cx<T> *x = lds_base<T>(), *y = x + n;
-    // line (c, xb) holds z = 0 .. Pz-1 of component c at kx0 + xb
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int z = q / (3 * XB), cxb = q - z * 3 * XB;
-        const int c = cxb / XB, xb = cxb - c * XB;
-        x[cxb * Pz + z] = z < dm.ncz ? w[base + c * cstride + (int64_t)z * Py * Px + xb]
-                                     : Cx<T>{T(0), T(0)};
+    const int ls = Pz + 1;
+    const int nl = 3 * XB;
+    Cx<T> *x = lds_base<T>(), *y = x + nl * ls;
+    // rows (c, z) of XB neighbouring kx: lanes read along kx
+    for (int q = threadIdx.x; q < 3 * Pz * XB; q += blockDim.x) {
+        const int xb = q & (XB - 1), row = q >> lxb;
+        const int c = row >> dm.lz, z = row & (Pz - 1);
+        x[(c * XB + xb) * ls + z] =
+            z < dm.ncz ? w[base + c * cstride + z * plane + xb] : Cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    Cx<T> *r = fft_lines<T, false>(x, y, 3 * XB, dm.lz, (const Cx<T> *)dm.tw[2]);
-    // tensor octant: components even in every wavenumber, or odd in the two
-    // that appear in their name
+    Cx<T> *r = fft_lines<T, false>(x, y, nl, dm.lz, ls, (const Cx<T> *)dm.tw[2]);
+    // tensor spectrum octant [6][Py/2+1][Px/2+1][Pz/2+1] (kz fastest): the
+    // components are even in every wavenumber, or odd in the two named ones
     const int ox = (Px >> 1) + 1, oy = (Py >> 1) + 1, oz = (Pz >> 1) + 1;
     const int64_t ocomp = (int64_t)ox * oy * oz;
     const T *K = (const T *)dm.K;
     const int kyr = ky <= (Py >> 1) ? ky : Py - ky;
     const T sy = ky <= (Py >> 1) ? T(1) : T(-1);
     for (int q = threadIdx.x; q < XB * Pz; q += blockDim.x) {
-        const int xb = q / Pz, kz = q - xb * Pz;
+        const int kz = q & (Pz - 1), xb = q >> dm.lz;
         const int kx = kx0 + xb;
         const int kxr = kx <= (Px >> 1) ? kx : Px - kx;
         const int kzr = kz <= (Pz >> 1) ? kz : Pz - kz;
         const T sx = kx <= (Px >> 1) ? T(1) : T(-1);
         const T sz = kz <= (Pz >> 1) ? T(1) : T(-1);
-        const int64_t o = ((int64_t)kzr * oy + kyr) * ox + kxr;
+        const int64_t o = ((int64_t)kyr * ox + kxr) * oz + kzr;
         const T nxx = K[o], nyy = K[ocomp + o], nzz = K[2 * ocomp + o];
         const T nxy = sx * sy * K[3 * ocomp + o], nxz = sx * sz * K[4 * ocomp + o],
                 nyz = sy * sz * K[5 * ocomp + o];
-        Cx<T> *px = r + (0 * XB + xb) * Pz + kz;
-        Cx<T> *py = r + (1 * XB + xb) * Pz + kz;
-        Cx<T> *pz = r + (2 * XB + xb) * Pz + kz;
+        Cx<T> *px = r + (0 * XB + xb) * ls + kz;
+        Cx<T> *py = r + (1 * XB + xb) * ls + kz;
+        Cx<T> *pz = r + (2 * XB + xb) * ls + kz;
         const Cx<T> mx = *px, my = *py, mz = *pz;
         *px = Cx<T>{(nxx * mx.re + nxy * my.re) + nxz * mz.re, (nxx * mx.im + nxy * my.im) + nxz * mz.im};
         *py = Cx<T>{(nxy * mx.re + nyy * my.re) + nyz * mz.re, (nxy * mx.im + nyy * my.im) + nyz * mz.im};
@@ -196,11 +259,11 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
     }
     __syncthreads();
     Cx<T> *other = r == x ? y : x;
-    const Cx<T> *h = fft_lines<T, true>(r, other, 3 * XB, dm.lz, (const Cx<T> *)dm.tw[2]);
-    for (int q = threadIdx.x; q < 3 * XB * dm.ncz; q += blockDim.x) {
-        const int z = q / (3 * XB), cxb = q - z * 3 * XB;
-        const int c = cxb / XB, xb = cxb - c * XB;
-        w[base + c * cstride + (int64_t)z * Py * Px + xb] = h[cxb * Pz + z];
+    const Cx<T> *h = fft_lines<T, true>(r, other, nl, dm.lz, ls, (const Cx<T> *)dm.tw[2]);
+    for (int q = threadIdx.x; q < 3 * Pz * XB; q += blockDim.x) {
+        const int xb = q & (XB - 1), row = q >> lxb;
+        const int c = row >> dm.lz, z = row & (Pz - 1);
+        if (z < dm.ncz) w[base + c * cstride + z * plane + xb] = h[(c * XB + xb) * ls + z];
     }
 }
 
@@ -217,7 +280,7 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage)
         x[q] = in[((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Px + kx];
     }
     __syncthreads();
-    const Cx<T> *r = fft_lines<T, true>(x, y, 3, dm.lx, (const Cx<T> *)dm.tw[0]);
+    const Cx<T> *r = fft_lines<T, true>(x, y, 3, dm.lx, Px, (const Cx<T> *)dm.tw[0]);
     T *bd = (T *)dm.bd[stage];
     const int64_t cell0 = (int64_t)dm.ncx * (j + (int64_t)dm.ncy * k);
     for (int q = threadIdx.x; q < 3 * dm.ncx; q += blockDim.x) {
@@ -237,10 +300,10 @@ int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
     const dim3 grows(dm.ncy * dm.ncz, dm.n_sys);
     hipLaunchKernelGGL(k_dm_gather_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, S, ncs, sys, origin);
     const dim3 gy(Px / dm.xb_y, 3 * dm.ncz, dm.n_sys);
-    hipLaunchKernelGGL((k_dm_y<T, false>), gy, blk, 2 * dm.xb_y * Py * cb, st, dm);
+    hipLaunchKernelGGL((k_dm_y<T, false>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
     const dim3 gz(Px / dm.xb_z, Py, dm.n_sys);
-    hipLaunchKernelGGL(k_dm_z<T>, gz, blk, 2 * 3 * dm.xb_z * Pz * cb, st, dm);
-    hipLaunchKernelGGL((k_dm_y<T, true>), gy, blk, 2 * dm.xb_y * Py * cb, st, dm);
+    hipLaunchKernelGGL(k_dm_z<T>, gz, blk, 2 * 3 * dm.xb_z * (Pz + 1) * cb, st, dm);
+    hipLaunchKernelGGL((k_dm_y<T, true>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
     hipLaunchKernelGGL(k_dm_x_out<T>, grows, blk, 2 * 3 * Px * cb, st, dm, stage);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -78,7 +78,8 @@ void fft1(std::complex<double> *a, int l, size_t st)
 
 // Spectrum of the six tensor components on the zero-padded mesh (padded
 // sizes 2^lx x 2^ly x 2^lz), times `scale`, kept on the octant kx <= Px/2,
-// ky <= Py/2, kz <= Pz/2: [6][Pz/2+1][Py/2+1][Px/2+1] (xx yy zz xy xz yz).
+// ky <= Py/2, kz <= Pz/2: [6][Py/2+1][Px/2+1][Pz/2+1] (xx yy zz xy xz yz;
+// kz fastest, the order in which the z pass reads it).
 // The components are real and even or odd in each wavenumber by the
 // symmetry of the tensor, so the octant determines the whole spectrum.
 void demag_spectrum(int ncx, int ncy, int ncz, double dx, double dy, double dz, int lx, int ly,
@@ -140,7 +141,7 @@ void demag_spectrum(int ncx, int ncy, int ncz, double dx, double dy, double dz, 
         for (int kz = 0; kz < oz; ++kz)
             for (int ky = 0; ky < oy; ++ky)
                 for (int kx = 0; kx < ox; ++kx)
-                    octant[(((size_t)comp * oz + kz) * oy + ky) * ox + kx] =
+                    octant[(((size_t)comp * oy + ky) * ox + kx) * oz + kz] =
                         a[((size_t)(kz % Pz) * Py + (ky % Py)) * Px + (kx % Px)].real();
     }
 }

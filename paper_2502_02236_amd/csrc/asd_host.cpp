@@ -416,15 +416,20 @@ static const char *demag_geometry(const asd_params *p, const asd_system_desc *sy
     g->lx = ilog2_ceil(2 * g->ncx - 1);
     g->ly = ilog2_ceil(2 * g->ncy - 1);
     g->lz = ilog2_ceil(2 * g->ncz - 1);
-    // lines per workgroup of the y and z passes: LDS of two buffers of
-    // at most 1024 (FP64) / 2048 (FP32) complex values
+    // x lines per workgroup of the y and z passes: two LDS buffers of at
+    // most 1024 (FP64) / 2048 (FP32) complex values (lines padded by one),
+    // and no fewer than 1024 workgroups while the lines can be split
     const int budget = p->precision == ASD_FP64 ? 1024 : 2048;
     const int Px = 1 << g->lx, Py = 1 << g->ly, Pz = 1 << g->lz;
     int xb = 1;
-    while (xb * 2 <= Px && xb * 2 * Py <= budget) xb *= 2;
+    while (xb * 2 <= Px && xb * 2 * (Py + 1) <= budget &&
+           (int64_t)(Px / (xb * 2)) * 3 * g->ncz * n_sys >= 1024)
+        xb *= 2;
     g->xb_y = xb;
     xb = 1;
-    while (xb * 2 <= Px && xb * 2 * 3 * Pz <= budget) xb *= 2;
+    while (xb * 2 <= Px && xb * 2 * 3 * (Pz + 1) <= budget &&
+           (int64_t)(Px / (xb * 2)) * Py * n_sys >= 1024)
+        xb *= 2;
     g->xb_z = xb;
     g->n_sys = n_sys;
     g->fd_cx = host_fastdiv((uint32_t)c[0]);

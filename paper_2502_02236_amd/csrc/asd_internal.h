@@ -72,7 +72,7 @@ struct DemagDev {
     void *wx;                 // complex [S][3][ncz][ncy][Px]
     void *wy;                 // complex [S][3][ncz][Py][Px]
     void *bd[2];              // field (T) per coarse cell, [S][3][ncell], one per Heun stage
-    const void *K;            // tensor spectrum, octant [6][Pz/2+1][Py/2+1][Px/2+1]
+    const void *K;            // tensor spectrum, octant [6][Py/2+1][Px/2+1][Pz/2+1]
     const void *tw[3];        // twiddles exp(-2 pi i t / P), t < P / 2, per axis
 };
 

@@ -75,6 +75,12 @@ FIELD_CASES = [
     ("sc_one_cell", sc_slab(nx=8, ny=6, nz=3), (8, 6, 3), 1),
     ("l10_3x3x2", l10_slab(), (3, 3, 2), 2),
     ("track_window_5x4x5", track(), (5, 4, 5), 2),
+    # meshes 5 x 4 x ncz: the FP32 z pass sums directly up to 16 planes
+    # (register blocks of 4, 8, 12, 16), FFTs beyond
+    ("sc_ncz7", sc_slab(nx=10, ny=8, nz=7), (2, 2, 1), 1),
+    ("sc_ncz11", sc_slab(nx=10, ny=8, nz=11), (2, 2, 1), 1),
+    ("sc_ncz15", sc_slab(nx=10, ny=8, nz=15), (2, 2, 1), 1),
+    ("sc_ncz20", sc_slab(nx=10, ny=8, nz=20), (2, 2, 1), 2),
 ]
 
 
