@@ -104,9 +104,14 @@ typedef struct asd_params {
     int32_t demag_cell[3]; /* all > 0: add the demagnetising field of the window
                               (Eq. 7, Newell's tensor, open boundaries) on coarse
                               cells of demag_cell[0] x [1] x [2] lattice cells
-                              (Eq. 6), evaluated at both Heun stages; all 0: off.
-                              Needs every system to have the same window size,
-                              at most 256 coarse cells per axis, and the
+                              (Eq. 6), evaluated at both Heun stages; for a
+                              track system also the stray field of the frozen
+                              track (Sec. II), on the window's cells continued
+                              along the track, recomputed after the track
+                              changes (spins set, window shifted, columns
+                              thermalised); all 0: off.  Needs every system to
+                              have the same window size, at most 256 coarse
+                              cells per axis (254 along a track), and the
                               two-pass kernels (ASD_KERNEL_PLAIN or AUTO) */
 } asd_params;
 
@@ -268,7 +273,8 @@ int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int
 
 /* Step counter and window origin of system sys (host copies). */
 /* Demagnetising field (Eq. 7) of the current spins of every system, as
- * the flux density mu0 H_d (T) per coarse cell: per_cell is a host array
+ * the flux density mu0 H_d (T) per coarse cell of the window (including the
+ * frozen track's stray field for a track system): per_cell is a host array
  * [n_sys][3][ncell] (cells numbered x fastest over the window,
  * c = i + ncx (j + ncy k)); mesh (optional, host int32[3]) receives
  * (ncx, ncy, ncz).  Coarse cell moment M = mu_s (sum of unit spins) / V

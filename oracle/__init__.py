@@ -67,7 +67,7 @@ class OrcSystem(C.Structure):
         ("steps_per_bit", C.c_int64), ("spot_mode", C.c_int), ("T_amb", C.c_double),
         ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
         ("v", C.c_double), ("seed", C.c_uint64), ("rounds", C.c_int),
-        ("dn", C.c_int * 3), ("dd", C.c_double * 3), ("dcell", i32p),
+        ("dn", C.c_int * 3), ("dd", C.c_double * 3), ("dcell", i32p), ("bstray", f64p),
     ]
 
 
@@ -229,10 +229,14 @@ class System:
         self._s = s
         self.set_demag(demag)
 
-    def set_demag(self, demag):
+    def set_demag(self, demag, stray=None):
         """demag = (dn, dd, dcell): coarse mesh (cells along x, y, z), cell
-        edges (m) and the coarse cell of every site (-1 = none); None = off."""
+        edges (m) and the coarse cell of every site (-1 = none); None = off.
+        stray: float[3, ncell] field (T) of sources outside the evolving sites,
+        added to every cell's demagnetising field (None = none)."""
         s = self._s
+        self.bstray = None if stray is None else np.ascontiguousarray(stray, np.float64).reshape(-1)
+        s.bstray = _ptr(self.bstray, f64p)
         if demag is None:
             self.dcell = None
             s.dn[0] = s.dn[1] = s.dn[2] = 0

@@ -903,6 +903,8 @@ static int demag_cells(const orc_system *s, const double *Sx, const double *Sy, 
     for (int64_t c = 0; c < 3 * nc; ++c) M[c] = k * M[c];
     orc_demag_direct(s->dn[0], s->dn[1], s->dn[2], s->dd[0], s->dd[1], s->dd[2], M, H);
     for (int64_t c = 0; c < 3 * nc; ++c) out[c] = ORC_MU0 * H[c];
+    if (s->bstray)
+        for (int64_t c = 0; c < 3 * nc; ++c) out[c] = out[c] + s->bstray[c];
     free(M);
     free(H);
     return 0;

@@ -56,6 +56,8 @@ typedef struct orc_system {
     int dn[3];              /* coarse mesh, cells along x, y, z */
     double dd[3];           /* coarse cell edges (m) */
     const int32_t *dcell;
+    const double *bstray;   /* [3][ncell] field (T) of sources outside the
+                               evolving sites, added per coarse cell; or NULL */
 } orc_system;
 
 void orc_philox4x32(int rounds, uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4]);

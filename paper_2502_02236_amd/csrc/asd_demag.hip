@@ -139,12 +139,19 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T
     const int G = kDmThreads / dm.ncx;  // ncx <= 256
     const int i = threadIdx.x % dm.ncx, g = threadIdx.x / dm.ncx;
     T ax = T(0), ay = T(0), az = T(0);
-    if (g < G) {
-        const int xb = i * dm.cx;
-        const int nq = per * min(dm.cx, d.nx - xb);
+    // window-frame columns [lo, hi) of cell i that hold sources
+    int lo = i * dm.cx, hi = min(lo + dm.cx, d.nx);
+    if (dm.stray) {
+        lo = (i - (org + dm.cx - 1) / dm.cx) * dm.cx;
+        hi = min(lo + dm.cx, d.sx - org);
+        if (lo >= 0 && lo < d.nx) lo = d.nx;  // a window cell: only its columns past the window
+        lo = max(lo, -org);
+    }
+    if (g < G && lo < hi) {
+        const int nq = per * (hi - lo);
         for (int r = g; r < wy * wz; r += G) {
             const int zz = r / wy, yy = r - zz * wy;
-            const int64_t row = d.base + per * ((int64_t)(org + xb) +
+            const int64_t row = d.base + per * ((int64_t)(org + lo) +
                                                 (int64_t)d.sx * ((yb + yy) + (int64_t)d.ny * (zb + zz)));
             for (int q = 0; q < nq; ++q) {
                 ax += S[row + q];
@@ -269,7 +276,8 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
 
 // --- 5: inverse FFT along x of one (y, z) row, the field of its ncx cells
 template <typename T>
-__global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage)
+__global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage,
+                                                         const int32_t *origin)
 {
     const int Px = 1 << dm.lx;
     const int j = blockIdx.x % dm.ncy, k = blockIdx.x / dm.ncy, s = blockIdx.y;
@@ -281,11 +289,25 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage)
     }
     __syncthreads();
     const Cx<T> *r = fft_lines<T, true>(x, y, 3, dm.lx, Px, (const Cx<T> *)dm.tw[0]);
+    if (dm.stray) {
+        // window cells i0 .. i0 + ncx_win - 1 of the track mesh
+        const int org = origin[s];
+        const int i0 = (org + dm.cx - 1) / dm.cx;
+        T *out = (T *)dm.bstray;
+        const int64_t cell0 = (int64_t)dm.ncx_win * (j + (int64_t)dm.ncy * k);
+        for (int q = threadIdx.x; q < 3 * dm.ncx_win; q += blockDim.x) {
+            const int c = q / dm.ncx_win, i = q - c * dm.ncx_win;
+            out[((int64_t)s * 3 + c) * dm.ncell_win + cell0 + i] = r[c * Px + i0 + i].re;
+        }
+        return;
+    }
     T *bd = (T *)dm.bd[stage];
+    const T *add = (const T *)dm.bstray;
     const int64_t cell0 = (int64_t)dm.ncx * (j + (int64_t)dm.ncy * k);
     for (int q = threadIdx.x; q < 3 * dm.ncx; q += blockDim.x) {
         const int c = q / dm.ncx, i = q - c * dm.ncx;
-        bd[((int64_t)s * 3 + c) * dm.ncell + cell0 + i] = r[c * Px + i].re;
+        const int64_t o = ((int64_t)s * 3 + c) * dm.ncell + cell0 + i;
+        bd[o] = add ? r[c * Px + i].re + add[o] : r[c * Px + i].re;
     }
 }
 
@@ -304,7 +326,7 @@ int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
     const dim3 gz(Px / dm.xb_z, Py, dm.n_sys);
     hipLaunchKernelGGL(k_dm_z<T>, gz, blk, 2 * 3 * dm.xb_z * (Pz + 1) * cb, st, dm);
     hipLaunchKernelGGL((k_dm_y<T, true>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
-    hipLaunchKernelGGL(k_dm_x_out<T>, grows, blk, 2 * 3 * Px * cb, st, dm, stage);
+    hipLaunchKernelGGL(k_dm_x_out<T>, grows, blk, 2 * 3 * Px * cb, st, dm, stage, origin);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -65,6 +65,8 @@ struct Layout {
     // demagnetising field (when asd_params.demag_cell is set)
     DemagDev dm{};            // geometry; pointers filled at create
     size_t off_dwx = 0, off_dwy = 0, off_dbd[2] = {0, 0}, off_dK = 0, off_dtw[3] = {0, 0, 0};
+    DemagDev dmT{};           // stray field of the frozen track (track systems only)
+    size_t off_twx = 0, off_twy = 0, off_tK = 0, off_ttw = 0, off_tstray = 0;
     size_t bytes = 0;
 };
 
@@ -92,6 +94,8 @@ struct asd_t {
     int graph_kernel = -1, graph_tile = -1;
     int n_ftiles = 0;         // fused tiles of the current variant
     DemagDev dm{};            // demagnetising field (dm.on = 0: none)
+    DemagDev dmT{};           // stray field of the frozen track (dmT.on = 0: none)
+    bool stray_dirty = true;  // the frozen track changed since the stray field was computed
 };
 
 static thread_local std::string g_err;
@@ -411,6 +415,9 @@ static const char *demag_geometry(const asd_params *p, const asd_system_desc *sy
     g->ncz = (sys[0].nz + c[2] - 1) / c[2];
     if (g->ncx > 256 || g->ncy > 256 || g->ncz > 256)
         return "the demagnetising mesh is limited to 256 coarse cells per axis";
+    for (int s = 0; s < n_sys; ++s)
+        if (sys[s].bc_x == ASD_BC_TRACK && (sys[s].track_nx + c[0] - 1) / c[0] + 2 > 256)
+            return "the stray field of a track needs at most 254 coarse cells along the track";
     g->ncell = g->ncx * g->ncy * g->ncz;
     // zero padding to a power of two >= 2 n - 1 (none for a single cell)
     g->lx = ilog2_ceil(2 * g->ncx - 1);
@@ -506,6 +513,41 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         L.off_dtw[0] = take(std::max<size_t>(Px / 2, 1) * cplx);
         L.off_dtw[1] = take(std::max<size_t>(Py / 2, 1) * cplx);
         L.off_dtw[2] = take(std::max<size_t>(Pz / 2, 1) * cplx);
+        bool track = false;
+        int32_t sxmax = 0;
+        for (int s = 0; s < n_sys; ++s) {
+            if (sys[s].bc_x == ASD_BC_TRACK) track = true;
+            sxmax = std::max(sxmax, sys[s].bc_x == ASD_BC_TRACK ? sys[s].track_nx : sys[s].nx);
+        }
+        if (track) {
+            // the window's cells continued over the whole track: at most
+            // ceil(track / cx) + 1 of them hold sites
+            DemagDev &t = L.dmT;
+            t = g;
+            t.stray = 1;
+            t.ncx_win = g.ncx;
+            t.ncell_win = g.ncell;
+            t.ncx = (sxmax + g.cx - 1) / g.cx + 2;
+            t.ncell = t.ncx * g.ncy * g.ncz;
+            t.lx = ilog2_ceil(2 * t.ncx - 1);
+            const size_t PxT = (size_t)1 << t.lx;
+            const int budget = p->precision == ASD_FP64 ? 1024 : 2048;
+            int xb = 1;
+            while (xb * 2 <= (int)PxT && xb * 2 * ((int)Py + 1) <= budget &&
+                   (int64_t)(PxT / (xb * 2)) * 3 * g.ncz * n_sys >= 1024)
+                xb *= 2;
+            t.xb_y = xb;
+            xb = 1;
+            while (xb * 2 <= (int)PxT && xb * 2 * 3 * ((int)Pz + 1) <= budget &&
+                   (int64_t)(PxT / (xb * 2)) * Py * n_sys >= 1024)
+                xb *= 2;
+            t.xb_z = xb;
+            L.off_twx = take((size_t)n_sys * 3 * g.ncz * g.ncy * PxT * cplx);
+            L.off_twy = take((size_t)n_sys * 3 * g.ncz * Py * PxT * cplx);
+            L.off_tK = take(6 * (PxT / 2 + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * elem);
+            L.off_ttw = take(std::max<size_t>(PxT / 2, 1) * cplx);
+            L.off_tstray = take((size_t)n_sys * 3 * g.ncell * elem);
+        }
     }
     L.bytes = off;
     return L;
@@ -758,6 +800,41 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
         g.bd[1] = w + L.off_dbd[1];
         g.K = w + L.off_dK;
         for (int ax = 0; ax < 3; ++ax) g.tw[ax] = w + L.off_dtw[ax];
+        if (L.dmT.on) {
+            DemagDev t = L.dmT;
+            const int PxT = 1 << t.lx;
+            const double scaleT = -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)PxT * Py * Pz));
+            demag_spectrum(t.ncx, t.ncy, t.ncz, dx, dy, dz, t.lx, t.ly, t.lz, scaleT, oct);
+            buf.assign(oct.size() * h->elem, 0);
+            for (size_t i = 0; i < oct.size(); ++i) {
+                if (h->elem == 8) ((double *)buf.data())[i] = oct[i];
+                else ((float *)buf.data())[i] = (float)oct[i];
+            }
+            HIP_OK(h, hipMemcpyAsync(w + L.off_tK, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
+            std::vector<char> twT((size_t)std::max(PxT / 2, 1) * 2 * h->elem);
+            for (int q = 0; q < std::max(PxT / 2, 1); ++q) {
+                const double ang = -2.0 * M_PI * (double)q / (double)PxT;
+                if (h->elem == 8) {
+                    ((double *)twT.data())[2 * q] = std::cos(ang);
+                    ((double *)twT.data())[2 * q + 1] = std::sin(ang);
+                } else {
+                    ((float *)twT.data())[2 * q] = (float)std::cos(ang);
+                    ((float *)twT.data())[2 * q + 1] = (float)std::sin(ang);
+                }
+            }
+            HIP_OK(h, hipMemcpyAsync(w + L.off_ttw, twT.data(), twT.size(), hipMemcpyHostToDevice, st));
+            t.wx = w + L.off_twx;
+            t.wy = w + L.off_twy;
+            t.K = w + L.off_tK;
+            t.tw[0] = w + L.off_ttw;
+            t.tw[1] = g.tw[1];
+            t.tw[2] = g.tw[2];
+            t.bstray = w + L.off_tstray;
+            t.bd[0] = t.bd[1] = nullptr;
+            h->dmT = t;
+            g.bstray = t.bstray;  // the window's field includes the track's
+            HIP_OK(h, hipStreamSynchronize(st));
+        }
         h->dm = g;
         HIP_OK(h, hipStreamSynchronize(st));
     }
@@ -835,6 +912,7 @@ int asd_set_spins(asd_t *h, int32_t s, const void *src, int32_t on_device)
                               (const uint16_t *)(h->ws + h->L.off_label), d, h->stream))
             return fail(h, ASD_EHIP, "mask kernel launch failed");
     }
+    h->stray_dirty = true;
     HIP_OK(h, hipStreamSynchronize(h->stream));
     return ASD_OK;
 }
@@ -941,6 +1019,26 @@ static int launch_one(asd_t *h, int cur, int step_off)
     return ASD_OK;
 }
 
+// stray field of the frozen track, recomputed when the track changed
+// (spins set, window shifted, columns thermalised)
+static int refresh_stray(asd_t *h)
+{
+    if (!h->dmT.on || !h->stray_dirty) return ASD_OK;
+    const char *w = h->ws;
+    const SysDev *sys = (const SysDev *)(w + h->L.off_sys);
+    const int32_t *org = (const int32_t *)(w + h->L.off_origin);
+    int rc;
+    if (h->elem == 8)
+        rc = launch_demag(h->dmT, (const double *)(w + h->L.off_S[h->cur]), h->L.ncs, sys, org, 0,
+                          h->stream);
+    else
+        rc = launch_demag(h->dmT, (const float *)(w + h->L.off_S[h->cur]), h->L.ncs, sys, org, 0,
+                          h->stream);
+    if (rc) return fail(h, ASD_EHIP, "stray field launch failed: %s", hipGetErrorString(hipGetLastError()));
+    h->stray_dirty = false;
+    return ASD_OK;
+}
+
 static int capture_graph(asd_t *h, int cur)
 {
     hipGraph_t g = nullptr;
@@ -974,6 +1072,7 @@ int asd_step(asd_t *h, int64_t n)
     if (h->step + n >= ((int64_t)1 << 32))
         return fail(h, ASD_ESTATE, "step counter would exceed 2^32 (Philox counter word)");
     if (n == 0) return ASD_OK;
+    if (int rc = refresh_stray(h)) return rc;
     int64_t done = 0;
     if (h->graph_steps > 0 && n >= h->graph_steps) {
         if (h->graph_kernel != h->kernel || h->graph_tile != h->tile_cfg) drop_graphs(h);
@@ -1038,6 +1137,7 @@ int asd_shift_window(asd_t *h, int32_t columns)
             return fail(h, ASD_EHIP, "column copy failed");
         h->origin[s] += columns;
     }
+    h->stray_dirty = true;
     if (launch_set_i32((int32_t *)(h->ws + h->L.off_origin), h->origin.data(), (int)h->origin.size(),
                        h->stream))
         return fail(h, ASD_EHIP, "origin update failed");
@@ -1300,6 +1400,7 @@ int asd_thermalise_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32
     a.step = step;
     a.rounds = h->p.philox_rounds;
     if (launch_cone_columns(a, h->stream)) return fail(h, ASD_EHIP, "cone launch failed");
+    h->stray_dirty = true;
     return ASD_OK;
 }
 
@@ -1311,7 +1412,8 @@ int asd_demag_field(asd_t *h, double *per_cell, int32_t *mesh)
     const DemagDev &g = h->dm;
     const char *w = h->ws;
     const size_t n = (size_t)g.n_sys * 3 * g.ncell;
-    int rc;
+    int rc = refresh_stray(h);
+    if (rc) return rc;
     if (h->elem == 8)
         rc = launch_demag(g, (const double *)(w + h->L.off_S[h->cur]), h->L.ncs,
                           (const SysDev *)(w + h->L.off_sys), (const int32_t *)(w + h->L.off_origin),

@@ -69,6 +69,16 @@ struct DemagDev {
     int32_t xb_y, xb_z;       // x lines per workgroup in the y and z passes
     int32_t n_sys;
     FastDivH fd_cx, fd_cy, fd_cz;
+    // stray field of a frozen track: the same pipeline on a mesh that
+    // extends the window's cells along x over the whole stored track
+    // (window cell i is cell i + ceil(origin / cx) of this mesh); its
+    // sources are the stored sites outside the window and its output is
+    // kept at the window cells only
+    int32_t stray;            // 1 for the track mesh
+    int32_t ncx_win;          // track mesh: window cells along x
+    int32_t ncell_win;        // track mesh: cells of the window mesh
+    void *bstray;             // window mesh: added to the result when not null;
+                              // track mesh: the output [S][3][ncell_win]
     void *wx;                 // complex [S][3][ncz][ncy][Px]
     void *wy;                 // complex [S][3][ncz][Py][Px]
     void *bd[2];              // field (T) per coarse cell, [S][3][ncell], one per Heun stage

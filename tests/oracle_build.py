@@ -77,3 +77,26 @@ def demag_cells(w: W.Workload, cell, origin: int = 0):
     inwin = (x >= 0) & (x < w.nx)
     dcell = np.where(inwin, x // cx + dn[0] * (y // cy + dn[1] * (z // cz)), -1).astype(np.int32)
     return dn, dd, dcell
+
+
+def track_stray(w: W.Workload, cell, origin: int, S) -> np.ndarray:
+    """Field (T) of the frozen track at the window's coarse cells, float[3, ncell]:
+    the window's cells continued along the whole stored track (window cell i is
+    track cell i + ceil(origin / cx)), Eq. 6 over the stored sites outside the
+    window, Eq. 7 summed directly, read at the window's cells."""
+    nx = w.track_nx or w.nx
+    n = oracle.lattice_sites(w.kind, nx, w.ny, w.nz)
+    idx = np.arange(n)
+    lc = idx if w.kind == W.SC else idx // 2
+    xw, y, z = lc % nx - origin, (lc // nx) % w.ny, lc // (nx * w.ny)
+    cx, cy, cz = cell
+    dn, dd, _ = demag_cells(w, cell, origin)
+    i0 = -(-origin // cx)
+    it = xw // cx + i0
+    nt = int(it.max()) + 1
+    frozen = (xw < 0) | (xw >= w.nx)
+    dcell = np.where(frozen, it + nt * (y // cy + dn[1] * (z // cz)), -1).astype(np.int32)
+    B = oracle.demag_field(S, dcell, (nt, dn[1], dn[2]), dd, w.mu_s)
+    i, j, k = np.meshgrid(np.arange(dn[0]), np.arange(dn[1]), np.arange(dn[2]), indexing="ij")
+    win = (i + i0 + nt * (j + dn[1] * k)).transpose(2, 1, 0).reshape(-1)  # window cell order
+    return B[:, win]

@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 import workloads as W
-from oracle_build import demag_cells, oracle_labels, oracle_system, window_mask
+from oracle_build import demag_cells, oracle_labels, oracle_system, track_stray, window_mask
 from paper_2502_02236_amd import asd as A
 from paper_2502_02236_amd import bridge
 
@@ -107,9 +107,38 @@ def test_demag_field_matches_direct_sum(name, w, cell, n_sys, prec):
     scale = mu0_ms(w)
     for s, S in enumerate(states):
         ref = oracle.demag_field(S, dcell, dn, dd, w.mu_s)
+        if name.startswith("track"):  # + the field of the frozen track
+            ref = ref + track_stray(w, cell, 7, S)
         err = float(np.max(np.abs(got[s] - ref))) / scale
         say(f"  system {s}: max |B_gpu - B_oracle| / mu0 Ms = {err:.3e} (|B| max {np.max(np.abs(ref)):.3f} T)")
         assert err <= FIELD_TOL[prec], (name, s, err)
+    h.close()
+
+
+@pytest.mark.parametrize("prec", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("origin", [0, 3, 10, 18])
+def test_track_stray_field_matches_direct_sum(prec, origin):
+    """Field of the frozen track at the window cells, for window origins aligned
+    and not aligned with the coarse cells, up to the far end of the track."""
+    w = track()
+    cell = (4, 5, 2)
+    h = bridge.make_handle(w, prec, demag_cell=cell, n_systems=2)
+    lab = h.labels()
+    states = [random_state(w, lab, 31 + s) for s in range(2)]
+    if origin:
+        h.shift_window(origin)
+    for s, S in enumerate(states):
+        h.set_spins(S, s)
+    got, _ = h.demag_field()
+    dn, dd, dcell = demag_cells(w, cell, origin)
+    for s, S in enumerate(states):
+        stray = track_stray(w, cell, origin, S)
+        ref = oracle.demag_field(S, dcell, dn, dd, w.mu_s) + stray
+        err = float(np.max(np.abs(got[s] - ref))) / mu0_ms(w)
+        say(f"[stray] origin={origin} prec={prec} system {s}: err {err:.3e}, "
+            f"|stray| max {np.max(np.abs(stray)):.4f} T")
+        assert err <= FIELD_TOL[prec]
+        assert np.max(np.abs(stray)) > 1e-3  # the track's field is not negligible
     h.close()
 
 
@@ -161,12 +190,14 @@ def test_heun_with_demag_matches_oracle(name, w, cell, n_sys, prec, variant):
     h.close()
 
 
-@pytest.mark.parametrize("prec", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
-def test_track_with_demag_and_shifts(prec):
-    """Moving window: the demagnetising mesh moves with the window; graph-captured
-    segments (the demag kernels are plain launches, no memset nodes) replayed."""
+@pytest.mark.parametrize("prec,cell", [(A.ASD_FP64, (5, 4, 5)), (A.ASD_FP32, (5, 4, 5)),
+                                       (A.ASD_FP64, (4, 3, 2)), (A.ASD_FP32, (7, 6, 3))],
+                         ids=["fp64_5x4x5", "fp32_5x4x5", "fp64_4x3x2", "fp32_7x6x3_ragged"])
+def test_track_with_demag_and_shifts(prec, cell):
+    """Moving window: the demagnetising mesh moves with the window and the frozen
+    track's stray field is recomputed after every shift; graph-captured segments
+    (the demag kernels are plain launches, no memset nodes) replayed."""
     w = track()
-    cell = (5, 4, 5)
     shifts = [(10, 1), (20, 2)]
     steps = 40
     h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10)
@@ -185,14 +216,14 @@ def test_track_with_demag_and_shifts(prec):
     done = 0
     for at, cols in shifts + [(steps, 0)]:
         dn, dd, dcell = demag_cells(w, cell, origin=org)
-        sysm.set_demag((dn, dd, dcell))
+        sysm.set_demag((dn, dd, dcell), stray=track_stray(w, cell, org, S))
         S = sysm.heun(S, done, at - done)
         done = at
         if cols:
             org += cols
             sysm.set_active(window_mask(w, org), org)
     err = float(np.max(np.abs(h.get_spins().astype(np.float64) - S)))
-    say(f"[demag track] prec={prec} max |dS| = {err:.3e}")
+    say(f"[demag track] prec={prec} cell={cell} max |dS| = {err:.3e}")
     assert err <= SPIN_TOL[prec]
     h.close()
 

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as W
-from oracle_build import free_spins_system, oracle_system
+from oracle_build import demag_cells, free_spins_system, oracle_system, track_stray
 
 
 def aharoni_Dz(a, b, c):
@@ -171,3 +171,29 @@ def test_heun_with_demag_is_macrospin_with_shape_anisotropy():
     assert keff < w.ku
     nodemag = oracle_system(w).heun(S, 0, steps)
     assert np.max(np.abs(nodemag[:, 0] - Sf)) > 1e-6
+
+
+@pytest.mark.parametrize("origin,cell", [(0, (3, 2, 2)), (5, (3, 2, 2)), (7, (4, 3, 5))])
+def test_track_stray_plus_window_field_is_whole_track_field(origin, cell):
+    """Superposition on the window's cells: the field of the window's own sites
+    (window mesh) plus the frozen track's (track mesh aligned with it) equals
+    the field of all stored sites on the track mesh, read at the window cells."""
+    w = W.c5_track_window().scaled(nx=14, ny=6, nz=5, track_nx=26, grains=False)
+    n = w.track_nx * w.ny * w.nz
+    S = W.random_spins(n, 3)
+    dn, dd, dcell = demag_cells(w, cell, origin)
+    own = oracle.demag_field(S, dcell, dn, dd, w.mu_s)
+    stray = track_stray(w, cell, origin, S)
+    # all stored sites on the track mesh
+    cx, cy, cz = cell
+    idx = np.arange(n)
+    xw, y, z = idx % w.track_nx - origin, (idx // w.track_nx) % w.ny, idx // (w.track_nx * w.ny)
+    i0 = -(-origin // cx)
+    it = xw // cx + i0
+    nt = int(it.max()) + 1
+    dall = (it + nt * (y // cy + dn[1] * (z // cz))).astype(np.int32)
+    Ball = oracle.demag_field(S, dall, (nt, dn[1], dn[2]), dd, w.mu_s)
+    i, j, k = np.meshgrid(np.arange(dn[0]), np.arange(dn[1]), np.arange(dn[2]), indexing="ij")
+    win = (i + i0 + nt * (j + dn[1] * k)).transpose(2, 1, 0).reshape(-1)
+    np.testing.assert_allclose(own + stray, Ball[:, win], rtol=0, atol=1e-12)
+    assert np.max(np.abs(stray)) > 1e-3
