@@ -94,6 +94,8 @@ def _declare(L):
                                    C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
     L.orc_newell_tensor.argtypes = [C.c_double] * 6 + [f64p]
     L.orc_demag_direct.argtypes = [C.c_int] * 3 + [C.c_double] * 3 + [f64p, f64p]
+    L.orc_mc_sweeps.argtypes = [P(OrcSystem), i8p, f64p, f64p, f64p, C.c_int64, C.c_int64]
+    L.orc_mc_sweeps.restype = C.c_int
     L.orc_cone_theta_max.argtypes = [C.c_double]
     L.orc_cone_theta_max.restype = C.c_double
     L.orc_cone_spin.argtypes = [f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -262,6 +264,16 @@ class System:
                                   _ptr(Sz, f64p), step0, nsteps)
         if rc != 0:
             raise MemoryError("oracle step allocation failed")
+        return np.stack([Sx, Sy, Sz])
+
+    def mc(self, S, colour, sweep0: int, nsweeps: int) -> np.ndarray:
+        """Metropolis sweeps of the same Hamiltonian at T_amb (colour: int8 per
+        site, 0 or 1, -1 = never visited)."""
+        S = np.array(S, dtype=np.float64, copy=True).reshape(3, -1)
+        Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+        col = np.ascontiguousarray(colour, dtype=np.int8)
+        lib().orc_mc_sweeps(C.byref(self._s), _ptr(col, i8p), _ptr(Sx, f64p), _ptr(Sy, f64p),
+                            _ptr(Sz, f64p), sweep0, nsweeps)
         return np.stack([Sx, Sy, Sz])
 
     def magnetisation(self, S, n_grains: int):

@@ -909,3 +909,74 @@ static int demag_cells(const orc_system *s, const double *Sx, const double *Sy, 
     free(H);
     return 0;
 }
+
+
+/* ------------------------------------------------------------------ */
+/* Metropolis Monte Carlo of the same Hamiltonian (the calibration of */
+/* the exchange constant, Sec. III with Eq. 8).  Site energy          */
+/*   E_i(S) = -mu_s S . (B_ex + p B) - k_u S_z^2,                      */
+/* B_ex = Eq. 2 summed by shell as in the field above.  A sweep visits */
+/* the sites of colour 0 in index order, then those of colour 1; no    */
+/* two neighbours share a colour, so the order within a colour does    */
+/* not matter.  A visit takes Philox words (site, sweep, system, 2):   */
+/* trial direction uniform on the sphere, S_z = 2 u0 - 1 with          */
+/* u0 = (w0 + 1/2) 2^-32 and azimuth 2 pi w1 2^-32; the trial is       */
+/* accepted when dE <= 0 or (w2 + 1/2) 2^-32 < exp(-dE / kB T), with   */
+/* T the system's ambient temperature.                                 */
+/* ------------------------------------------------------------------ */
+static void mc_visit(const orc_system *s, double *Sx, double *Sy, double *Sz, int64_t i,
+                     int64_t sweep, double pol)
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int sh = 0; sh < s->n_shells; ++sh) {
+        double part[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
+            if (s->shell[k] != sh) continue;
+            int64_t j = s->col[k];
+            if (s->label[j] != s->label[i]) continue;
+            part[0] = part[0] + Sx[j];
+            part[1] = part[1] + Sy[j];
+            part[2] = part[2] + Sz[j];
+        }
+        double cex = s->J[sh] / s->mu_s;
+        acc[0] = acc[0] + cex * part[0];
+        acc[1] = acc[1] + cex * part[1];
+        acc[2] = acc[2] + cex * part[2];
+    }
+    double h[3] = {acc[0] + pol * s->B[0], acc[1] + pol * s->B[1], acc[2] + pol * s->B[2]};
+    uint32_t ctr[4] = {s->ctr0[i], (uint32_t)sweep, s->sys_id, 2u};
+    uint32_t w[4];
+    orc_philox4x32(s->rounds, (uint32_t)s->seed, (uint32_t)(s->seed >> 32), ctr, w);
+    double z = 2.0 * (((double)w[0] + 0.5) * TWO_M32) - 1.0;
+    double r = sqrt(1.0 - z * z);
+    double sp, cp;
+    orc_sincos2pi((double)w[1] * TWO_M32, &sp, &cp);
+    double t[3] = {r * cp, r * sp, z};
+    double d[3] = {t[0] - Sx[i], t[1] - Sy[i], t[2] - Sz[i]};
+    double ku = s->ku_grain ? s->ku_grain[s->label[i]] : s->ku;
+    double dE = -s->mu_s * ((d[0] * h[0] + d[1] * h[1]) + d[2] * h[2]) -
+                ku * (t[2] * t[2] - Sz[i] * Sz[i]);
+    int accept = dE <= 0.0;
+    if (!accept && s->T_amb > 0.0) {
+        double u = ((double)w[2] + 0.5) * TWO_M32;
+        accept = u < orc_exp(-(dE / (ORC_KB * s->T_amb)));
+    }
+    if (accept) {
+        Sx[i] = t[0];
+        Sy[i] = t[1];
+        Sz[i] = t[2];
+    }
+}
+
+int orc_mc_sweeps(const orc_system *s, const int8_t *colour, double *Sx, double *Sy, double *Sz,
+                  int64_t sweep0, int64_t nsweeps)
+{
+    for (int64_t t = 0; t < nsweeps; ++t) {
+        int64_t sweep = sweep0 + t;
+        double pol = polarity(s, sweep);
+        for (int c = 0; c < 2; ++c)
+            for (int64_t i = 0; i < s->n_sites; ++i)
+                if (evolves(s, i) && colour[i] == c) mc_visit(s, Sx, Sy, Sz, i, sweep, pol);
+    }
+    return 0;
+}

@@ -100,3 +100,12 @@ def track_stray(w: W.Workload, cell, origin: int, S) -> np.ndarray:
     i, j, k = np.meshgrid(np.arange(dn[0]), np.arange(dn[1]), np.arange(dn[2]), indexing="ij")
     win = (i + i0 + nt * (j + dn[1] * k)).transpose(2, 1, 0).reshape(-1)  # window cell order
     return B[:, win]
+
+
+def checkerboard(w: W.Workload) -> np.ndarray:
+    """Colour (x + y + z) mod 2 of every stored SC site (stored-lattice coordinates)."""
+    nx = w.track_nx or w.nx
+    n = oracle.lattice_sites(w.kind, nx, w.ny, w.nz)
+    idx = np.arange(n)
+    x, y, z = idx % nx, (idx // nx) % w.ny, idx // (nx * w.ny)
+    return ((x + y + z) % 2).astype(np.int8)
