@@ -272,6 +272,19 @@ int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int
                            int32_t cy, int32_t cz, const double *mcell, uint32_t step);
 
 /* Step counter and window origin of system sys (host copies). */
+/* n Metropolis Monte Carlo sweeps of the same Hamiltonian (exchange,
+ * anisotropy, write field with its polarity at the sweep index; no thermal
+ * field) at each system's ambient temperature: the calibration of the
+ * exchange constant against the Curie temperature (Sec. III with Eq. 8).
+ * A sweep visits the window sites with (x + y + z) even, then those with it
+ * odd (stored-lattice coordinates); a visit proposes a direction uniform on
+ * the sphere from Philox words (site, sweep, system, 2) and accepts it with
+ * probability min(1, exp(-dE / kB T)).  The sweep index is the step counter,
+ * which advances by n.  ASD_EUNSUPPORTED for L1_0 lattices, for a periodic
+ * axis of odd length (the checkerboard would pair neighbours) and with the
+ * demagnetising field. */
+int asd_mc_sweep(asd_t *h, int64_t n);
+
 /* Demagnetising field (Eq. 7) of the current spins of every system, as
  * the flux density mu0 H_d (T) per coarse cell of the window (including the
  * frozen track's stray field for a track system): per_cell is a host array

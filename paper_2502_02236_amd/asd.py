@@ -29,7 +29,7 @@ SYMBOLS = [
     "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
     "asd_neighbour_count", "asd_get_neighbours", "asd_host_grain_labels", "asd_host_neighbours",
-    "asd_coarse_grain", "asd_thermalise_columns", "asd_demag_field",
+    "asd_coarse_grain", "asd_thermalise_columns", "asd_demag_field", "asd_mc_sweep",
     "asd_get_state", "asd_set_step", "asd_philox",
     "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_count", "asd_variant_name",
     "asd_strerror",
@@ -112,6 +112,7 @@ def lib():
         L.asd_thermalise_columns.argtypes = [h, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                              C.c_int32, C.c_int32, vp, C.c_uint32]
         L.asd_demag_field.argtypes = [h, vp, vp]
+        L.asd_mc_sweep.argtypes = [h, C.c_int64]
         L.asd_variant_count.argtypes = [h, C.c_int32, P(C.c_int32)]
         L.asd_variant_name.argtypes = [h, C.c_char_p, C.c_size_t]
         L.asd_strerror.argtypes = [C.c_int]
@@ -330,6 +331,10 @@ class Handle:
         _check(lib().asd_thermalise_columns(self.h, sys, x0, ncols, cx, cy, cz, m.data_ptr(),
                                             step), self.h)
         self.stream.synchronize()
+
+    def mc_sweep(self, n: int):
+        """n Metropolis sweeps at each system's ambient temperature."""
+        _check(lib().asd_mc_sweep(self.h, n), self.h)
 
     def demag_field(self):
         """Demagnetising flux density mu0 H_d (T) of the current spins per coarse

@@ -1404,6 +1404,55 @@ int asd_thermalise_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32
     return ASD_OK;
 }
 
+int asd_mc_sweep(asd_t *h, int64_t n)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (n < 0) return fail(h, ASD_EINVAL, "n must be >= 0");
+    if (h->p.lattice != ASD_SC)
+        return fail(h, ASD_EUNSUPPORTED, "Metropolis sweeps use the simple-cubic checkerboard");
+    if (h->dm.on)
+        return fail(h, ASD_EUNSUPPORTED, "Metropolis sweeps do not include the demagnetising field");
+    for (const HostSys &hs : h->sys) {
+        const asd_system_desc &d = hs.desc;
+        if ((d.bc_x == ASD_BC_PERIODIC && d.nx % 2) || (d.bc_y == ASD_BC_PERIODIC && d.ny % 2) ||
+            (d.bc_z == ASD_BC_PERIODIC && d.nz % 2))
+            return fail(h, ASD_EUNSUPPORTED,
+                        "the checkerboard needs an even length along every periodic axis");
+    }
+    if (h->step + n >= ((int64_t)1 << 32))
+        return fail(h, ASD_ESTATE, "step counter would exceed 2^32 (Philox counter word)");
+    if (n == 0) return ASD_OK;
+    // in place on the current buffer (a Heun step only reads the window of the
+    // current buffer; the other one's window is overwritten)
+    for (int64_t t = 0; t < n; ++t) {
+        int rc;
+        if (h->p.precision == ASD_FP64) {
+            MCArgs<double> m;
+            m.st = make_args<double>(h, h->cur, (int)t);
+            m.st.tile_sys = (const int32_t *)(h->ws + h->L.off_tile);
+            m.st.So = (double *)(h->ws + h->L.off_S[h->cur]);
+            m.mu_s = h->p.mu_s;
+            m.ku = h->p.k_u;
+            m.ku_grain = (const double *)(h->ws + h->L.off_ku);
+            rc = launch_mc_sweep_f64(m, h->L.n_tiles, h->stream);
+        } else {
+            MCArgs<float> m;
+            m.st = make_args<float>(h, h->cur, (int)t);
+            m.st.tile_sys = (const int32_t *)(h->ws + h->L.off_tile);
+            m.st.So = (float *)(h->ws + h->L.off_S[h->cur]);
+            m.mu_s = h->p.mu_s;
+            m.ku = h->p.k_u;
+            m.ku_grain = (const double *)(h->ws + h->L.off_ku);
+            rc = launch_mc_sweep_f32(m, h->L.n_tiles, h->stream);
+        }
+        if (rc) return fail(h, ASD_EHIP, "Metropolis launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    if (launch_advance_step((int64_t *)(h->ws + h->L.off_step), n, h->stream))
+        return fail(h, ASD_EHIP, "advance launch failed");
+    h->step += n;
+    return ASD_OK;
+}
+
 int asd_demag_field(asd_t *h, double *per_cell, int32_t *mesh)
 {
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");

@@ -195,5 +195,15 @@ int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, do
                          void *stream);
 int launch_energy_f64(const EnergyArgs<double> &a, int n_tiles, void *stream);
 int launch_energy_f32(const EnergyArgs<float> &a, int n_tiles, void *stream);
+// Metropolis sweeps in place on st.S (checkerboard colour 0, then 1); the
+// sweep index is the step counter + st.step_off
+template <typename T>
+struct MCArgs {
+    StepArgs<T> st;           // S = So = the current buffer
+    double mu_s, ku;          // J/T, J (uniform anisotropy)
+    const double *ku_grain;   // per global grain (J) when st.c.has_can_grain
+};
+int launch_mc_sweep_f64(const MCArgs<double> &a, int n_tiles, void *stream);
+int launch_mc_sweep_f32(const MCArgs<float> &a, int n_tiles, void *stream);
 
 }  // namespace asd

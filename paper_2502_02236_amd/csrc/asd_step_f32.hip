@@ -17,6 +17,11 @@ int launch_fused_step_f32(const StepArgs<float> &a, int n_blocks, void *stream)
     return launch_fused<float>(a, n_blocks, stream);
 }
 
+int launch_mc_sweep_f32(const MCArgs<float> &a, int n_tiles, void *stream)
+{
+    return launch_mc<float>(a, n_tiles, stream);
+}
+
 int launch_energy_f32(const EnergyArgs<float> &e, int n_tiles, void *stream)
 {
     hipLaunchKernelGGL(k_energy<float>, dim3(n_tiles), dim3(kPlainTile), 0, (hipStream_t)stream, e);

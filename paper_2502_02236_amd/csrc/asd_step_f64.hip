@@ -18,6 +18,11 @@ int launch_fused_step_f64(const StepArgs<double> &a, int n_blocks, void *stream)
     return launch_fused<double>(a, n_blocks, stream);
 }
 
+int launch_mc_sweep_f64(const MCArgs<double> &a, int n_tiles, void *stream)
+{
+    return launch_mc<double>(a, n_tiles, stream);
+}
+
 int launch_energy_f64(const EnergyArgs<double> &e, int n_tiles, void *stream)
 {
     hipLaunchKernelGGL(k_energy<double>, dim3(n_tiles), dim3(kPlainTile), 0, (hipStream_t)stream, e);

@@ -1,0 +1,243 @@
+"""GPU parity of the Metropolis Monte Carlo sweeps (the calibration of the
+exchange constant, Sec. III with Eq. 8), through the C ABI.
+
+Bars: FP64 sweeps bit-identical to the oracle (same Philox words, the same
+arithmetic in the same order, so every accept/reject decision is the same);
+FP32 sweeps take their decisions in FP32, so they are compared through
+equilibrium averages: within 4 standard errors (+0.005) of the closed forms
+and of the oracle's ensemble.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle_build import checkerboard, free_spins_system, oracle_labels, oracle_system, window_mask
+from paper_2502_02236_amd import asd as A
+from paper_2502_02236_amd import bridge
+
+pytestmark = pytest.mark.gpu
+
+MU_S = 3.23 * W.MU_B
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    A.lib()
+    return torch
+
+
+def slab(**kw):
+    w = W.c2_granular_slab().scaled(nx=36, ny=28, nz=7, x0=5e-9, y0=4e-9, grain_pitch=4.0e-9,
+                                    spot_mode=W.SPOT_NONE, T_amb=600.0)
+    return w.scaled(**kw)
+
+
+def track(**kw):
+    w = W.c5_track_window().scaled(nx=30, ny=20, nz=5, track_nx=48, steps_per_bit=3,
+                                   x0=4.5e-9, y0=3e-9, grain_pitch=3.0e-9, spot_mode=W.SPOT_NONE,
+                                   T_amb=500.0)
+    return w.scaled(**kw)
+
+
+def random_state(w, labels, seed):
+    S = W.random_spins(len(labels), seed)
+    S[:, labels < 0] = 0.0
+    return S
+
+
+CASES = [
+    ("slab_600K", slab(), None, 0),
+    ("slab_cold_0K", slab(T_amb=0.0), None, 0),
+    ("slab_hot_1200K", slab(T_amb=1200.0, B=(0.3, 0.0, 0.8)), None, 0),
+    ("periodic_z_cube", slab(nx=12, ny=10, nz=8, bc=(1, 1, 1), grains=False), None, 0),
+    ("track_window_ku_spread_shifted", track(), "ku", 5),
+]
+
+
+@pytest.mark.parametrize("name,w,ku_mode,shift", CASES, ids=[c[0] for c in CASES])
+def test_mc_fp64_bit_identical_to_oracle(name, w, ku_mode, shift):
+    sweeps = 25
+    say(f"[mc fp64] {name} sweeps={sweeps}")
+    lab = oracle_labels(w)
+    ku = None
+    if ku_mode:
+        ng = int(lab.max()) + 1
+        ku = W.grain_ku(ng, w.ku, 0.05, w.seed)
+    h = bridge.make_handle(w, A.ASD_FP64, ku_grain=ku)
+    glab = h.labels()
+    np.testing.assert_array_equal(glab, lab)
+    if shift:
+        h.shift_window(shift)
+    S0 = random_state(w, lab, 3)
+    h.set_spins(S0)
+    h.mc_sweep(sweeps)
+    got = h.get_spins()
+    track_w = w.bc[0] == W.BC_TRACK
+    sysm = oracle_system(w, labels=lab, ku_grain=ku,
+                         active=window_mask(w, shift) if track_w else None, origin=shift)
+    ref = sysm.mc(S0, checkerboard(w), 0, sweeps)
+    diff = float(np.max(np.abs(got - ref)))
+    moved = float(np.mean(np.any(ref != S0, axis=0)[lab >= 0]))
+    say(f"  max |dS| = {diff:.3e}, fraction of magnetic sites moved {moved:.3f}")
+    assert diff == 0.0
+    if w.T_amb > 0:
+        assert moved > 0.2
+    # the step counter advanced by the sweeps
+    assert h.state(0)[0] == sweeps
+    h.close()
+
+
+def test_mc_fp64_multi_system_temperatures():
+    """Systems of one handle at their own temperatures (T_system), each its own
+    Philox counter word 2."""
+    w = slab(nx=16, ny=12, nz=5, grains=False)
+    Ts = [150.0, 700.0, 1400.0]
+    ins = [bridge.SystemInputs(w, T_system=T) for T in Ts]
+    h = A.Handle(bridge.params_for(w, A.ASD_FP64), [i.desc for i in ins])
+    dr, _ = bridge.drive_for(w)
+    h.set_drive(dr)
+    S0 = [W.random_spins(w.n_sites, 10 + k) for k in range(3)]
+    for k in range(3):
+        h.set_spins(S0[k], k)
+    h.mc_sweep(12)
+    for k, T in enumerate(Ts):
+        ref = oracle_system(w, sys_id=k, T_amb=T).mc(S0[k], checkerboard(w), 0, 12)
+        assert np.array_equal(h.get_spins(k), ref), k
+    h.close()
+
+
+@pytest.mark.parametrize("prec", [A.ASD_FP32, A.ASD_FP64], ids=["fp32", "fp64"])
+def test_mc_heisenberg_ring_correlation(prec):
+    """<S_i . S_i+1> of the classical Heisenberg ring = coth K - 1/K."""
+    n, J = 4096, 6.7e-21
+    for K in (0.5, 2.0):
+        T = J / (W.KB * K)
+        w = W.Workload("ring", nx=n, ny=1, nz=1, bc=(1, 0, 0), J=(J,), ku=0.0,
+                       B=(0.0, 0.0, 0.0), T_amb=T, seed=43)
+        h = bridge.make_handle(w, prec)
+        h.set_spins(W.random_spins(n, 7))
+        h.mc_sweep(300)
+        acc = []
+        for b in range(20):
+            h.mc_sweep(40)
+            S = h.get_spins().astype(np.float64)
+            acc.append((S * np.roll(S, -1, axis=1)).sum(0).mean())
+        m, err = np.mean(acc), np.std(acc, ddof=1) / math.sqrt(len(acc))
+        expect = 1 / math.tanh(K) - 1 / K
+        say(f"[mc ring] prec={prec} K={K}: {m:.4f} +- {err:.4f} (exact {expect:.4f})")
+        assert abs(m - expect) < 4 * err + 0.005
+        h.close()
+
+
+def test_mc_fp32_magnetisation_matches_oracle_ensemble():
+    """Grain-free slab crop in its ordered phase and near the transition: FP32 <m_z>
+    and <|m|> over sweeps against the FP64 oracle's over the same sweeps."""
+    for T in (400.0, 900.0):
+        w = slab(nx=16, ny=16, nz=6, grains=False, T_amb=T, B=(0.0, 0.0, 0.5))
+        h = bridge.make_handle(w, A.ASD_FP32)
+        S0 = np.stack([np.zeros(w.n_sites), np.zeros(w.n_sites), np.ones(w.n_sites)])
+        h.set_spins(S0)
+        sysm = oracle_system(w)
+        col = checkerboard(w)
+        So = sysm.mc(S0, col, 0, 200)
+        h.mc_sweep(200)
+        g, o = [], []
+        for b in range(25):
+            h.mc_sweep(20)
+            So = sysm.mc(So, col, 200 + 20 * b, 20)
+            g.append(h.get_spins().astype(np.float64).mean(axis=1))
+            o.append(So.mean(axis=1))
+        g, o = np.array(g), np.array(o)
+        for k, name in ((2, "m_z"),):
+            se = math.sqrt(g[:, k].var(ddof=1) / len(g) + o[:, k].var(ddof=1) / len(o))
+            say(f"[mc fp32] T={T}: {name} gpu {g[:, k].mean():.4f} oracle {o[:, k].mean():.4f} se {se:.4f}")
+            assert abs(g[:, k].mean() - o[:, k].mean()) < 4 * se + 0.005
+        h.close()
+
+
+def test_mc_curie_temperature_and_eq8_correction_factor():
+    """Binder cumulants of periodic simple-cubic Heisenberg cubes (L = 8, 16; no
+    anisotropy, no field) cross at T_C = 1.443 J/kB (classical Heisenberg model);
+    with Eq. 8, J = 3 kB T_C / (eps z), this is the paper's mean-field correction
+    eps_SC = 0.72 (z = 6).  Tolerance 2 % (finite size, statistics)."""
+    J = 6.7e-21
+    Tc = 1.443 * J / W.KB
+    ratios = [0.94, 0.97, 1.0, 1.03, 1.06]
+    Ls, reps = (8, 16), 6
+    w0 = W.Workload("cube", bc=(1, 1, 1), J=(J,), ku=0.0, B=(0.0, 0.0, 0.0), seed=33)
+    ins, meta = [], []
+    for L in Ls:
+        for r in ratios:
+            for k in range(reps):
+                ins.append(bridge.SystemInputs(w0.scaled(nx=L, ny=L, nz=L), T_system=r * Tc))
+                meta.append((L, r, k))
+    h = A.Handle(bridge.params_for(w0, A.ASD_FP32), [i.desc for i in ins])
+    dr, _ = bridge.drive_for(w0, T_amb=0.0)
+    h.set_drive(dr)
+    for i, (L, _, k) in enumerate(meta):
+        h.set_spins(W.random_spins(L ** 3, 200 + i) if k % 2 else
+                    np.stack([np.zeros(L ** 3), np.zeros(L ** 3), np.ones(L ** 3)]), i)
+    h.mc_sweep(3000)
+    m2 = np.zeros(len(meta))
+    m4 = np.zeros(len(meta))
+    ns = 0
+    for b in range(800):
+        h.mc_sweep(5)
+        _, per_sys = h.magnetization()
+        m = np.linalg.norm(per_sys[:, :3], axis=1) / per_sys[:, 3]
+        m2 += m ** 2
+        m4 += m ** 4
+        ns += 1
+    U = {}
+    for L in Ls:
+        for r in ratios:
+            idx = [i for i, mm in enumerate(meta) if mm[:2] == (L, r)]
+            a2 = m2[idx].sum() / (ns * len(idx))
+            a4 = m4[idx].sum() / (ns * len(idx))
+            U[(L, r)] = 1 - a4 / (3 * a2 * a2)
+    d = np.array([U[(Ls[0], r)] - U[(Ls[1], r)] for r in ratios])
+    say("  U4 L=8 ", [round(float(U[(8, r)]), 4) for r in ratios])
+    say("  U4 L=16", [round(float(U[(16, r)]), 4) for r in ratios])
+    assert d[0] < 0 and d[-1] > 0
+    k = int(np.argmax(d > 0))
+    r0, r1 = ratios[k - 1], ratios[k]
+    cross = r0 + (r1 - r0) * (-d[k - 1]) / (d[k] - d[k - 1])
+    eps = 3 * cross * 1.443 / 6
+    say(f"  Binder crossing T/Tc = {cross:.4f}; Eq. 8 eps_SC = {eps:.4f} (paper 0.72)")
+    assert abs(cross - 1.0) < 0.02
+    assert abs(eps - 0.72) < 0.02
+    h.close()
+
+
+def test_mc_error_paths():
+    w = slab()
+    h = bridge.make_handle(w.scaled(nx=35), A.ASD_FP32)  # periodic x of odd length
+    with pytest.raises(A.AsdError) as e:
+        h.mc_sweep(1)
+    assert e.value.code == A.ASD_EUNSUPPORTED
+    h.close()
+    wl = W.c3_l10_window().scaled(nx=8, ny=8, nz=4, grains=False)
+    h = bridge.make_handle(wl, A.ASD_FP32)
+    with pytest.raises(A.AsdError) as e:
+        h.mc_sweep(1)
+    assert e.value.code == A.ASD_EUNSUPPORTED
+    h.close()
+    h = bridge.make_handle(w, A.ASD_FP32, demag_cell=(4, 4, 7))
+    with pytest.raises(A.AsdError) as e:
+        h.mc_sweep(1)
+    assert e.value.code == A.ASD_EUNSUPPORTED
+    with pytest.raises(A.AsdError) as e:
+        h.mc_sweep(-1)
+    assert e.value.code == A.ASD_EINVAL
+    h.close()
