@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track", "transfer",
-                                           "demag"], default="slab")
+                                           "demag", "mc"], default="slab")
     ap.add_argument("--demag-cell", type=int, nargs=3, default=[4, 4, 3],
                     help="coarse cell of the demag workload, in lattice cells")
     ap.add_argument("--kernel", choices=["auto", "plain", "fused"], default="auto")
@@ -293,6 +293,37 @@ def transfer_run(args, cell=7, reps=20):
                 th_bytes=th_bytes, e=e, cell=cell, reps=reps)
 
 
+MC_ALU_CYCLES = 101
+
+
+def mc_run(args):
+    """Metropolis sweeps of the 200x200x33 granular slab at its 300 K ambient
+    temperature (the exchange calibration of Sec. III with Eq. 8), timed with HIP
+    events on the handle's stream.  Algorithmic VALU lane-cycles per visited
+    magnetic site: Philox4x32-10 40, uniforms 6, trial S_z and radius 6 (one
+    square root), azimuth sine and cosine 10, exchange sum and scale 18, local
+    field 3, energy change 11, Boltzmann factor and test 7 (the four
+    transcendentals count 4 each): 101."""
+    import torch
+    from paper_2502_02236_amd import asd as A
+
+    prec = A.ASD_FP32 if args.precision == "fp32" else A.ASD_FP64
+    w, h, S0s, n_mag, n_sites, extra = build_workload("slab", prec, 0)
+    h.mc_sweep(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(h.stream)
+    h.mc_sweep(args.steps)
+    e1.record(h.stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    S = h.get_spins(0).astype(np.float64)
+    mz = float(S[2].sum() / n_mag)
+    h.close()
+    return dict(w=w, t=t, n_mag=n_mag, n_sites=n_sites, mz=mz)
+
+
 def cpu_baseline(target_s=15.0, steps=0):
     """The FP64 oracle, single-threaded plain C, on the full lattice for a few steps."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -346,6 +377,32 @@ def main():
                                     "kernel": "k_cone_columns",
                                     "bytes_per_site": 2 * 3 * t["e"] + 2},
         }), flush=True)
+        return
+    if args.workload == "mc":
+        r = mc_run(args)
+        per_sweep = r["t"] / args.steps
+        e = 4 if args.precision == "fp32" else 8
+        hbm = 2 * 3 * e * r["n_sites"] / per_sweep / 1e9
+        if args.precision == "fp32":
+            ach = MC_ALU_CYCLES * r["n_mag"] / per_sweep / 1e12
+            roof = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_T,
+                    "unit": "T VALU lane-cycles/s", "frac": ach / VALU_PEAK_T,
+                    "alu_cycles_per_magnetic_site": MC_ALU_CYCLES,
+                    "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": hbm / HBM_PEAK_GBS, "bytes_per_site": 6 * e}}
+        else:
+            roof = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hbm / HBM_PEAK_GBS, "bytes_per_site": 6 * e}
+        roof.update({"traffic": None, "kernel": "k_mc_colour (two launches per sweep)"})
+        print(json.dumps({
+            "metric": "Metropolis spin-updates/s (magnetic sites x sweeps)",
+            "value": r["n_mag"] * args.steps / r["t"], "unit": "spin-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * per_sweep,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": r["w"].name + "+metropolis300K", "sites": r["n_sites"],
+                       "magnetic_sites": r["n_mag"], "precision": args.precision},
+            "roofline": roof, "final_mz": r["mz"]}), flush=True)
         return
     r = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, args.graph_steps)
     demag = None
