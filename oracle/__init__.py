@@ -71,6 +71,18 @@ class OrcSystem(C.Structure):
     ]
 
 
+class OrcMM(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("periodic", C.c_int * 3),
+        ("h", C.c_double * 3), ("Ms0", C.c_double), ("A0", C.c_double), ("K0", C.c_double),
+        ("lambda_", C.c_double), ("gamma", C.c_double), ("Tc", C.c_double), ("mu_s", C.c_double),
+        ("dt", C.c_double), ("B", C.c_double * 3), ("n_bits", C.c_int), ("bits", u8p),
+        ("steps_per_bit", C.c_int64), ("spot_mode", C.c_int), ("T_amb", C.c_double),
+        ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+        ("v", C.c_double),
+    ]
+
+
 def _declare(L):
     L.orc_philox_batch.argtypes = [C.c_int, C.c_uint64, u32p, u32p, C.c_int64]
     L.orc_ln_batch.argtypes = [f64p, f64p, C.c_int64]
@@ -96,6 +108,12 @@ def _declare(L):
     L.orc_demag_direct.argtypes = [C.c_int] * 3 + [C.c_double] * 3 + [f64p, f64p]
     L.orc_mc_sweeps.argtypes = [P(OrcSystem), i8p, f64p, f64p, f64p, C.c_int64, C.c_int64]
     L.orc_mc_sweeps.restype = C.c_int
+    L.orc_langevin.argtypes = [C.c_double]
+    L.orc_langevin.restype = C.c_double
+    L.orc_mm_me.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.orc_mm_me.restype = C.c_double
+    L.orc_mm_rk4.argtypes = [P(OrcMM), f64p, C.c_int64, C.c_int64]
+    L.orc_mm_rk4.restype = C.c_int
     L.orc_cone_theta_max.argtypes = [C.c_double]
     L.orc_cone_theta_max.restype = C.c_double
     L.orc_cone_spin.argtypes = [f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -368,3 +386,45 @@ def cone_columns(kind, sx, ny, nz, label, S, x0, ncols, cx, cy, cz, mcell, round
                            _ptr(Sz, f64p), x0, ncols, cx, cy, cz, _ptr(mc, f64p), rounds, seed,
                            step, sys)
     return np.stack([Sx, Sy, Sz])
+
+
+# ---------------------------------------------------------------- micromagnetic region
+def langevin(x: float) -> float:
+    return lib().orc_langevin(x)
+
+
+def mm_me(T: float, Tc: float, b: float = 0.0) -> float:
+    """Equilibrium reduced magnetisation m_e(T) (b = mu_s |B| / kB in kelvin)."""
+    return lib().orc_mm_me(T, Tc, b)
+
+
+class MM:
+    """Micromagnetic LLG region integrated by RK4 (m float64[3, nx*ny*nz])."""
+
+    def __init__(self, *, n, h, Ms0, A0, K0, lam, gamma, Tc, mu_s, dt, B=(0.0, 0.0, 0.0),
+                 periodic=(0, 0, 0), bits=None, steps_per_bit=0, spot_mode=SPOT_NONE,
+                 T_amb=0.0, T_peak=0.0, fwhm=0.0, x0=0.0, y0=0.0, v=0.0):
+        p = OrcMM()
+        p.nx, p.ny, p.nz = n
+        for k in range(3):
+            p.periodic[k] = int(periodic[k])
+            p.h[k] = h[k]
+            p.B[k] = B[k]
+        p.Ms0, p.A0, p.K0, p.lambda_, p.gamma, p.Tc, p.mu_s, p.dt = (Ms0, A0, K0, lam, gamma, Tc,
+                                                                      mu_s, dt)
+        self.bits = None if bits is None else np.ascontiguousarray(bits, dtype=np.uint8)
+        p.n_bits = 0 if self.bits is None else len(self.bits)
+        p.bits = _ptr(self.bits, u8p)
+        p.steps_per_bit = steps_per_bit
+        p.spot_mode = spot_mode
+        p.T_amb, p.T_peak, p.fwhm, p.x0, p.y0, p.v = T_amb, T_peak, fwhm, x0, y0, v
+        self._p = p
+        self.n = n[0] * n[1] * n[2]
+
+    def rk4(self, m, step0: int, nsteps: int) -> np.ndarray:
+        m = np.array(m, dtype=np.float64, copy=True).reshape(3, -1)
+        assert m.shape[1] == self.n
+        flat = np.ascontiguousarray(m.reshape(-1))
+        if lib().orc_mm_rk4(C.byref(self._p), _ptr(flat, f64p), step0, nsteps) != 0:
+            raise MemoryError("oracle allocation failed")
+        return flat.reshape(3, -1)

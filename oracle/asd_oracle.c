@@ -980,3 +980,157 @@ int orc_mc_sweeps(const orc_system *s, const int8_t *colour, double *Sx, double 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Micromagnetic region (Sec. II): LLG without the thermal field (Eq. 1 */
+/* in Landau-Lifshitz form) on a finite-difference mesh, integrated by  */
+/* classic RK4 (the paper's integrator for these regions, Sec. III) with */
+/* the magnetisation renormalised after each step.  Field (tesla):       */
+/*   exchange   (2 A(T) / M_S(T)) lap m           (Eq. 4, 6-point stencil) */
+/*   anisotropy (2 K(T) / M_S(T)) (m . z) z       (Eq. 5)                 */
+/*   write field p(n) B                                                    */
+/* with M_S = M_S0 m_e, A = A_0 m_e^2, K = K_0 m_e^3 and the damping      */
+/* alpha = lambda (1 - T / 3 T_C) (Sec. II); m_e(T) is the root of        */
+/* m = L(3 T_C m / T + mu_s |B| / kB T), L the Langevin function.  T per  */
+/* cell from the laser spot at the stage time.                            */
+/* ------------------------------------------------------------------ */
+
+/* Langevin function coth x - 1/x for x >= 0; below 0.1 its Taylor series
+ * through x^11 (coefficients 2^2n B_2n / (2n)!, the closed form cancels
+ * there); coth from this file's exp. */
+double orc_langevin(double x)
+{
+    if (x < 0.1) {
+        double x2 = x * x;
+        double p = -1382.0 / 638512875.0;
+        p = 2.0 / 93555.0 + x2 * p;
+        p = -1.0 / 4725.0 + x2 * p;
+        p = 2.0 / 945.0 + x2 * p;
+        p = -1.0 / 45.0 + x2 * p;
+        p = 1.0 / 3.0 + x2 * p;
+        return x * p;
+    }
+    double e = orc_exp(-2.0 * x);
+    return (1.0 + e) / (1.0 - e) - 1.0 / x;
+}
+
+/* m_e(T): 64 halvings of [0, 1] keeping f(lo) >= 0 > f(hi), f(m) =
+ * L((3 T_C m + b) / T) - m, b = mu_s |B| / kB (kelvin).  This brackets the
+ * largest root: the ordered one below T_C, 0 above it when b = 0. */
+double orc_mm_me(double T, double Tc, double b)
+{
+    if (T <= 0.0) return 1.0;
+    double lo = 0.0, hi = 1.0;
+    for (int k = 0; k < 64; ++k) {
+        double mid = 0.5 * (lo + hi);
+        double f = orc_langevin((3.0 * Tc * mid + b) / T) - mid;
+        if (f >= 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+static double mm_temperature(const orc_mm *p, int i, int j, double t)
+{
+    if (p->spot_mode == ORC_SPOT_NONE) return p->T_amb;
+    double xc = p->spot_mode == ORC_SPOT_MOVING ? p->x0 + p->v * t : p->x0;
+    double sd = p->fwhm / 2.3548200450309493;
+    double inv2s2 = 1.0 / ((2.0 * sd) * sd);
+    double dx = ((double)i + 0.5) * p->h[0] - xc;
+    double dy = ((double)j + 0.5) * p->h[1] - p->y0;
+    double q = (dx * dx + dy * dy) * inv2s2;
+    return p->T_amb + (p->T_peak - p->T_amb) * orc_exp(-q);
+}
+
+/* neighbour of cell (i, j, k) along axis ax, direction d (+-1), or -1 */
+static int64_t mm_nb(const orc_mm *p, int i, int j, int k, int ax, int d)
+{
+    int c[3] = {i, j, k};
+    int n[3] = {p->nx, p->ny, p->nz};
+    c[ax] += d;
+    if (c[ax] < 0 || c[ax] >= n[ax]) {
+        if (!p->periodic[ax]) return -1;
+        c[ax] = (c[ax] + n[ax]) % n[ax];
+    }
+    return c[0] + (int64_t)n[0] * (c[1] + (int64_t)n[1] * c[2]);
+}
+
+/* k = dm/dt at configuration u (all cells) and time t */
+static void mm_rhs(const orc_mm *p, const double *u, double t, double pol, double *k)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    double bmag = sqrt((p->B[0] * p->B[0] + p->B[1] * p->B[1]) + p->B[2] * p->B[2]);
+    double b = p->mu_s * bmag / ORC_KB;
+    double ih2[3] = {1.0 / (p->h[0] * p->h[0]), 1.0 / (p->h[1] * p->h[1]),
+                     1.0 / (p->h[2] * p->h[2])};
+    for (int64_t c = 0; c < n; ++c) {
+        int i = (int)(c % p->nx), j = (int)((c / p->nx) % p->ny), kk = (int)(c / ((int64_t)p->nx * p->ny));
+        double T = mm_temperature(p, i, j, t);
+        double me = orc_mm_me(T, p->Tc, b);
+        double Tr = T < p->Tc ? T : p->Tc;
+        double alpha = p->lambda * (1.0 - Tr / (3.0 * p->Tc));
+        double gp = -p->gamma / (1.0 + alpha * alpha);
+        double m[3] = {u[c], u[n + c], u[2 * n + c]};
+        double lap[3] = {0.0, 0.0, 0.0};
+        for (int ax = 0; ax < 3; ++ax)
+            for (int d = -1; d <= 1; d += 2) {
+                int64_t q = mm_nb(p, i, j, kk, ax, d);
+                if (q < 0) continue;
+                for (int s = 0; s < 3; ++s) lap[s] = lap[s] + (u[s * n + q] - m[s]) * ih2[ax];
+            }
+        double cex = (2.0 * p->A0 * me) / p->Ms0;
+        double can = (2.0 * p->K0 * (me * me)) / p->Ms0;
+        double B[3];
+        for (int s = 0; s < 3; ++s) B[s] = cex * lap[s] + pol * p->B[s];
+        B[2] = B[2] + can * m[2];
+        double f[3];
+        ll_rhs(gp, alpha, m, B, f);
+        k[c] = f[0];
+        k[n + c] = f[1];
+        k[2 * n + c] = f[2];
+    }
+}
+
+int orc_mm_rk4(const orc_mm *p, double *m, int64_t step0, int64_t nsteps)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    double *k1 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *k2 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *k3 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *k4 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *u = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!k1 || !k2 || !k3 || !k4 || !u) {
+        free(k1); free(k2); free(k3); free(k4); free(u);
+        return -1;
+    }
+    const double dt = p->dt;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int64_t step = step0 + s;
+        double pol = 1.0;
+        if (p->n_bits > 0 && p->steps_per_bit > 0)
+            pol = p->bits[(step / p->steps_per_bit) % p->n_bits] ? 1.0 : -1.0;
+        double t = (double)step * dt;
+        mm_rhs(p, m, t, pol, k1);
+        for (int64_t q = 0; q < 3 * n; ++q) u[q] = m[q] + (0.5 * dt) * k1[q];
+        mm_rhs(p, u, t + 0.5 * dt, pol, k2);
+        for (int64_t q = 0; q < 3 * n; ++q) u[q] = m[q] + (0.5 * dt) * k2[q];
+        mm_rhs(p, u, t + 0.5 * dt, pol, k3);
+        for (int64_t q = 0; q < 3 * n; ++q) u[q] = m[q] + dt * k3[q];
+        mm_rhs(p, u, t + dt, pol, k4);
+        for (int64_t c = 0; c < n; ++c) {
+            double v[3];
+            for (int d = 0; d < 3; ++d) {
+                int64_t q = d * n + c;
+                v[d] = m[q] + (dt / 6.0) * (((k1[q] + 2.0 * k2[q]) + 2.0 * k3[q]) + k4[q]);
+            }
+            normalise(v);
+            m[c] = v[0];
+            m[n + c] = v[1];
+            m[2 * n + c] = v[2];
+        }
+    }
+    free(k1); free(k2); free(k3); free(k4); free(u);
+    return 0;
+}

@@ -108,6 +108,24 @@ void orc_demag_direct(int nx, int ny, int nz, double dx, double dy, double dz, c
  * never visited) at the system's ambient temperature; see asd_oracle.c */
 int orc_mc_sweeps(const orc_system *s, const int8_t *colour, double *Sx, double *Sy, double *Sz,
                   int64_t sweep0, int64_t nsweeps);
+/* micromagnetic region: LLG (no thermal field) by RK4 on a finite-difference
+ * mesh with temperature-dependent parameters; see asd_oracle.c */
+typedef struct orc_mm {
+    int nx, ny, nz;
+    int periodic[3];
+    double h[3];            /* cell edges (m) */
+    double Ms0, A0, K0;     /* A/m, J/m, J/m^3 at 0 K */
+    double lambda, gamma, Tc, mu_s, dt;
+    double B[3];
+    int n_bits;
+    const uint8_t *bits;
+    int64_t steps_per_bit;
+    int spot_mode;
+    double T_amb, T_peak, fwhm, x0, y0, v;
+} orc_mm;
+double orc_langevin(double x);
+double orc_mm_me(double T, double Tc, double b);
+int orc_mm_rk4(const orc_mm *p, double *m, int64_t step0, int64_t nsteps);
 void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                 int64_t step, double out[4]);
 
