@@ -328,6 +328,51 @@ int asd_variant_count(asd_t *h, int32_t kernel, int32_t *count);
  * them), NUL-terminated into buf[len]; ASD_EINVAL if it does not fit. */
 int asd_variant_name(asd_t *h, char *buf, size_t len);
 
+/* ---- micromagnetic region (Sec. II) ----
+ * LLG without the thermal field (Eq. 1 in Landau-Lifshitz form) on a
+ * finite-difference mesh of nx x ny x nz cells (x fastest, arrays
+ * [3][n] of unit vectors in the handle precision), integrated by classic
+ * RK4 (the integrator the paper names for these regions, Sec. III) and
+ * renormalised after every step.  Field per cell, in tesla:
+ *   exchange (2 A(T) / M_S(T)) lap m (Eq. 4; six-point stencil, a missing
+ *   neighbour at an open face contributes nothing), uniaxial anisotropy
+ *   (2 K(T) / M_S(T)) m_z z (Eq. 5), write field p(n) B;
+ * M_S = Ms0 m_e(T), A = A0 m_e^2, K = K0 m_e^3, alpha = lambda (1 - T / 3 T_C)
+ * with T clamped to T_C, and m_e(T) the largest root of
+ * m = L(3 T_C m / T + mu_s |B| / kB T) with L the Langevin function
+ * (Sec. II), computed in FP64.  T per cell from the drive's spot at the
+ * cell centre ((i + 1/2) h_x, (j + 1/2) h_y) and the stage time
+ * (ASD_SPOT_LOCKED: centre (x0, y0) in the mesh frame).  The handle owns no
+ * device memory (caller workspace); work runs on the given stream. */
+typedef struct asd_mm_t asd_mm_t;
+typedef struct asd_mm_params {
+    int32_t precision;        /* ASD_FP64 or ASD_FP32 */
+    int32_t nx, ny, nz;       /* cells, at most 2^28 in all */
+    int32_t bc_x, bc_y, bc_z; /* ASD_BC_OPEN or ASD_BC_PERIODIC */
+    double h[3];              /* cell edges (m) */
+    double Ms0;               /* spontaneous magnetisation at 0 K (A/m) */
+    double A0;                /* exchange stiffness at 0 K (J/m); Eq. 9: J / 2a */
+    double K0;                /* uniaxial anisotropy at 0 K (J/m^3) */
+    double lambda;            /* damping at 0 K */
+    double gamma;             /* gyromagnetic ratio (rad s^-1 T^-1) */
+    double Tc;                /* Curie temperature (K) */
+    double mu_s;              /* atomic moment in the field term of m_e (J/T) */
+    double dt;                /* time step (s) */
+    int32_t graph_steps;      /* > 0: capture segments of this many steps */
+} asd_mm_params;
+int asd_mm_workspace_bytes(const asd_mm_params *p, size_t *bytes);
+/* m starts at +z everywhere, the step counter at 0, no field, T = 0. */
+int asd_mm_create(const asd_mm_params *p, void *workspace, size_t workspace_bytes, void *stream,
+                  asd_mm_t **out);
+int asd_mm_destroy(asd_mm_t *h);
+int asd_mm_set_field_temperature(asd_mm_t *h, const asd_drive *d);
+int asd_mm_set_m(asd_mm_t *h, const void *src, int32_t on_device);
+int asd_mm_get_m(asd_mm_t *h, void *dst, int32_t on_device);
+/* n RK4 steps; the polarity of step k is that of bit (k / steps_per_bit). */
+int asd_mm_step(asd_mm_t *h, int64_t n);
+int asd_mm_get_step(asd_mm_t *h, int64_t *step);
+const char *asd_mm_last_error(const asd_mm_t *h);
+
 const char *asd_strerror(int code);
 const char *asd_last_error(const asd_t *h);
 

@@ -34,6 +34,8 @@ SYMBOLS = [
     "asd_autotune", "asd_set_variant", "asd_get_variant", "asd_variant_count", "asd_variant_name",
     "asd_strerror",
     "asd_last_error",
+    "asd_mm_workspace_bytes", "asd_mm_create", "asd_mm_destroy", "asd_mm_set_field_temperature",
+    "asd_mm_set_m", "asd_mm_get_m", "asd_mm_step", "asd_mm_get_step", "asd_mm_last_error",
 ]
 
 
@@ -50,6 +52,15 @@ class asd_params(C.Structure):
                 ("dt", C.c_double), ("k_u", C.c_double), ("seed", C.c_uint64),
                 ("philox_rounds", C.c_int32), ("kernel", C.c_int32), ("graph_steps", C.c_int32),
                 ("demag_cell", C.c_int32 * 3)]
+
+
+class asd_mm_params(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("bc_z", C.c_int32),
+                ("h", C.c_double * 3), ("Ms0", C.c_double), ("A0", C.c_double),
+                ("K0", C.c_double), ("lambda_", C.c_double), ("gamma", C.c_double),
+                ("Tc", C.c_double), ("mu_s", C.c_double), ("dt", C.c_double),
+                ("graph_steps", C.c_int32)]
 
 
 class asd_system_desc(C.Structure):
@@ -114,6 +125,16 @@ def lib():
         L.asd_demag_field.argtypes = [h, vp, vp]
         L.asd_mc_sweep.argtypes = [h, C.c_int64]
         L.asd_variant_count.argtypes = [h, C.c_int32, P(C.c_int32)]
+        L.asd_mm_workspace_bytes.argtypes = [P(asd_mm_params), P(C.c_size_t)]
+        L.asd_mm_create.argtypes = [P(asd_mm_params), vp, C.c_size_t, vp, P(vp)]
+        L.asd_mm_destroy.argtypes = [vp]
+        L.asd_mm_set_field_temperature.argtypes = [vp, P(asd_drive)]
+        L.asd_mm_set_m.argtypes = [vp, vp, C.c_int32]
+        L.asd_mm_get_m.argtypes = [vp, vp, C.c_int32]
+        L.asd_mm_step.argtypes = [vp, C.c_int64]
+        L.asd_mm_get_step.argtypes = [vp, P(C.c_int64)]
+        L.asd_mm_last_error.argtypes = [vp]
+        L.asd_mm_last_error.restype = C.c_char_p
         L.asd_variant_name.argtypes = [h, C.c_char_p, C.c_size_t]
         L.asd_strerror.argtypes = [C.c_int]
         L.asd_strerror.restype = C.c_char_p
@@ -416,3 +437,66 @@ class Handle:
 
     def autotune(self, cache_path=None):
         asd_autotune(self.h, cache_path)
+
+
+# ----------------------------------------------------------------- micromagnetic region
+def _mm_check(rc, handle=None):
+    if rc != ASD_OK:
+        msg = lib().asd_mm_last_error(handle).decode(errors="replace")
+        raise AsdError(rc, f"{lib().asd_strerror(rc).decode()}: {msg}")
+    return rc
+
+
+class MMHandle:
+    """A micromagnetic region (asd_mm_*) with a torch-owned workspace and its own stream."""
+
+    def __init__(self, params: asd_mm_params, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = params
+        nb = C.c_size_t()
+        _mm_check(lib().asd_mm_workspace_bytes(C.byref(params), C.byref(nb)))
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        out = C.c_void_p()
+        _mm_check(lib().asd_mm_create(C.byref(params), ptr, nb.value, self.stream.cuda_stream,
+                                      C.byref(out)))
+        self.h = out.value
+        self.n = params.nx * params.ny * params.nz
+        self.dtype = np.float64 if params.precision == ASD_FP64 else np.float32
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().asd_mm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_drive(self, drive: asd_drive):
+        _mm_check(lib().asd_mm_set_field_temperature(self.h, C.byref(drive)), self.h)
+
+    def set_m(self, m):
+        a = np.ascontiguousarray(m, dtype=self.dtype).reshape(3, -1)
+        if a.shape[1] != self.n:
+            raise ValueError("magnetisation array does not match the mesh")
+        _mm_check(lib().asd_mm_set_m(self.h, a.ctypes.data, 0), self.h)
+
+    def get_m(self) -> np.ndarray:
+        out = np.empty((3, self.n), dtype=self.dtype)
+        _mm_check(lib().asd_mm_get_m(self.h, out.ctypes.data, 0), self.h)
+        return out
+
+    def step(self, n: int):
+        _mm_check(lib().asd_mm_step(self.h, n), self.h)
+
+    def step_count(self) -> int:
+        v = C.c_int64()
+        _mm_check(lib().asd_mm_get_step(self.h, C.byref(v)), self.h)
+        return v.value

@@ -29,6 +29,7 @@ SOURCES = [
     ("asd_step_f32.hip", ["-ffp-contract=fast"]),
     ("asd_misc.hip", ["-ffp-contract=off"]),
     ("asd_demag.hip", ["-ffp-contract=fast"]),
+    ("asd_mm.hip", ["-ffp-contract=off"]),
     ("asd_host.cpp", ["-ffp-contract=off"]),
     ("asd_demag_tensor.cpp", ["-ffp-contract=off"]),
 ]

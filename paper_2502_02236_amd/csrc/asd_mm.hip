@@ -1,0 +1,523 @@
+// asd_mm.hip -- micromagnetic region (Sec. II): LLG without the thermal field
+// (Eq. 1 in Landau-Lifshitz form) on a finite-difference mesh, classic RK4
+// (the integrator the paper names for these regions, Sec. III), the
+// magnetisation renormalised after each step.
+//
+// Field per cell (tesla), from the configuration u of the stage:
+//   exchange   (2 A(T) / M_S(T)) lap u                 (Eq. 4, 6-point stencil,
+//              neighbours in the order -x, +x, -y, +y, -z, +z; a missing
+//              neighbour at an open face contributes nothing)
+//   anisotropy (2 K(T) / M_S(T)) u_z z                 (Eq. 5)
+//   write field p(n) B
+// with M_S = M_S0 m_e, A = A_0 m_e^2, K = K_0 m_e^3, damping
+// alpha = lambda (1 - min(T, T_C) / 3 T_C), and m_e(T) the largest root of
+// m = L(3 T_C m / T + mu_s |B| / kB T) (Sec. II), found by 64 halvings of
+// [0, 1] in FP64 for both precisions.  T per cell from the laser spot at
+// the stage time t_n, t_n + dt/2, t_n + dt/2, t_n + dt.
+//
+// One launch per RK4 stage; stage inputs ping-pong between two buffers so
+// that no launch overwrites what its neighbours read; the last stage writes
+// the new magnetisation in place (each cell reads only its own old value).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "asd.h"
+#include "asd_device.h"
+
+namespace asd {
+namespace {
+
+constexpr int kMMTile = 256;
+constexpr int kMMMaxBits = 1 << 16;
+constexpr size_t kMMAlign = 256;
+
+struct MMArgs {
+    int32_t nx, ny, nz, n;
+    int32_t per[3];
+    double ih2[3];            // 1 / h^2 per axis
+    double h[3];
+    double Ms0, A0, K0, lambda, gamma, Tc, dt, b;  // b = mu_s |B| / kB (K)
+    double B[3];
+    int32_t n_bits, spot_mode;
+    int64_t spb;
+    double T_amb, T_peak, inv2s2, x0, y0, v;
+    const uint8_t *bits;
+    const int64_t *step;      // device step counter
+    int32_t step_off;
+    void *m, *ua, *ub, *acc;  // [3][n] in the handle precision
+    double *me, *alpha;       // per cell, filled by the parameter pass
+};
+
+// Langevin function coth x - 1/x for x >= 0: series through x^11 below 0.1,
+// coth from the portable exp above
+__device__ __forceinline__ double langevin(double x)
+{
+    if (x < 0.1) {
+        const double x2 = x * x;
+        double p = -1382.0 / 638512875.0;
+        p = 2.0 / 93555.0 + x2 * p;
+        p = -1.0 / 4725.0 + x2 * p;
+        p = 2.0 / 945.0 + x2 * p;
+        p = -1.0 / 45.0 + x2 * p;
+        p = 1.0 / 3.0 + x2 * p;
+        return x * p;
+    }
+    const double e = f64::expn(-2.0 * x);
+    return (1.0 + e) / (1.0 - e) - 1.0 / x;
+}
+
+__device__ __forceinline__ double equilibrium_m(double T, double Tc, double b)
+{
+    if (T <= 0.0) return 1.0;
+    double lo = 0.0, hi = 1.0;
+    for (int k = 0; k < 64; ++k) {
+        const double mid = 0.5 * (lo + hi);
+        const double f = langevin((3.0 * Tc * mid + b) / T) - mid;
+        if (f >= 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// m_e and alpha of every cell at time t = (step + frac) dt
+__global__ __launch_bounds__(kMMTile) void k_mm_params(MMArgs a, double frac)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    const int i = c % a.nx, j = (c / a.nx) % a.ny;
+    double T = a.T_amb;
+    if (a.spot_mode != ASD_SPOT_NONE) {
+        const double t0 = (double)(*a.step + a.step_off) * a.dt;
+        const double t = frac == 0.0 ? t0 : (frac == 1.0 ? t0 + a.dt : t0 + 0.5 * a.dt);
+        const double xc = a.spot_mode == ASD_SPOT_MOVING ? a.x0 + a.v * t : a.x0;
+        const double dx = ((double)i + 0.5) * a.h[0] - xc;
+        const double dy = ((double)j + 0.5) * a.h[1] - a.y0;
+        const double q = (dx * dx + dy * dy) * a.inv2s2;
+        T = a.T_amb + (a.T_peak - a.T_amb) * f64::expn(-q);
+    }
+    a.me[c] = equilibrium_m(T, a.Tc, a.b);
+    const double Tr = T < a.Tc ? T : a.Tc;
+    a.alpha[c] = a.lambda * (1.0 - Tr / (3.0 * a.Tc));
+}
+
+template <typename T>
+struct M3 {
+    T x, y, z;
+};
+
+template <typename T>
+__device__ __forceinline__ int64_t mm_nb(const MMArgs &a, int i, int j, int k, int ax, int d)
+{
+    int c[3] = {i, j, k};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    c[ax] += d;
+    if (c[ax] < 0 || c[ax] >= n[ax]) {
+        if (!a.per[ax]) return -1;
+        c[ax] = (c[ax] + n[ax]) % n[ax];
+    }
+    return c[0] + (int64_t)n[0] * (c[1] + (int64_t)n[1] * c[2]);
+}
+
+// stage s: k_s from the stage input (m for s = 0, else the buffer the
+// previous stage wrote); s < 3 writes the next input, s = 3 the new m
+template <typename T>
+__global__ __launch_bounds__(kMMTile) void k_mm_stage(MMArgs a, int s)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    const int64_t n = a.n;
+    const int i = c % a.nx, j = (c / a.nx) % a.ny, k = c / (a.nx * a.ny);
+    T *m = (T *)a.m, *acc = (T *)a.acc;
+    const T *u = s == 0 ? m : (s == 2 ? (const T *)a.ub : (const T *)a.ua);
+    T *nxt = s == 1 ? (T *)a.ub : (T *)a.ua;  // written by s = 0, 1, 2
+    const M3<T> mc{u[c], u[n + c], u[2 * n + c]};
+    T lap[3] = {T(0), T(0), T(0)};
+    for (int ax = 0; ax < 3; ++ax)
+        for (int d = -1; d <= 1; d += 2) {
+            const int64_t q = mm_nb<T>(a, i, j, k, ax, d);
+            if (q < 0) continue;
+            const T w = (T)a.ih2[ax];
+            lap[0] = lap[0] + (u[q] - mc.x) * w;
+            lap[1] = lap[1] + (u[n + q] - mc.y) * w;
+            lap[2] = lap[2] + (u[2 * n + q] - mc.z) * w;
+        }
+    const int64_t step = *a.step + a.step_off;
+    T pol = T(1);
+    if (a.n_bits > 0 && a.spb > 0) pol = a.bits[(step / a.spb) % a.n_bits] ? T(1) : T(-1);
+    const double me = a.me[c];
+    const T cex = (T)((2.0 * a.A0 * me) / a.Ms0);
+    const T can = (T)((2.0 * a.K0 * (me * me)) / a.Ms0);
+    T B[3];
+    B[0] = cex * lap[0] + pol * (T)a.B[0];
+    B[1] = cex * lap[1] + pol * (T)a.B[1];
+    B[2] = cex * lap[2] + pol * (T)a.B[2];
+    B[2] = B[2] + can * mc.z;
+    const double al = a.alpha[c];
+    const T alpha = (T)al;
+    const T gp = (T)(-a.gamma / (1.0 + al * al));
+    // Landau-Lifshitz right-hand side gp (m x B + alpha m x (m x B))
+    const T cx = mc.y * B[2] - mc.z * B[1];
+    const T cy = mc.z * B[0] - mc.x * B[2];
+    const T cz = mc.x * B[1] - mc.y * B[0];
+    const T ddx = mc.y * cz - mc.z * cy;
+    const T ddy = mc.z * cx - mc.x * cz;
+    const T ddz = mc.x * cy - mc.y * cx;
+    const T f[3] = {gp * (cx + alpha * ddx), gp * (cy + alpha * ddy), gp * (cz + alpha * ddz)};
+    const T dt = (T)a.dt;
+    const T m0[3] = {m[c], m[n + c], m[2 * n + c]};
+    if (s == 0) {
+        for (int d = 0; d < 3; ++d) {
+            acc[d * n + c] = f[d];
+            nxt[d * n + c] = m0[d] + (T(0.5) * dt) * f[d];
+        }
+    } else if (s < 3) {
+        for (int d = 0; d < 3; ++d) {
+            acc[d * n + c] = acc[d * n + c] + T(2) * f[d];
+            nxt[d * n + c] = m0[d] + (s == 1 ? T(0.5) * dt : dt) * f[d];
+        }
+    } else {
+        T v[3];
+        for (int d = 0; d < 3; ++d) v[d] = m0[d] + (dt / T(6)) * (acc[d * n + c] + f[d]);
+        const T r = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        m[c] = v[0] / r;
+        m[n + c] = v[1] / r;
+        m[2 * n + c] = v[2] / r;
+    }
+}
+
+__global__ void k_mm_advance(int64_t *step, int64_t n)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *step += n;
+}
+
+size_t align_up(size_t v) { return (v + kMMAlign - 1) / kMMAlign * kMMAlign; }
+
+}  // namespace
+}  // namespace asd
+
+using namespace asd;
+
+struct asd_mm_t {
+    asd_mm_params p{};
+    asd_drive drive{};
+    std::vector<uint8_t> bits;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    int elem = 8;
+    int64_t n = 0, step = 0;
+    size_t off_m = 0, off_ua = 0, off_ub = 0, off_acc = 0, off_me = 0, off_al = 0,
+           off_step = 0, off_bits = 0, bytes = 0;
+    bool params_valid = false;  // m_e, alpha current for a spot that does not move
+    hipGraphExec_t graph = nullptr;
+    std::string err;
+};
+
+static thread_local std::string g_mm_err;
+
+static int mm_fail(asd_mm_t *h, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    (h ? h->err : g_mm_err) = buf;
+    return code;
+}
+
+#define MM_HIP(h, call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return mm_fail((h), ASD_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static int mm_check(const asd_mm_params *p)
+{
+    if (!p) return mm_fail(nullptr, ASD_EINVAL, "params is NULL");
+    if (p->precision != ASD_FP64 && p->precision != ASD_FP32)
+        return mm_fail(nullptr, ASD_EINVAL, "precision must be ASD_FP64 or ASD_FP32");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || (int64_t)p->nx * p->ny * p->nz > (1 << 28))
+        return mm_fail(nullptr, ASD_EINVAL, "mesh must have 1 .. 2^28 cells");
+    const int32_t bc[3] = {p->bc_x, p->bc_y, p->bc_z};
+    for (int k = 0; k < 3; ++k)
+        if (bc[k] != ASD_BC_OPEN && bc[k] != ASD_BC_PERIODIC)
+            return mm_fail(nullptr, ASD_EINVAL, "micromagnetic faces are open or periodic");
+    for (int k = 0; k < 3; ++k)
+        if (!(p->h[k] > 0)) return mm_fail(nullptr, ASD_EINVAL, "cell edges must be positive");
+    if (!(p->Ms0 > 0) || !(p->A0 >= 0) || !std::isfinite(p->K0) || !(p->lambda >= 0) ||
+        !(p->gamma > 0) || !(p->Tc > 0) || !(p->mu_s >= 0) || !(p->dt > 0))
+        return mm_fail(nullptr, ASD_EINVAL, "material constants out of range");
+    if (p->graph_steps < 0) return mm_fail(nullptr, ASD_EINVAL, "graph_steps must be >= 0");
+    return ASD_OK;
+}
+
+static void mm_layout(const asd_mm_params *p, asd_mm_t *h)
+{
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    const size_t e = p->precision == ASD_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off = align_up(off + b);
+        return o;
+    };
+    h->off_m = take(3 * n * e);
+    h->off_ua = take(3 * n * e);
+    h->off_ub = take(3 * n * e);
+    h->off_acc = take(3 * n * e);
+    h->off_me = take(n * sizeof(double));
+    h->off_al = take(n * sizeof(double));
+    h->off_step = take(sizeof(int64_t));
+    h->off_bits = take(kMMMaxBits);
+    h->bytes = off;
+}
+
+static MMArgs mm_args(const asd_mm_t *h, int step_off)
+{
+    const asd_mm_params &p = h->p;
+    const asd_drive &d = h->drive;
+    MMArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.n = (int32_t)h->n;
+    a.per[0] = p.bc_x == ASD_BC_PERIODIC;
+    a.per[1] = p.bc_y == ASD_BC_PERIODIC;
+    a.per[2] = p.bc_z == ASD_BC_PERIODIC;
+    for (int k = 0; k < 3; ++k) {
+        a.h[k] = p.h[k];
+        a.ih2[k] = 1.0 / (p.h[k] * p.h[k]);
+        a.B[k] = d.B[k];
+    }
+    a.Ms0 = p.Ms0;
+    a.A0 = p.A0;
+    a.K0 = p.K0;
+    a.lambda = p.lambda;
+    a.gamma = p.gamma;
+    a.Tc = p.Tc;
+    a.dt = p.dt;
+    const double bmag = std::sqrt((d.B[0] * d.B[0] + d.B[1] * d.B[1]) + d.B[2] * d.B[2]);
+    a.b = p.mu_s * bmag / 1.380649e-23;
+    a.n_bits = d.n_bits;
+    a.spb = d.steps_per_bit;
+    a.spot_mode = d.spot_mode;
+    a.T_amb = d.T_amb;
+    a.T_peak = d.T_peak;
+    if (d.spot_mode != ASD_SPOT_NONE) {
+        const double sd = d.fwhm / 2.3548200450309493;
+        a.inv2s2 = 1.0 / ((2.0 * sd) * sd);
+    }
+    a.x0 = d.x0;
+    a.y0 = d.y0;
+    a.v = d.v;
+    char *w = h->ws;
+    a.bits = (const uint8_t *)(w + h->off_bits);
+    a.step = (const int64_t *)(w + h->off_step);
+    a.step_off = step_off;
+    a.m = w + h->off_m;
+    a.ua = w + h->off_ua;
+    a.ub = w + h->off_ub;
+    a.acc = w + h->off_acc;
+    a.me = (double *)(w + h->off_me);
+    a.alpha = (double *)(w + h->off_al);
+    return a;
+}
+
+// launches of one step (step_off after the device counter); the parameter
+// pass runs per stage for a moving spot, else once when the drive changed
+static int mm_launch_step(asd_mm_t *h, int step_off, bool params_now)
+{
+    const MMArgs a = mm_args(h, step_off);
+    const dim3 grid((unsigned)((h->n + kMMTile - 1) / kMMTile)), blk(kMMTile);
+    const bool moving = h->drive.spot_mode == ASD_SPOT_MOVING;
+    const double frac[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int s = 0; s < 4; ++s) {
+        if (moving ? (s != 2) : (s == 0 && params_now))
+            hipLaunchKernelGGL(k_mm_params, grid, blk, 0, h->stream, a, frac[s]);
+        if (h->elem == 8)
+            hipLaunchKernelGGL(k_mm_stage<double>, grid, blk, 0, h->stream, a, s);
+        else
+            hipLaunchKernelGGL(k_mm_stage<float>, grid, blk, 0, h->stream, a, s);
+    }
+    return hipGetLastError() == hipSuccess ? ASD_OK
+                                            : mm_fail(h, ASD_EHIP, "micromagnetic launch failed: %s",
+                                                      hipGetErrorString(hipGetLastError()));
+}
+
+static void mm_drop_graph(asd_mm_t *h)
+{
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+}
+
+extern "C" {
+
+int asd_mm_workspace_bytes(const asd_mm_params *p, size_t *bytes)
+{
+    int rc = mm_check(p);
+    if (rc) return rc;
+    if (!bytes) return mm_fail(nullptr, ASD_EINVAL, "bytes is NULL");
+    asd_mm_t tmp;
+    mm_layout(p, &tmp);
+    *bytes = tmp.bytes;
+    return ASD_OK;
+}
+
+int asd_mm_create(const asd_mm_params *p, void *workspace, size_t workspace_bytes, void *stream,
+                  asd_mm_t **out)
+{
+    if (!out) return mm_fail(nullptr, ASD_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = mm_check(p);
+    if (rc) return rc;
+    asd_mm_t *h = new (std::nothrow) asd_mm_t();
+    if (!h) return mm_fail(nullptr, ASD_ENOMEM, "host allocation failed");
+    h->p = *p;
+    mm_layout(p, h);
+    if (!workspace || ((uintptr_t)workspace % kMMAlign) != 0 || workspace_bytes < h->bytes) {
+        delete h;
+        return mm_fail(nullptr, workspace_bytes < h->bytes ? ASD_ENOMEM : ASD_EINVAL,
+                       "workspace must be 256-byte aligned and hold asd_mm_workspace_bytes");
+    }
+    h->ws = (char *)workspace;
+    h->stream = (hipStream_t)stream;
+    h->elem = p->precision == ASD_FP64 ? 8 : 4;
+    h->n = (int64_t)p->nx * p->ny * p->nz;
+    // zero everything, then m = +z
+    hipError_t e = hipMemsetAsync(h->ws, 0, h->bytes, h->stream);
+    std::vector<char> m0((size_t)3 * h->n * h->elem, 0);
+    for (int64_t c = 0; c < h->n; ++c) {
+        if (h->elem == 8) ((double *)m0.data())[2 * h->n + c] = 1.0;
+        else ((float *)m0.data())[2 * h->n + c] = 1.0f;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->ws + h->off_m, m0.data(), m0.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return mm_fail(nullptr, ASD_EHIP, "set-up copy failed: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return ASD_OK;
+}
+
+int asd_mm_destroy(asd_mm_t *h)
+{
+    if (!h) return ASD_OK;
+    mm_drop_graph(h);
+    delete h;
+    return ASD_OK;
+}
+
+int asd_mm_set_field_temperature(asd_mm_t *h, const asd_drive *d)
+{
+    if (!h || !d) return mm_fail(h, ASD_EINVAL, "NULL argument");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(d->B[k])) return mm_fail(h, ASD_EINVAL, "B must be finite");
+    if (d->n_bits < 0 || d->n_bits > kMMMaxBits ||
+        (d->n_bits > 0 && (!d->bits || d->steps_per_bit <= 0)))
+        return mm_fail(h, ASD_EINVAL, "bits: 0..65536 entries with steps_per_bit > 0");
+    if (d->spot_mode < ASD_SPOT_NONE || d->spot_mode > ASD_SPOT_LOCKED)
+        return mm_fail(h, ASD_EINVAL, "unknown spot mode");
+    if (!(d->T_amb >= 0) || (d->spot_mode != ASD_SPOT_NONE && !(d->T_peak >= 0 && d->fwhm > 0)))
+        return mm_fail(h, ASD_EINVAL, "temperatures must be >= 0 and fwhm > 0 with a spot");
+    h->drive = *d;
+    h->drive.bits = nullptr;
+    h->bits.assign(d->bits, d->bits + d->n_bits);
+    if (d->n_bits > 0)
+        MM_HIP(h, hipMemcpyAsync(h->ws + h->off_bits, h->bits.data(), h->bits.size(),
+                                 hipMemcpyHostToDevice, h->stream));
+    MM_HIP(h, hipStreamSynchronize(h->stream));
+    h->params_valid = false;
+    mm_drop_graph(h);
+    return ASD_OK;
+}
+
+int asd_mm_set_m(asd_mm_t *h, const void *src, int32_t on_device)
+{
+    if (!h || !src) return mm_fail(h, ASD_EINVAL, "NULL argument");
+    MM_HIP(h, hipMemcpyAsync(h->ws + h->off_m, src, (size_t)3 * h->n * h->elem,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             h->stream));
+    MM_HIP(h, hipStreamSynchronize(h->stream));
+    return ASD_OK;
+}
+
+int asd_mm_get_m(asd_mm_t *h, void *dst, int32_t on_device)
+{
+    if (!h || !dst) return mm_fail(h, ASD_EINVAL, "NULL argument");
+    MM_HIP(h, hipMemcpyAsync(dst, h->ws + h->off_m, (size_t)3 * h->n * h->elem,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             h->stream));
+    MM_HIP(h, hipStreamSynchronize(h->stream));
+    return ASD_OK;
+}
+
+int asd_mm_step(asd_mm_t *h, int64_t n)
+{
+    if (!h) return mm_fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (n < 0) return mm_fail(h, ASD_EINVAL, "n must be >= 0");
+    if (n == 0) return ASD_OK;
+    int64_t *step = (int64_t *)(h->ws + h->off_step);
+    int64_t done = 0;
+    const int G = h->p.graph_steps;
+    if (G > 0 && n >= G) {
+        if (!h->params_valid) {  // graphs never hold the parameter pass of a static spot
+            const MMArgs a = mm_args(h, 0);
+            hipLaunchKernelGGL(k_mm_params, dim3((unsigned)((h->n + kMMTile - 1) / kMMTile)),
+                               dim3(kMMTile), 0, h->stream, a, 0.0);
+            h->params_valid = true;
+        }
+        if (!h->graph) {
+            hipGraph_t g = nullptr;
+            MM_HIP(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            int rc = ASD_OK;
+            for (int t = 0; t < G && rc == ASD_OK; ++t) rc = mm_launch_step(h, t, false);
+            if (rc == ASD_OK) hipLaunchKernelGGL(k_mm_advance, dim3(1), dim3(1), 0, h->stream, step, (int64_t)G);
+            hipError_t e = hipStreamEndCapture(h->stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return mm_fail(h, ASD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return mm_fail(h, ASD_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
+        while (n - done >= G) {
+            MM_HIP(h, hipGraphLaunch(h->graph, h->stream));
+            done += G;
+        }
+    }
+    for (int64_t t = 0; t < n - done; ++t) {
+        int rc = mm_launch_step(h, (int)t, !h->params_valid);
+        if (rc) return rc;
+        if (h->drive.spot_mode != ASD_SPOT_MOVING) h->params_valid = true;
+    }
+    if (n - done > 0)
+        hipLaunchKernelGGL(k_mm_advance, dim3(1), dim3(1), 0, h->stream, step, n - done);
+    MM_HIP(h, hipGetLastError());
+    h->step += n;
+    return ASD_OK;
+}
+
+int asd_mm_get_step(asd_mm_t *h, int64_t *step)
+{
+    if (!h || !step) return mm_fail(h, ASD_EINVAL, "NULL argument");
+    *step = h->step;
+    return ASD_OK;
+}
+
+const char *asd_mm_last_error(const asd_mm_t *h) { return h ? h->err.c_str() : g_mm_err.c_str(); }
+
+}  // extern "C"
