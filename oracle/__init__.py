@@ -79,7 +79,7 @@ class OrcMM(C.Structure):
         ("dt", C.c_double), ("B", C.c_double * 3), ("n_bits", C.c_int), ("bits", u8p),
         ("steps_per_bit", C.c_int64), ("spot_mode", C.c_int), ("T_amb", C.c_double),
         ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
-        ("v", C.c_double),
+        ("v", C.c_double), ("ghost", f64p * 2),
     ]
 
 
@@ -420,6 +420,19 @@ class MM:
         p.T_amb, p.T_peak, p.fwhm, p.x0, p.y0, p.v = T_amb, T_peak, fwhm, x0, y0, v
         self._p = p
         self.n = n[0] * n[1] * n[2]
+        self.ghosts = [None, None]
+
+    def set_ghost(self, face: int, dirs):
+        """Direction [ny*nz, 3] of the region across x face `face` (0: -x, 1: +x)
+        seen by the boundary cells' exchange stencil; None removes it."""
+        self.ghosts[face] = None if dirs is None else np.ascontiguousarray(dirs, np.float64)
+        self._p.ghost[face] = _ptr(self.ghosts[face], f64p)
+
+    def face(self, face: int, m) -> np.ndarray:
+        """Directions [ny*nz, 3] of the boundary cells on x face `face`."""
+        nx, ny, nz = self._p.nx, self._p.ny, self._p.nz
+        M = np.asarray(m).reshape(3, nz, ny, nx)
+        return np.ascontiguousarray(M[:, :, :, 0 if face == 0 else nx - 1].reshape(3, -1).T)
 
     def rk4(self, m, step0: int, nsteps: int) -> np.ndarray:
         m = np.array(m, dtype=np.float64, copy=True).reshape(3, -1)

@@ -1077,7 +1077,14 @@ static void mm_rhs(const orc_mm *p, const double *u, double t, double pol, doubl
         for (int ax = 0; ax < 3; ++ax)
             for (int d = -1; d <= 1; d += 2) {
                 int64_t q = mm_nb(p, i, j, kk, ax, d);
-                if (q < 0) continue;
+                if (q < 0) {
+                    /* the other region across an x face: its direction */
+                    const double *g = ax == 0 ? p->ghost[d < 0 ? 0 : 1] : NULL;
+                    if (!g) continue;
+                    const double *gv = g + 3 * ((int64_t)j + (int64_t)p->ny * kk);
+                    for (int s = 0; s < 3; ++s) lap[s] = lap[s] + (gv[s] - m[s]) * ih2[ax];
+                    continue;
+                }
                 for (int s = 0; s < 3; ++s) lap[s] = lap[s] + (u[s * n + q] - m[s]) * ih2[ax];
             }
         double cex = (2.0 * p->A0 * me) / p->Ms0;

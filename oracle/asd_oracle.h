@@ -122,6 +122,10 @@ typedef struct orc_mm {
     int64_t steps_per_bit;
     int spot_mode;
     double T_amb, T_peak, fwhm, x0, y0, v;
+    /* exchange coupling across the x faces (Sec. II): direction [ny*nz][3]
+     * taken as the -x (ghost[0]) or +x (ghost[1]) neighbour of the boundary
+     * cells of an open face; NULL: no neighbour */
+    const double *ghost[2];
 } orc_mm;
 double orc_langevin(double x);
 double orc_mm_me(double T, double Tc, double b);

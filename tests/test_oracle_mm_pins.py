@@ -166,3 +166,43 @@ def test_unit_length_and_energy_descent_with_exchange():
         e = energy(m)
         assert e < prev
         prev = e
+
+
+def test_x_face_coupling_converges_to_the_unsplit_mesh():
+    """A periodic mesh cut in two along x, each half seeing the other's boundary
+    cells (taken at the start of every step) through its x faces: as dt halves the
+    coupled halves approach the uncut mesh linearly (the lag is first order), and
+    with the faces removed they do not."""
+    n, h = (8, 3, 2), (1e-9, 1e-9, 2e-9)
+    rng = np.random.default_rng(3)
+    m0 = rng.normal(size=(3, 16 * 3 * 2)) * 0.3
+    m0[2] += 1
+    m0 /= np.linalg.norm(m0, axis=0)
+    M0 = m0.reshape(3, 2, 3, 16)
+    t_end = 200e-15
+    errs = []
+    for dt in (4e-15, 2e-15, 1e-15):
+        steps = int(round(t_end / dt))
+        full = mm(n=(16, 3, 2), h=h, dt=dt, B=(0.0, 0.0, 0.5), periodic=(1, 0, 0))
+        ref = full.rk4(m0, 0, steps).reshape(3, 2, 3, 16)
+        L = mm(n=n, h=h, dt=dt, B=(0.0, 0.0, 0.5))
+        R = mm(n=n, h=h, dt=dt, B=(0.0, 0.0, 0.5))
+        a = np.ascontiguousarray(M0[:, :, :, :8]).reshape(3, -1)
+        b = np.ascontiguousarray(M0[:, :, :, 8:]).reshape(3, -1)
+        for k in range(steps):
+            fa0, fa1, fb0, fb1 = L.face(0, a), L.face(1, a), R.face(0, b), R.face(1, b)
+            L.set_ghost(0, fb1)  # periodic: left's -x neighbour is right's last column
+            L.set_ghost(1, fb0)
+            R.set_ghost(0, fa1)
+            R.set_ghost(1, fa0)
+            a, b = L.rk4(a, k, 1), R.rk4(b, k, 1)
+        got = np.concatenate([a.reshape(3, 2, 3, 8), b.reshape(3, 2, 3, 8)], axis=3)
+        errs.append(np.max(np.abs(got - ref)))
+    assert errs[-1] < 5e-3
+    for e0, e1 in zip(errs, errs[1:]):
+        assert abs(math.log2(e0 / e1) - 1) < 0.25, errs
+    # without the faces the halves drift apart from the uncut mesh
+    L = mm(n=n, h=h, dt=1e-15, B=(0.0, 0.0, 0.5))
+    a = L.rk4(np.ascontiguousarray(M0[:, :, :, :8]).reshape(3, -1), 0, 200)
+    drift = np.max(np.abs(a.reshape(3, 2, 3, 8) - ref[:, :, :, :8]))
+    assert drift > 10 * errs[-1]
