@@ -285,6 +285,15 @@ int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int
  * demagnetising field. */
 int asd_mc_sweep(asd_t *h, int64_t n);
 
+/* Every magnetic site of stored columns [x0, x0 + ncols) of system sys takes
+ * the direction mcell[c] / |mcell[c]| of its coarse cell c (cells and mcell
+ * as in asd_thermalise_columns; a zero cell gives +z), in both buffers: the
+ * micromagnetic neighbours of the atomistic window (Sec. II). */
+int asd_set_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int32_t cx, int32_t cy,
+                    int32_t cz, const double *mcell);
+int asd_window_size(asd_t *h, int32_t sys, int32_t *nx, int32_t *ny, int32_t *nz);
+int asd_get_stream(asd_t *h, void **stream);
+
 /* Demagnetising field (Eq. 7) of the current spins of every system, as
  * the flux density mu0 H_d (T) per coarse cell of the window (including the
  * frozen track's stray field for a track system): per_cell is a host array
@@ -371,6 +380,28 @@ int asd_mm_get_m(asd_mm_t *h, void *dst, int32_t on_device);
 /* n RK4 steps; the polarity of step k is that of bit (k / steps_per_bit). */
 int asd_mm_step(asd_mm_t *h, int64_t n);
 int asd_mm_get_step(asd_mm_t *h, int64_t *step);
+/* Exchange coupling across an x face (Sec. II): vec (device, or NULL to
+ * remove) holds per boundary cell c = j + ny k a vector at vec[c * stride];
+ * its direction becomes the -x (face 0) or +x (face 1) stencil neighbour of
+ * the cells on that face (a zero vector: no neighbour).  stride 4 takes the
+ * sums of asd_coarse_grain directly. */
+int asd_mm_set_face(asd_mm_t *h, int32_t face, const double *vec, int32_t stride);
+/* Directions of the cells on x face `face` into dirs (device, [ny*nz][3]). */
+int asd_mm_get_face(asd_mm_t *h, int32_t face, double *dirs);
+/* n steps of a multiscale window (Sec. II, Fig. 1): micromagnetic regions
+ * left (may be NULL) and right (may be NULL) of the atomistic window of
+ * track system `sys`, exchange-coupled through their x faces.  Cells of the
+ * micromagnetic meshes are cx x cy x cz lattice cells (their ny, nz equal
+ * the window's coarse cells).  Each step: the first and last coarse column
+ * of the window, averaged (Eq. 6), become the +x / -x face neighbours of
+ * the left / right region (the average atomistic spin direction of the
+ * stencil cell); the regions' boundary cell directions are written into the
+ * cx frozen columns just outside the window (the atomistic exchange
+ * neighbours there); then one Heun step of the atoms and one RK4 step of each
+ * region, all on the atomistic handle's stream (both handles must have been
+ * created on it).  Needs cx <= origin and origin + nx + cx <= track_nx. */
+int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                        int32_t cy, int32_t cz, int64_t n);
 const char *asd_mm_last_error(const asd_mm_t *h);
 
 const char *asd_strerror(int code);

@@ -114,6 +114,8 @@ def _declare(L):
     L.orc_mm_me.restype = C.c_double
     L.orc_mm_rk4.argtypes = [P(OrcMM), f64p, C.c_int64, C.c_int64]
     L.orc_mm_rk4.restype = C.c_int
+    L.orc_set_columns.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p, f64p, f64p,
+                                  C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
     L.orc_cone_theta_max.argtypes = [C.c_double]
     L.orc_cone_theta_max.restype = C.c_double
     L.orc_cone_spin.argtypes = [f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -441,3 +443,14 @@ class MM:
         if lib().orc_mm_rk4(C.byref(self._p), _ptr(flat, f64p), step0, nsteps) != 0:
             raise MemoryError("oracle allocation failed")
         return flat.reshape(3, -1)
+
+
+def set_columns(kind, sx, ny, nz, label, S, x0, ncols, cx, cy, cz, mcell) -> np.ndarray:
+    """Magnetic sites of columns [x0, x0 + ncols) take their coarse cell's direction."""
+    S = np.array(S, dtype=np.float64, copy=True).reshape(3, -1)
+    Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+    lab = np.ascontiguousarray(label, dtype=np.int32)
+    mc = np.ascontiguousarray(mcell, dtype=np.float64)
+    lib().orc_set_columns(kind, sx, ny, nz, _ptr(lab, i32p), _ptr(Sx, f64p), _ptr(Sy, f64p),
+                          _ptr(Sz, f64p), x0, ncols, cx, cy, cz, _ptr(mc, f64p))
+    return np.stack([Sx, Sy, Sz])

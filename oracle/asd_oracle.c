@@ -1082,6 +1082,7 @@ static void mm_rhs(const orc_mm *p, const double *u, double t, double pol, doubl
                     const double *g = ax == 0 ? p->ghost[d < 0 ? 0 : 1] : NULL;
                     if (!g) continue;
                     const double *gv = g + 3 * ((int64_t)j + (int64_t)p->ny * kk);
+                    if (gv[0] == 0.0 && gv[1] == 0.0 && gv[2] == 0.0) continue; /* nothing there */
                     for (int s = 0; s < 3; ++s) lap[s] = lap[s] + (gv[s] - m[s]) * ih2[ax];
                     continue;
                 }
@@ -1140,4 +1141,31 @@ int orc_mm_rk4(const orc_mm *p, double *m, int64_t step0, int64_t nsteps)
     }
     free(k1); free(k2); free(k3); free(k4); free(u);
     return 0;
+}
+
+
+/* The magnetic sites of stored columns [x0, x0 + ncols) take the direction
+ * of their coarse cell, mcell[c] / |mcell[c]| (+z for a zero cell): the
+ * micromagnetic neighbours just outside the atomistic window (Sec. II). */
+void orc_set_columns(int kind, int sx, int ny, int nz, const int32_t *label, double *Sx,
+                     double *Sy, double *Sz, int x0, int ncols, int cx, int cy, int cz,
+                     const double *mcell)
+{
+    int64_t n = (kind == ORC_SC ? 1 : 2) * (int64_t)sx * ny * nz;
+    for (int64_t i = 0; i < n; ++i) {
+        if (label[i] < 0) continue;
+        int64_t c = coarse_cell(kind, sx, ny, i, x0, ncols, cx, cy, cz);
+        if (c < 0) continue;
+        const double *v = mcell + 3 * c;
+        double m = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        if (m > 0.0) {
+            Sx[i] = v[0] / m;
+            Sy[i] = v[1] / m;
+            Sz[i] = v[2] / m;
+        } else {
+            Sx[i] = 0.0;
+            Sy[i] = 0.0;
+            Sz[i] = 1.0;
+        }
+    }
 }

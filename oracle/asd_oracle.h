@@ -90,6 +90,9 @@ void orc_magnetisation(const orc_system *s, const double *Sx, const double *Sy, 
 void orc_coarse_grain(int kind, int sx, int ny, int nz, const int32_t *label, const double *Sx,
                       const double *Sy, const double *Sz, int x0, int ncols, int cx, int cy,
                       int cz, double *out);
+void orc_set_columns(int kind, int sx, int ny, int nz, const int32_t *label, double *Sx,
+                     double *Sy, double *Sz, int x0, int ncols, int cx, int cy, int cz,
+                     const double *mcell);
 double orc_cone_theta_max(double m);
 void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t site, uint32_t step,
                    uint32_t sys, double out[3]);

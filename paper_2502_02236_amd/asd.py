@@ -36,6 +36,8 @@ SYMBOLS = [
     "asd_last_error",
     "asd_mm_workspace_bytes", "asd_mm_create", "asd_mm_destroy", "asd_mm_set_field_temperature",
     "asd_mm_set_m", "asd_mm_get_m", "asd_mm_step", "asd_mm_get_step", "asd_mm_last_error",
+    "asd_mm_set_face", "asd_mm_get_face", "asd_multiscale_step", "asd_set_columns",
+    "asd_window_size", "asd_get_stream",
 ]
 
 
@@ -133,6 +135,14 @@ def lib():
         L.asd_mm_get_m.argtypes = [vp, vp, C.c_int32]
         L.asd_mm_step.argtypes = [vp, C.c_int64]
         L.asd_mm_get_step.argtypes = [vp, P(C.c_int64)]
+        L.asd_mm_set_face.argtypes = [vp, C.c_int32, vp, C.c_int32]
+        L.asd_mm_get_face.argtypes = [vp, C.c_int32, vp]
+        L.asd_multiscale_step.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32,
+                                          C.c_int64]
+        L.asd_set_columns.argtypes = [h, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_int32, vp]
+        L.asd_window_size.argtypes = [h, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+        L.asd_get_stream.argtypes = [h, P(vp)]
         L.asd_mm_last_error.argtypes = [vp]
         L.asd_mm_last_error.restype = C.c_char_p
         L.asd_variant_name.argtypes = [h, C.c_char_p, C.c_size_t]
@@ -451,6 +461,8 @@ class MMHandle:
     """A micromagnetic region (asd_mm_*) with a torch-owned workspace and its own stream."""
 
     def __init__(self, params: asd_mm_params, device: str = "cuda:0", stream=None):
+        """stream: a torch stream to share (a multiscale window runs both kinds of
+        handle on the atomistic handle's stream)."""
         import torch
 
         self.torch = torch
@@ -500,3 +512,12 @@ class MMHandle:
         v = C.c_int64()
         _mm_check(lib().asd_mm_get_step(self.h, C.byref(v)), self.h)
         return v.value
+
+
+def multiscale_step(atoms: "Handle", sys: int, left, right, cell, n: int):
+    """n coupled steps of micromagnetic regions left/right (MMHandle or None) and the
+    atomistic window of track system `sys` (all on atoms.stream)."""
+    rc = lib().asd_multiscale_step(atoms.h, sys, left.h if left else None,
+                                   right.h if right else None, cell[0], cell[1], cell[2], n)
+    if rc != ASD_OK:
+        raise AsdError(rc, lib().asd_strerror(rc).decode())

@@ -1453,6 +1453,37 @@ int asd_mc_sweep(asd_t *h, int64_t n)
     return ASD_OK;
 }
 
+int asd_set_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32_t cx, int32_t cy,
+                    int32_t cz, const double *mcell)
+{
+    TransferArgs a;
+    int rc = transfer_args(h, s, x0, ncols, cx, cy, cz, &a);
+    if (rc) return rc;
+    if (!mcell) return fail(h, ASD_EINVAL, "NULL cell direction");
+    a.mcell = mcell;
+    a.exact = 1;
+    if (launch_cone_columns(a, h->stream)) return fail(h, ASD_EHIP, "column launch failed");
+    h->stray_dirty = true;
+    return ASD_OK;
+}
+
+int asd_window_size(asd_t *h, int32_t s, int32_t *nx, int32_t *ny, int32_t *nz)
+{
+    if (!h || !nx || !ny || !nz) return fail(h, ASD_EINVAL, "NULL argument");
+    if (s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad system index");
+    *nx = h->sys[s].desc.nx;
+    *ny = h->sys[s].desc.ny;
+    *nz = h->sys[s].desc.nz;
+    return ASD_OK;
+}
+
+int asd_get_stream(asd_t *h, void **stream)
+{
+    if (!h || !stream) return fail(h, ASD_EINVAL, "NULL argument");
+    *stream = (void *)h->stream;
+    return ASD_OK;
+}
+
 int asd_demag_field(asd_t *h, double *per_cell, int32_t *mesh)
 {
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");

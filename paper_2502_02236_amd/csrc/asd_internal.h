@@ -187,6 +187,7 @@ struct TransferArgs {
     const double *mcell;      // cone: [ncell][3]
     uint32_t k0, k1, step;    // cone: Philox key and counter word 1
     int32_t rounds;
+    int32_t exact;            // 1: each magnetic site takes its cell's direction, no cone
 };
 int launch_coarse_grain(const TransferArgs &a, void *stream);
 int launch_cone_columns(const TransferArgs &a, void *stream);

@@ -360,6 +360,15 @@ __global__ void k_cone_columns(TransferArgs a)
         ny = my / m;
         nz = mz / m;
     }
+    if (a.exact) {  // the coarse cell's direction itself
+        T *S0 = (T *)a.S[0], *S1 = (T *)a.S[1];
+        const T v[3] = {(T)nx, (T)ny, (T)nz};
+        for (int k = 0; k < 3; ++k) {
+            S0[k * a.ncs + g] = v[k];
+            S1[k * a.ncs + g] = v[k];
+        }
+        return;
+    }
     const Words4 w = philox4x32(a.rounds, a.k0, a.k1, (uint32_t)site, a.step, a.d.sys_id, 1u);
     const double TWO_M32 = 2.3283064365386962890625e-10;
     const double u1 = ((double)w.w0 + 0.5) * TWO_M32;

@@ -53,6 +53,7 @@ struct MMArgs {
     int32_t step_off;
     void *m, *ua, *ub, *acc;  // [3][n] in the handle precision
     double *me, *alpha;       // per cell, filled by the parameter pass
+    const double *ghost[2];   // x-face neighbours [ny*nz][3] (zero: none), or null
 };
 
 // Langevin function coth x - 1/x for x >= 0: series through x^11 below 0.1,
@@ -144,8 +145,18 @@ __global__ __launch_bounds__(kMMTile) void k_mm_stage(MMArgs a, int s)
     for (int ax = 0; ax < 3; ++ax)
         for (int d = -1; d <= 1; d += 2) {
             const int64_t q = mm_nb<T>(a, i, j, k, ax, d);
-            if (q < 0) continue;
             const T w = (T)a.ih2[ax];
+            if (q < 0) {
+                // the region across an x face: its direction (zero: nothing there)
+                const double *g = ax == 0 ? a.ghost[d < 0 ? 0 : 1] : nullptr;
+                if (!g) continue;
+                const double *gv = g + 3 * ((int64_t)j + (int64_t)a.ny * k);
+                if (gv[0] == 0.0 && gv[1] == 0.0 && gv[2] == 0.0) continue;
+                lap[0] = lap[0] + ((T)gv[0] - mc.x) * w;
+                lap[1] = lap[1] + ((T)gv[1] - mc.y) * w;
+                lap[2] = lap[2] + ((T)gv[2] - mc.z) * w;
+                continue;
+            }
             lap[0] = lap[0] + (u[q] - mc.x) * w;
             lap[1] = lap[1] + (u[n + q] - mc.y) * w;
             lap[2] = lap[2] + (u[2 * n + q] - mc.z) * w;
@@ -194,6 +205,30 @@ __global__ __launch_bounds__(kMMTile) void k_mm_stage(MMArgs a, int s)
     }
 }
 
+// face neighbours from vectors (normalised; zero stays zero)
+__global__ void k_mm_set_face(double *ghost, const double *vec, int stride, int nyz)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nyz) return;
+    const double x = vec[(int64_t)c * stride], y = vec[(int64_t)c * stride + 1],
+                 z = vec[(int64_t)c * stride + 2];
+    const double r = sqrt((x * x + y * y) + z * z);
+    ghost[3 * c] = r > 0.0 ? x / r : 0.0;
+    ghost[3 * c + 1] = r > 0.0 ? y / r : 0.0;
+    ghost[3 * c + 2] = r > 0.0 ? z / r : 0.0;
+}
+
+// directions of the cells of x face `face`
+template <typename T>
+__global__ void k_mm_get_face(MMArgs a, int face, double *dirs)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ny * a.nz) return;
+    const int64_t cell = (face == 0 ? 0 : a.nx - 1) + (int64_t)a.nx * c;
+    const T *m = (const T *)a.m;
+    for (int d = 0; d < 3; ++d) dirs[3 * c + d] = (double)m[d * (int64_t)a.n + cell];
+}
+
 __global__ void k_mm_advance(int64_t *step, int64_t n)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *step += n;
@@ -215,7 +250,8 @@ struct asd_mm_t {
     int elem = 8;
     int64_t n = 0, step = 0;
     size_t off_m = 0, off_ua = 0, off_ub = 0, off_acc = 0, off_me = 0, off_al = 0,
-           off_step = 0, off_bits = 0, bytes = 0;
+           off_step = 0, off_bits = 0, off_ghost[2] = {0, 0}, off_fsum = 0, off_fdir = 0, bytes = 0;
+    bool ghost_on[2] = {false, false};
     bool params_valid = false;  // m_e, alpha current for a spot that does not move
     hipGraphExec_t graph = nullptr;
     std::string err;
@@ -278,6 +314,11 @@ static void mm_layout(const asd_mm_params *p, asd_mm_t *h)
     h->off_al = take(n * sizeof(double));
     h->off_step = take(sizeof(int64_t));
     h->off_bits = take(kMMMaxBits);
+    const size_t nyz = (size_t)p->ny * p->nz;
+    h->off_ghost[0] = take(3 * nyz * sizeof(double));
+    h->off_ghost[1] = take(3 * nyz * sizeof(double));
+    h->off_fsum = take(4 * nyz * sizeof(double));  // coupling scratch
+    h->off_fdir = take(3 * nyz * sizeof(double));
     h->bytes = off;
 }
 
@@ -330,6 +371,8 @@ static MMArgs mm_args(const asd_mm_t *h, int step_off)
     a.acc = w + h->off_acc;
     a.me = (double *)(w + h->off_me);
     a.alpha = (double *)(w + h->off_al);
+    for (int f = 0; f < 2; ++f)
+        a.ghost[f] = h->ghost_on[f] ? (const double *)(w + h->off_ghost[f]) : nullptr;
     return a;
 }
 
@@ -515,6 +558,96 @@ int asd_mm_get_step(asd_mm_t *h, int64_t *step)
 {
     if (!h || !step) return mm_fail(h, ASD_EINVAL, "NULL argument");
     *step = h->step;
+    return ASD_OK;
+}
+
+int asd_mm_set_face(asd_mm_t *h, int32_t face, const double *vec, int32_t stride)
+{
+    if (!h) return mm_fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (face != 0 && face != 1) return mm_fail(h, ASD_EINVAL, "face is 0 (-x) or 1 (+x)");
+    const bool per = h->p.bc_x == ASD_BC_PERIODIC;
+    if (vec && per) return mm_fail(h, ASD_EINVAL, "a periodic x axis has no faces to couple");
+    const bool was = h->ghost_on[face];
+    if (!vec) {
+        h->ghost_on[face] = false;
+    } else {
+        if (stride < 3) return mm_fail(h, ASD_EINVAL, "stride must be >= 3");
+        const int nyz = h->p.ny * h->p.nz;
+        hipLaunchKernelGGL(k_mm_set_face, dim3((nyz + 255) / 256), dim3(256), 0, h->stream,
+                           (double *)(h->ws + h->off_ghost[face]), vec, (int)stride, nyz);
+        MM_HIP(h, hipGetLastError());
+        h->ghost_on[face] = true;
+    }
+    if (was != h->ghost_on[face]) mm_drop_graph(h);  // graphs bake the face pointers in
+    return ASD_OK;
+}
+
+int asd_mm_get_face(asd_mm_t *h, int32_t face, double *dirs)
+{
+    if (!h || !dirs) return mm_fail(h, ASD_EINVAL, "NULL argument");
+    if (face != 0 && face != 1) return mm_fail(h, ASD_EINVAL, "face is 0 (-x) or 1 (+x)");
+    const MMArgs a = mm_args(h, 0);
+    const int nyz = h->p.ny * h->p.nz;
+    if (h->elem == 8)
+        hipLaunchKernelGGL(k_mm_get_face<double>, dim3((nyz + 255) / 256), dim3(256), 0, h->stream,
+                           a, (int)face, dirs);
+    else
+        hipLaunchKernelGGL(k_mm_get_face<float>, dim3((nyz + 255) / 256), dim3(256), 0, h->stream,
+                           a, (int)face, dirs);
+    MM_HIP(h, hipGetLastError());
+    return ASD_OK;
+}
+
+int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                        int32_t cy, int32_t cz, int64_t n)
+{
+    if (!atoms || (!left && !right)) return mm_fail(nullptr, ASD_EINVAL, "need atoms and a region");
+    if (n < 0 || cx < 1 || cy < 1 || cz < 1) return mm_fail(nullptr, ASD_EINVAL, "bad sizes");
+    int32_t nx, ny, nz;
+    int rc = asd_window_size(atoms, sys, &nx, &ny, &nz);
+    if (rc) return rc;
+    int64_t step;
+    int32_t org;
+    if ((rc = asd_get_state(atoms, sys, &step, &org))) return rc;
+    void *st = nullptr;
+    if ((rc = asd_get_stream(atoms, &st))) return rc;
+    asd_mm_t *r[2] = {left, right};
+    for (asd_mm_t *m : r) {
+        if (!m) continue;
+        if (m->stream != (hipStream_t)st)
+            return mm_fail(m, ASD_EINVAL, "the region must run on the atomistic handle's stream");
+        if (m->p.ny != (ny + cy - 1) / cy || m->p.nz != (nz + cz - 1) / cz)
+            return mm_fail(m, ASD_EINVAL, "region ny, nz must equal the window's coarse cells");
+        if (m->p.bc_x == ASD_BC_PERIODIC) return mm_fail(m, ASD_EINVAL, "region x axis is periodic");
+    }
+    if (nx < cx || org < cx) return mm_fail(nullptr, ASD_EINVAL, "window too narrow or too close to the track start");
+    for (int64_t t = 0; t < n; ++t) {
+        // window -> regions: averaged boundary coarse columns
+        if (left) {
+            double *sum = (double *)(left->ws + left->off_fsum);
+            if ((rc = asd_coarse_grain(atoms, sys, org, cx, cx, cy, cz, sum))) return rc;
+            if ((rc = asd_mm_set_face(left, 1, sum, 4))) return rc;
+        }
+        if (right) {
+            double *sum = (double *)(right->ws + right->off_fsum);
+            if ((rc = asd_coarse_grain(atoms, sys, org + nx - cx, cx, cx, cy, cz, sum))) return rc;
+            if ((rc = asd_mm_set_face(right, 0, sum, 4))) return rc;
+        }
+        // regions -> window: their boundary cells into the frozen columns
+        if (left) {
+            double *dir = (double *)(left->ws + left->off_fdir);
+            if ((rc = asd_mm_get_face(left, 1, dir))) return rc;
+            if ((rc = asd_set_columns(atoms, sys, org - cx, cx, cx, cy, cz, dir))) return rc;
+        }
+        if (right) {
+            double *dir = (double *)(right->ws + right->off_fdir);
+            if ((rc = asd_mm_get_face(right, 0, dir))) return rc;
+            if ((rc = asd_set_columns(atoms, sys, org + nx, cx, cx, cy, cz, dir))) return rc;
+        }
+        if ((rc = asd_step(atoms, 1))) return rc;
+        if (left && (rc = asd_mm_step(left, 1))) return rc;
+        if (right && (rc = asd_mm_step(right, 1))) return rc;
+    }
     return ASD_OK;
 }
 

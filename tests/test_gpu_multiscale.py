@@ -1,0 +1,163 @@
+"""GPU parity of the multiscale window (Sec. II, Fig. 1): micromagnetic regions
+either side of the atomistic window, exchange-coupled through their faces
+(asd_multiscale_step), against the same step sequence on the oracle.
+
+Bars: FP64 within 1e-12 per component of the atomistic spins and of both
+regions after 30 coupled steps (the only difference in arithmetic is the
+order of the FP64 cell sums that become the regions' face neighbours);
+FP32 within 1e-4 (atoms) and 2e-5 (regions).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle_build import oracle_labels, oracle_system, window_mask
+from paper_2502_02236_amd import asd as A
+from paper_2502_02236_amd import bridge
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    A.lib()
+    return torch
+
+
+CELL = (2, 2, 2)
+NXA, NYA, NZA = 24, 12, 4
+
+
+def atoms_workload(grains):
+    cx = CELL[0]
+    return W.c5_track_window().scaled(nx=NXA, ny=NYA, nz=NZA, track_nx=NXA + 2 * cx,
+                                      grains=grains, grain_pitch=3.0e-9, spot_mode=W.SPOT_NONE,
+                                      T_amb=300.0, bits=None, steps_per_bit=0, ku_spread=0.0,
+                                      B=(0.0, 0.0, -0.8))
+
+
+def mm_params(w, prec, nx):
+    a = w.a
+    p = A.asd_mm_params()
+    p.precision = prec
+    p.nx, p.ny, p.nz = nx, -(-NYA // CELL[1]), -(-NZA // CELL[2])
+    p.bc_x = p.bc_y = p.bc_z = A.ASD_BC_OPEN
+    for k in range(3):
+        p.h[k] = CELL[k] * a
+    p.Ms0 = w.mu_s / a ** 3
+    p.A0 = w.J[0] / (2 * a)          # Eq. 9
+    p.K0 = w.ku / a ** 3
+    p.lambda_, p.gamma, p.Tc, p.mu_s, p.dt = w.alpha, w.gamma, 710.0, w.mu_s, w.dt
+    return p
+
+
+def mm_oracle(p):
+    return oracle.MM(n=(p.nx, p.ny, p.nz), h=tuple(p.h), Ms0=p.Ms0, A0=p.A0, K0=p.K0,
+                     lam=p.lambda_, gamma=p.gamma, Tc=p.Tc, mu_s=p.mu_s, dt=p.dt)
+
+
+def face_dirs(sums):
+    s = np.asarray(sums)[:, :3]
+    r = np.sqrt((s[:, 0] * s[:, 0] + s[:, 1] * s[:, 1]) + s[:, 2] * s[:, 2])
+    out = np.zeros_like(s)
+    nz = r > 0
+    out[nz] = s[nz] / r[nz, None]
+    return out
+
+
+def random_m(n, seed):
+    rng = np.random.default_rng(seed)
+    m = np.stack([0.5 * rng.uniform(-1, 1, n), 0.5 * rng.uniform(-1, 1, n), np.ones(n)])
+    return m / np.linalg.norm(m, axis=0)
+
+
+@pytest.mark.parametrize("prec,grains", [(A.ASD_FP64, False), (A.ASD_FP64, True),
+                                         (A.ASD_FP32, True)], ids=["fp64", "fp64_grains", "fp32_grains"])
+def test_multiscale_window_matches_oracle(prec, grains):
+    steps = 30
+    cx, cy, cz = CELL
+    w = atoms_workload(grains)
+    say(f"[multiscale] prec={prec} grains={grains} window {NXA}x{NYA}x{NZA}, cells {CELL}")
+    h = bridge.make_handle(w, prec)
+    h.shift_window(cx)  # frozen columns [0, cx) and [cx + nx, track end) hold the regions' faces
+    lab = h.labels()
+    S0 = W.initial_spins(len(lab), 5)
+    S0[:, lab < 0] = 0
+    h.set_spins(S0)
+    pl, pr = mm_params(w, prec, 5), mm_params(w, prec, 4)
+    L = A.MMHandle(pl, stream=h.stream)
+    R = A.MMHandle(pr, stream=h.stream)
+    dr = A.asd_drive()
+    dr.B[2] = -0.8
+    dr.T_amb = 300.0
+    L.set_drive(dr)
+    R.set_drive(dr)
+    mL0, mR0 = random_m(L.n, 1), random_m(R.n, 2)
+    L.set_m(mL0)
+    R.set_m(mR0)
+    A.multiscale_step(h, 0, L, R, CELL, steps)
+    gS, gL, gR = h.get_spins(), L.get_m(), R.get_m()
+
+    # the same sequence on the oracle
+    sx = w.track_nx
+    org = cx
+    sysm = oracle_system(w, labels=oracle_labels(w), active=window_mask(w, org), origin=org)
+    oL, oR = mm_oracle(pl), mm_oracle(pr)
+    for o in (oL, oR):
+        o._p.B[2] = -0.8
+        o._p.T_amb = 300.0
+    S, mL, mR = np.array(S0, np.float64), mL0.astype(np.float64), mR0.astype(np.float64)
+    olab = oracle_labels(w)
+    for t in range(steps):
+        oL.set_ghost(1, face_dirs(oracle.coarse_grain(W.SC, sx, NYA, NZA, olab, S, org, cx, cx, cy, cz)))
+        oR.set_ghost(0, face_dirs(oracle.coarse_grain(W.SC, sx, NYA, NZA, olab, S, org + NXA - cx,
+                                                      cx, cx, cy, cz)))
+        S = oracle.set_columns(W.SC, sx, NYA, NZA, olab, S, org - cx, cx, cx, cy, cz, oL.face(1, mL))
+        S = oracle.set_columns(W.SC, sx, NYA, NZA, olab, S, org + NXA, cx, cx, cy, cz, oR.face(0, mR))
+        S = sysm.heun(S, t, 1)
+        mL, mR = oL.rk4(mL, t, 1), oR.rk4(mR, t, 1)
+    dS = float(np.max(np.abs(gS.astype(np.float64) - S)))
+    dL = float(np.max(np.abs(gL.astype(np.float64) - mL)))
+    dR = float(np.max(np.abs(gR.astype(np.float64) - mR)))
+    say(f"  max |dS| atoms {dS:.3e}, left region {dL:.3e}, right region {dR:.3e}")
+    tol_a, tol_m = (1e-12, 1e-12) if prec == A.ASD_FP64 else (1e-4, 2e-5)
+    assert dS <= tol_a and dL <= tol_m and dR <= tol_m
+    # the coupling mattered: the regions alone land elsewhere
+    alone = mm_oracle(pl)
+    alone._p.B[2] = -0.8
+    alone._p.T_amb = 300.0
+    assert float(np.max(np.abs(alone.rk4(mL0, 0, steps) - mL))) > 100 * max(dL, 1e-15)
+    L.close()
+    R.close()
+    h.close()
+
+
+def test_multiscale_errors():
+    w = atoms_workload(False)
+    h = bridge.make_handle(w, A.ASD_FP64)
+    L = A.MMHandle(mm_params(w, A.ASD_FP64, 3), stream=h.stream)
+    with pytest.raises(A.AsdError):  # origin 0: no frozen columns left of the window
+        A.multiscale_step(h, 0, L, None, CELL, 1)
+    h.shift_window(CELL[0])
+    other = A.MMHandle(mm_params(w, A.ASD_FP64, 3))  # its own stream
+    with pytest.raises(A.AsdError):
+        A.multiscale_step(h, 0, other, None, CELL, 1)
+    bad = mm_params(w, A.ASD_FP64, 3)
+    bad.ny += 1
+    Lb = A.MMHandle(bad, stream=h.stream)
+    with pytest.raises(A.AsdError):
+        A.multiscale_step(h, 0, Lb, None, CELL, 1)
+    A.multiscale_step(h, 0, L, None, CELL, 2)  # the valid pairing still runs
+    for x in (L, other, Lb, h):
+        x.close()
