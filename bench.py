@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track", "transfer",
-                                           "demag", "mc"], default="slab")
+                                           "demag", "mc", "mm", "multiscale"], default="slab")
     ap.add_argument("--demag-cell", type=int, nargs=3, default=[4, 4, 3],
                     help="coarse cell of the demag workload, in lattice cells")
     ap.add_argument("--kernel", choices=["auto", "plain", "fused"], default="auto")
@@ -293,6 +293,104 @@ def transfer_run(args, cell=7, reps=20):
                 th_bytes=th_bytes, e=e, cell=cell, reps=reps)
 
 
+MM_ALU_PER_STAGE = 66
+
+
+def mm_run(args):
+    """Micromagnetic window of the paper's multiscale runs (Sec. III): 300 x 60 x 16 nm
+    in 1 x 1 x 2 nm cells (300 x 60 x 8), SC parameters (Ms0 5.2e5 A/m, K0 2.2e6 J/m^3,
+    A0 = J / 2a with J = 6.8e-21 J, a = 0.5 nm, lambda 0.1, T_C 710 K), RK4 at
+    dt = 20 fs, 800 K spot locked to the window, write field 0.8 T with 20 nm bits.
+    Algorithmic VALU operations per cell and RK4 stage: Laplacian 36, field 7,
+    Landau-Lifshitz right-hand side 15, stage update 8: 66."""
+    import torch
+    from paper_2502_02236_amd import asd as A
+
+    prec = A.ASD_FP32 if args.precision == "fp32" else A.ASD_FP64
+    a, J = 0.5e-9, 6.8e-21
+    p = A.asd_mm_params()
+    p.precision = prec
+    p.nx, p.ny, p.nz = 300, 60, 8
+    p.bc_x = p.bc_y = p.bc_z = A.ASD_BC_OPEN
+    p.h[0], p.h[1], p.h[2] = 1e-9, 1e-9, 2e-9
+    p.Ms0, p.A0, p.K0, p.lambda_, p.gamma = 5.2e5, J / (2 * a), 2.2e6, 0.1, 1.76e11
+    p.Tc, p.mu_s, p.dt, p.graph_steps = 710.0, 5.2e5 * a ** 3, 20e-15, 100
+    g = A.MMHandle(p)
+    d = A.asd_drive()
+    d.B[2] = 0.8
+    bits = np.ascontiguousarray([int(b) for b in "0010111100101101100100001"], dtype=np.uint8)
+    d.n_bits = len(bits)
+    d.bits = bits.ctypes.data_as(A.C.POINTER(A.C.c_uint8))
+    d.steps_per_bit = int(round(20e-9 / (20.0 * p.dt)))
+    d.spot_mode = A.ASD_SPOT_LOCKED
+    d.T_amb, d.T_peak, d.fwhm, d.x0, d.y0 = 300.0, 800.0, 40e-9, 150e-9, 30e-9
+    g.set_drive(d)
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step(args.steps)
+    e1.record(g.stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    m = g.get_m().astype(np.float64)
+    g.close()
+    return dict(t=t, n=300 * 60 * 8, mz=float(m[2].mean()))
+
+
+def multiscale_run(args):
+    """The paper's multiscale window (Sec. III): 100 nm of SC atoms (334 x 200 x 33 at
+    a = 0.3 nm, 60 x 10 nm cross-section, Voronoi grains) between two 100 nm
+    micromagnetic regions of 4 x 4 x 3 lattice cells (84 x 50 x 11 cells each),
+    exchange-coupled through their faces, 800 K spot locked to the atomistic window,
+    dt = 1 fs for both (one RK4 step per Heun step)."""
+    import torch
+    import workloads as W
+    from paper_2502_02236_amd import asd as A
+    from paper_2502_02236_amd import bridge
+
+    prec = A.ASD_FP32 if args.precision == "fp32" else A.ASD_FP64
+    cell = (4, 4, 3)
+    nxa = 334
+    w = W.c5_track_window().scaled(nx=nxa, track_nx=nxa + 2 * cell[0], ku_spread=0.0,
+                                   x0=50e-9, y0=30e-9)
+    h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_AUTO)
+    h.shift_window(cell[0])
+    a = w.a
+    regions = []
+    for _ in range(2):
+        p = A.asd_mm_params()
+        p.precision = prec
+        p.nx, p.ny, p.nz = 84, -(-w.ny // cell[1]), -(-w.nz // cell[2])
+        p.bc_x = p.bc_y = p.bc_z = A.ASD_BC_OPEN
+        for k in range(3):
+            p.h[k] = cell[k] * a
+        p.Ms0, p.A0, p.K0 = w.mu_s / a ** 3, w.J[0] / (2 * a), w.ku / a ** 3
+        p.lambda_, p.gamma, p.Tc, p.mu_s, p.dt = w.alpha, w.gamma, 710.0, w.mu_s, w.dt
+        g = A.MMHandle(p, stream=h.stream)
+        d = A.asd_drive()
+        d.B[2] = 0.8
+        d.T_amb = 300.0
+        g.set_drive(d)
+        regions.append(g)
+    n_atoms = int((h.labels() >= 0).sum() * nxa / w.track_nx)
+    A.multiscale_step(h, 0, regions[0], regions[1], cell, args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(h.stream)
+    A.multiscale_step(h, 0, regions[0], regions[1], cell, args.steps)
+    e1.record(h.stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    kname = h.variant_name()
+    for g in regions:
+        g.close()
+    h.close()
+    return dict(t=t, n_atoms=n_atoms, n_cells=2 * 84 * 50 * 11, kernel=kname, name=w.name)
+
+
 MC_ALU_CYCLES = 101
 
 
@@ -377,6 +475,44 @@ def main():
                                     "kernel": "k_cone_columns",
                                     "bytes_per_site": 2 * 3 * t["e"] + 2},
         }), flush=True)
+        return
+    if args.workload == "multiscale":
+        r = multiscale_run(args)
+        per_step = r["t"] / args.steps
+        print(json.dumps({
+            "metric": "multiscale window steps/s (atomistic Heun + two micromagnetic RK4 regions)",
+            "value": args.steps / r["t"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": "multiscale_window_mm100nm_atoms100nm_mm100nm_60x10nm",
+                       "atomistic_magnetic_sites": r["n_atoms"], "micromagnetic_cells": r["n_cells"],
+                       "atomistic_kernel": r["kernel"], "precision": args.precision},
+            "atomistic_spin_updates_per_s": r["n_atoms"] / per_step,
+            "roofline": None}), flush=True)
+        return
+    if args.workload == "mm":
+        r = mm_run(args)
+        per_step = r["t"] / args.steps
+        e = 4 if args.precision == "fp32" else 8
+        hbm = 2 * 3 * e * r["n"] / per_step / 1e9
+        alu = 4 * MM_ALU_PER_STAGE * r["n"] / per_step / 1e12
+        peak = VALU_PEAK_T if args.precision == "fp32" else VALU_PEAK_T / 2
+        print(json.dumps({
+            "metric": "micromagnetic cell-updates/s (cells x RK4 steps)",
+            "value": r["n"] * args.steps / r["t"], "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": "mm_window300x60x8_cells1x1x2nm_spot800K_locked",
+                       "cells": r["n"], "dt_fs": 20.0, "precision": args.precision},
+            "roofline": {"bound": "alu", "achieved": alu, "peak": peak,
+                         "unit": "T VALU lane-ops/s", "frac": alu / peak,
+                         "alu_ops_per_cell_step": 4 * MM_ALU_PER_STAGE,
+                         "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": hbm / HBM_PEAK_GBS, "bytes_per_cell": 6 * e},
+                         "traffic": None, "kernel": "k_mm_stage (four launches per step)"},
+            "final_mz": r["mz"]}), flush=True)
         return
     if args.workload == "mc":
         r = mc_run(args)
