@@ -11,6 +11,9 @@
 //             spectrum, inverse FFT along z, keep the ncz planes of the mesh
 //   y pass    inverse FFT along y, keep the ncy rows of the mesh
 //   x_out     inverse FFT along x, keep the ncx cells: the field per cell
+// The x transform of the real cell sums is Hermitian, X(Px - k) = conj X(k),
+// so only kx = 0 .. Px/2 (Pxh columns) is kept through the y and z passes and
+// the full row is rebuilt before the inverse x transform.
 // The spectrum carries -mu0 mu_s / (V Px Py Pz), so the result is the flux
 // density mu0 H_d in tesla from plain spin sums.  Every transform is a
 // radix-2 Stockham FFT over a batch of lines held in LDS (ping-pong
@@ -178,9 +181,10 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T
     __syncthreads();
     const Cx<T> *r = fft_lines<T, false>(x, y, 3, dm.lx, Px, (const Cx<T> *)dm.tw[0]);
     Cx<T> *out = (Cx<T> *)dm.wx;
-    for (int q = threadIdx.x; q < 3 * Px; q += blockDim.x) {
-        const int c = q >> dm.lx, kx = q & (Px - 1);
-        out[((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Px + kx] = r[q];
+    const int Pxh = (Px >> 1) + 1;
+    for (int q = threadIdx.x; q < 3 * Pxh; q += blockDim.x) {
+        const int c = q / Pxh, kx = q - c * Pxh;
+        out[((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx] = r[c * Px + kx];
     }
 }
 
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T
 template <typename T, bool INV>
 __global__ __launch_bounds__(kDmThreads) void k_dm_y(DemagDev dm)
 {
-    const int Px = 1 << dm.lx, Py = 1 << dm.ly;
+    const int Px = ((1 << dm.lx) >> 1) + 1, Py = 1 << dm.ly;  // Px: the kept columns
     const int XB = dm.xb_y, lxb = __ffs(XB) - 1;
     const int kx0 = blockIdx.x * XB;
     const int plane = blockIdx.y;  // c * ncz + z
@@ -204,13 +208,14 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_y(DemagDev dm)
     Cx<T> *x = lds_base<T>(), *y = x + XB * ls;
     for (int q = threadIdx.x; q < XB * Py; q += blockDim.x) {
         const int yy = q >> lxb, xb = q & (XB - 1);
-        x[xb * ls + yy] = yy < rows_in ? src[pin + (int64_t)yy * Px + kx0 + xb] : Cx<T>{T(0), T(0)};
+        x[xb * ls + yy] = yy < rows_in && kx0 + xb < Px ? src[pin + (int64_t)yy * Px + kx0 + xb]
+                                                        : Cx<T>{T(0), T(0)};
     }
     __syncthreads();
     const Cx<T> *r = fft_lines<T, INV>(x, y, XB, dm.ly, ls, (const Cx<T> *)dm.tw[1]);
     for (int q = threadIdx.x; q < rows_out * XB; q += blockDim.x) {
         const int yy = q >> lxb, xb = q & (XB - 1);
-        dst[pout + (int64_t)yy * Px + kx0 + xb] = r[xb * ls + yy];
+        if (kx0 + xb < Px) dst[pout + (int64_t)yy * Px + kx0 + xb] = r[xb * ls + yy];
     }
 }
 
@@ -220,12 +225,13 @@ template <typename T>
 __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
 {
     const int Px = 1 << dm.lx, Py = 1 << dm.ly, Pz = 1 << dm.lz;
+    const int Pxh = (Px >> 1) + 1;  // kept columns kx = 0 .. Px/2
     const int XB = dm.xb_z, lxb = __ffs(XB) - 1;
     const int kx0 = blockIdx.x * XB, ky = blockIdx.y, s = blockIdx.z;
     Cx<T> *w = (Cx<T> *)dm.wy;
-    const int64_t plane = (int64_t)Py * Px;
+    const int64_t plane = (int64_t)Py * Pxh;
     const int64_t cstride = (int64_t)dm.ncz * plane;  // component stride in wy
-    const int64_t base = (int64_t)s * 3 * cstride + (int64_t)ky * Px + kx0;
+    const int64_t base = (int64_t)s * 3 * cstride + (int64_t)ky * Pxh + kx0;
     const int ls = Pz + 1;
     const int nl = 3 * XB;
     Cx<T> *x = lds_base<T>(), *y = x + nl * ls;
@@ -233,8 +239,9 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
     for (int q = threadIdx.x; q < 3 * Pz * XB; q += blockDim.x) {
         const int xb = q & (XB - 1), row = q >> lxb;
         const int c = row >> dm.lz, z = row & (Pz - 1);
-        x[(c * XB + xb) * ls + z] =
-            z < dm.ncz ? w[base + c * cstride + z * plane + xb] : Cx<T>{T(0), T(0)};
+        x[(c * XB + xb) * ls + z] = z < dm.ncz && kx0 + xb < Pxh
+                                        ? w[base + c * cstride + z * plane + xb]
+                                        : Cx<T>{T(0), T(0)};
     }
     __syncthreads();
     Cx<T> *r = fft_lines<T, false>(x, y, nl, dm.lz, ls, (const Cx<T> *)dm.tw[2]);
@@ -247,10 +254,10 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
     const T sy = ky <= (Py >> 1) ? T(1) : T(-1);
     for (int q = threadIdx.x; q < XB * Pz; q += blockDim.x) {
         const int kz = q & (Pz - 1), xb = q >> dm.lz;
-        const int kx = kx0 + xb;
-        const int kxr = kx <= (Px >> 1) ? kx : Px - kx;
+        const int kx = min(kx0 + xb, Px >> 1);  // columns past Px/2 are never stored
+        const int kxr = kx;
         const int kzr = kz <= (Pz >> 1) ? kz : Pz - kz;
-        const T sx = kx <= (Px >> 1) ? T(1) : T(-1);
+        const T sx = T(1);
         const T sz = kz <= (Pz >> 1) ? T(1) : T(-1);
         const int64_t o = ((int64_t)kyr * ox + kxr) * oz + kzr;
         const T nxx = K[o], nyy = K[ocomp + o], nzz = K[2 * ocomp + o];
@@ -270,7 +277,7 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
     for (int q = threadIdx.x; q < 3 * Pz * XB; q += blockDim.x) {
         const int xb = q & (XB - 1), row = q >> lxb;
         const int c = row >> dm.lz, z = row & (Pz - 1);
-        if (z < dm.ncz) w[base + c * cstride + z * plane + xb] = h[(c * XB + xb) * ls + z];
+        if (z < dm.ncz && kx0 + xb < Pxh) w[base + c * cstride + z * plane + xb] = h[(c * XB + xb) * ls + z];
     }
 }
 
@@ -283,9 +290,16 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage,
     const int j = blockIdx.x % dm.ncy, k = blockIdx.x / dm.ncy, s = blockIdx.y;
     const Cx<T> *in = (const Cx<T> *)dm.wx;
     Cx<T> *x = lds_base<T>(), *y = x + 3 * Px;
+    const int Pxh = (Px >> 1) + 1;
     for (int q = threadIdx.x; q < 3 * Px; q += blockDim.x) {
         const int c = q >> dm.lx, kx = q & (Px - 1);
-        x[q] = in[((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Px + kx];
+        const int64_t row = ((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh;
+        if (kx < Pxh) {
+            x[q] = in[row + kx];
+        } else {  // X(Px - k) = conj X(k)
+            const Cx<T> v = in[row + (Px - kx)];
+            x[q] = Cx<T>{v.re, -v.im};
+        }
     }
     __syncthreads();
     const Cx<T> *r = fft_lines<T, true>(x, y, 3, dm.lx, Px, (const Cx<T> *)dm.tw[0]);
@@ -321,9 +335,10 @@ int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
     const dim3 blk(kDmThreads);
     const dim3 grows(dm.ncy * dm.ncz, dm.n_sys);
     hipLaunchKernelGGL(k_dm_gather_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, S, ncs, sys, origin);
-    const dim3 gy(Px / dm.xb_y, 3 * dm.ncz, dm.n_sys);
+    const int Pxh = (Px >> 1) + 1;
+    const dim3 gy((Pxh + dm.xb_y - 1) / dm.xb_y, 3 * dm.ncz, dm.n_sys);
     hipLaunchKernelGGL((k_dm_y<T, false>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
-    const dim3 gz(Px / dm.xb_z, Py, dm.n_sys);
+    const dim3 gz((Pxh + dm.xb_z - 1) / dm.xb_z, Py, dm.n_sys);
     hipLaunchKernelGGL(k_dm_z<T>, gz, blk, 2 * 3 * dm.xb_z * (Pz + 1) * cb, st, dm);
     hipLaunchKernelGGL((k_dm_y<T, true>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
     hipLaunchKernelGGL(k_dm_x_out<T>, grows, blk, 2 * 3 * Px * cb, st, dm, stage, origin);

@@ -428,14 +428,15 @@ static const char *demag_geometry(const asd_params *p, const asd_system_desc *sy
     // and no fewer than 1024 workgroups while the lines can be split
     const int budget = p->precision == ASD_FP64 ? 1024 : 2048;
     const int Px = 1 << g->lx, Py = 1 << g->ly, Pz = 1 << g->lz;
+    const int Pxh = Px / 2 + 1;  // kept columns of the Hermitian x transform
     int xb = 1;
-    while (xb * 2 <= Px && xb * 2 * (Py + 1) <= budget &&
-           (int64_t)(Px / (xb * 2)) * 3 * g->ncz * n_sys >= 1024)
+    while (xb * 2 <= Pxh && xb * 2 * (Py + 1) <= budget &&
+           (int64_t)((Pxh + 2 * xb - 1) / (xb * 2)) * 3 * g->ncz * n_sys >= 1024)
         xb *= 2;
     g->xb_y = xb;
     xb = 1;
-    while (xb * 2 <= Px && xb * 2 * 3 * (Pz + 1) <= budget &&
-           (int64_t)(Px / (xb * 2)) * Py * n_sys >= 1024)
+    while (xb * 2 <= Pxh && xb * 2 * 3 * (Pz + 1) <= budget &&
+           (int64_t)((Pxh + 2 * xb - 1) / (xb * 2)) * Py * n_sys >= 1024)
         xb *= 2;
     g->xb_z = xb;
     g->n_sys = n_sys;
@@ -506,8 +507,9 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         const DemagDev &g = L.dm;
         const size_t Px = (size_t)1 << g.lx, Py = (size_t)1 << g.ly, Pz = (size_t)1 << g.lz;
         const size_t cplx = 2 * elem;
-        L.off_dwx = take((size_t)n_sys * 3 * g.ncz * g.ncy * Px * cplx);
-        L.off_dwy = take((size_t)n_sys * 3 * g.ncz * Py * Px * cplx);
+        const size_t Pxh = Px / 2 + 1;  // kept columns of the Hermitian x transform
+        L.off_dwx = take((size_t)n_sys * 3 * g.ncz * g.ncy * Pxh * cplx);
+        L.off_dwy = take((size_t)n_sys * 3 * g.ncz * Py * Pxh * cplx);
         for (int b = 0; b < 2; ++b) L.off_dbd[b] = take((size_t)n_sys * 3 * g.ncell * elem);
         L.off_dK = take(6 * (Px / 2 + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * elem);
         L.off_dtw[0] = take(std::max<size_t>(Px / 2, 1) * cplx);
@@ -532,18 +534,19 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
             t.lx = ilog2_ceil(2 * t.ncx - 1);
             const size_t PxT = (size_t)1 << t.lx;
             const int budget = p->precision == ASD_FP64 ? 1024 : 2048;
+            const int PxTh = (int)PxT / 2 + 1;
             int xb = 1;
-            while (xb * 2 <= (int)PxT && xb * 2 * ((int)Py + 1) <= budget &&
-                   (int64_t)(PxT / (xb * 2)) * 3 * g.ncz * n_sys >= 1024)
+            while (xb * 2 <= PxTh && xb * 2 * ((int)Py + 1) <= budget &&
+                   (int64_t)((PxTh + 2 * xb - 1) / (xb * 2)) * 3 * g.ncz * n_sys >= 1024)
                 xb *= 2;
             t.xb_y = xb;
             xb = 1;
-            while (xb * 2 <= (int)PxT && xb * 2 * 3 * ((int)Pz + 1) <= budget &&
-                   (int64_t)(PxT / (xb * 2)) * Py * n_sys >= 1024)
+            while (xb * 2 <= PxTh && xb * 2 * 3 * ((int)Pz + 1) <= budget &&
+                   (int64_t)((PxTh + 2 * xb - 1) / (xb * 2)) * Py * n_sys >= 1024)
                 xb *= 2;
             t.xb_z = xb;
-            L.off_twx = take((size_t)n_sys * 3 * g.ncz * g.ncy * PxT * cplx);
-            L.off_twy = take((size_t)n_sys * 3 * g.ncz * Py * PxT * cplx);
+            L.off_twx = take((size_t)n_sys * 3 * g.ncz * g.ncy * (PxT / 2 + 1) * cplx);
+            L.off_twy = take((size_t)n_sys * 3 * g.ncz * Py * (PxT / 2 + 1) * cplx);
             L.off_tK = take(6 * (PxT / 2 + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * elem);
             L.off_ttw = take(std::max<size_t>(PxT / 2, 1) * cplx);
             L.off_tstray = take((size_t)n_sys * 3 * g.ncell * elem);

@@ -79,8 +79,8 @@ struct DemagDev {
     int32_t ncell_win;        // track mesh: cells of the window mesh
     void *bstray;             // window mesh: added to the result when not null;
                               // track mesh: the output [S][3][ncell_win]
-    void *wx;                 // complex [S][3][ncz][ncy][Px]
-    void *wy;                 // complex [S][3][ncz][Py][Px]
+    void *wx;                 // complex [S][3][ncz][ncy][Px/2+1] (Hermitian half in x)
+    void *wy;                 // complex [S][3][ncz][Py][Px/2+1]
     void *bd[2];              // field (T) per coarse cell, [S][3][ncell], one per Heun stage
     const void *K;            // tensor spectrum, octant [6][Py/2+1][Px/2+1][Pz/2+1]
     const void *tw[3];        // twiddles exp(-2 pi i t / P), t < P / 2, per axis
