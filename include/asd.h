@@ -276,13 +276,14 @@ int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int
  * anisotropy, write field with its polarity at the sweep index; no thermal
  * field) at each system's ambient temperature: the calibration of the
  * exchange constant against the Curie temperature (Sec. III with Eq. 8).
- * A sweep visits the window sites with (x + y + z) even, then those with it
- * odd (stored-lattice coordinates); a visit proposes a direction uniform on
- * the sphere from Philox words (site, sweep, system, 2) and accepts it with
- * probability min(1, exp(-dE / kB T)).  The sweep index is the step counter,
- * which advances by n.  ASD_EUNSUPPORTED for L1_0 lattices, for a periodic
- * axis of odd length (the checkerboard would pair neighbours) and with the
- * demagnetising field. */
+ * A sweep visits the window sites colour by colour (stored-lattice cell
+ * coordinates): SC (x + y + z) mod 2, L1_0 s + 2 ((x + y) mod 2) + 4 (z mod 2)
+ * with s the sublattice, so that no two neighbours share a colour; a visit
+ * proposes a direction uniform on the sphere from Philox words (site, sweep,
+ * system, 2) and accepts it with probability min(1, exp(-dE / kB T)).  The
+ * sweep index is the step counter, which advances by n.  ASD_EUNSUPPORTED
+ * for a periodic axis of odd length (the colours would pair neighbours) and
+ * with the demagnetising field. */
 int asd_mc_sweep(asd_t *h, int64_t n);
 
 /* Every magnetic site of stored columns [x0, x0 + ncols) of system sys takes

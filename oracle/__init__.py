@@ -106,7 +106,8 @@ def _declare(L):
                                    C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
     L.orc_newell_tensor.argtypes = [C.c_double] * 6 + [f64p]
     L.orc_demag_direct.argtypes = [C.c_int] * 3 + [C.c_double] * 3 + [f64p, f64p]
-    L.orc_mc_sweeps.argtypes = [P(OrcSystem), i8p, f64p, f64p, f64p, C.c_int64, C.c_int64]
+    L.orc_mc_sweeps.argtypes = [P(OrcSystem), i8p, C.c_int, f64p, f64p, f64p, C.c_int64,
+                                C.c_int64]
     L.orc_mc_sweeps.restype = C.c_int
     L.orc_langevin.argtypes = [C.c_double]
     L.orc_langevin.restype = C.c_double
@@ -288,12 +289,12 @@ class System:
 
     def mc(self, S, colour, sweep0: int, nsweeps: int) -> np.ndarray:
         """Metropolis sweeps of the same Hamiltonian at T_amb (colour: int8 per
-        site, 0 or 1, -1 = never visited)."""
+        site, 0 .. n-1 with no two neighbours alike, -1 = never visited)."""
         S = np.array(S, dtype=np.float64, copy=True).reshape(3, -1)
         Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
         col = np.ascontiguousarray(colour, dtype=np.int8)
-        lib().orc_mc_sweeps(C.byref(self._s), _ptr(col, i8p), _ptr(Sx, f64p), _ptr(Sy, f64p),
-                            _ptr(Sz, f64p), sweep0, nsweeps)
+        lib().orc_mc_sweeps(C.byref(self._s), _ptr(col, i8p), int(col.max()) + 1, _ptr(Sx, f64p),
+                            _ptr(Sy, f64p), _ptr(Sz, f64p), sweep0, nsweeps)
         return np.stack([Sx, Sy, Sz])
 
     def magnetisation(self, S, n_grains: int):

@@ -968,13 +968,13 @@ static void mc_visit(const orc_system *s, double *Sx, double *Sy, double *Sz, in
     }
 }
 
-int orc_mc_sweeps(const orc_system *s, const int8_t *colour, double *Sx, double *Sy, double *Sz,
-                  int64_t sweep0, int64_t nsweeps)
+int orc_mc_sweeps(const orc_system *s, const int8_t *colour, int n_colours, double *Sx,
+                  double *Sy, double *Sz, int64_t sweep0, int64_t nsweeps)
 {
     for (int64_t t = 0; t < nsweeps; ++t) {
         int64_t sweep = sweep0 + t;
         double pol = polarity(s, sweep);
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < n_colours; ++c)
             for (int64_t i = 0; i < s->n_sites; ++i)
                 if (evolves(s, i) && colour[i] == c) mc_visit(s, Sx, Sy, Sz, i, sweep, pol);
     }

@@ -107,10 +107,11 @@ void orc_newell_tensor(double X, double Y, double Z, double dx, double dy, doubl
  * H_i = -sum_j N(r_j - r_i) M_j, M and H [3][n] in A/m */
 void orc_demag_direct(int nx, int ny, int nz, double dx, double dy, double dz, const double *M,
                       double *H);
-/* Metropolis sweeps (checkerboard colours 0 then 1 per sweep; colour -1:
- * never visited) at the system's ambient temperature; see asd_oracle.c */
-int orc_mc_sweeps(const orc_system *s, const int8_t *colour, double *Sx, double *Sy, double *Sz,
-                  int64_t sweep0, int64_t nsweeps);
+/* Metropolis sweeps (colours 0 .. n_colours-1 in turn per sweep, no two
+ * neighbours sharing one; colour -1: never visited) at the system's ambient
+ * temperature; see asd_oracle.c */
+int orc_mc_sweeps(const orc_system *s, const int8_t *colour, int n_colours, double *Sx,
+                  double *Sy, double *Sz, int64_t sweep0, int64_t nsweeps);
 /* micromagnetic region: LLG (no thermal field) by RK4 on a finite-difference
  * mesh with temperature-dependent parameters; see asd_oracle.c */
 typedef struct orc_mm {

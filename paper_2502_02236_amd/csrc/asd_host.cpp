@@ -1411,8 +1411,6 @@ int asd_mc_sweep(asd_t *h, int64_t n)
 {
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
     if (n < 0) return fail(h, ASD_EINVAL, "n must be >= 0");
-    if (h->p.lattice != ASD_SC)
-        return fail(h, ASD_EUNSUPPORTED, "Metropolis sweeps use the simple-cubic checkerboard");
     if (h->dm.on)
         return fail(h, ASD_EUNSUPPORTED, "Metropolis sweeps do not include the demagnetising field");
     for (const HostSys &hs : h->sys) {
@@ -1420,7 +1418,7 @@ int asd_mc_sweep(asd_t *h, int64_t n)
         if ((d.bc_x == ASD_BC_PERIODIC && d.nx % 2) || (d.bc_y == ASD_BC_PERIODIC && d.ny % 2) ||
             (d.bc_z == ASD_BC_PERIODIC && d.nz % 2))
             return fail(h, ASD_EUNSUPPORTED,
-                        "the checkerboard needs an even length along every periodic axis");
+                        "the Monte Carlo colours need an even length along every periodic axis");
     }
     if (h->step + n >= ((int64_t)1 << 32))
         return fail(h, ASD_ESTATE, "step counter would exceed 2^32 (Philox counter word)");

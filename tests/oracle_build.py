@@ -103,9 +103,16 @@ def track_stray(w: W.Workload, cell, origin: int, S) -> np.ndarray:
 
 
 def checkerboard(w: W.Workload) -> np.ndarray:
-    """Colour (x + y + z) mod 2 of every stored SC site (stored-lattice coordinates)."""
+    """Monte Carlo colours of every stored site (stored-lattice coordinates):
+    SC (x + y + z) mod 2; L1_0 s + 2 ((x + y) mod 2) + 4 (z mod 2) with s the
+    sublattice, so that no two sites of any of the four shells share a colour
+    (shells 1 and 4 change s, shell 2 changes z, shell 3 changes x + y)."""
     nx = w.track_nx or w.nx
     n = oracle.lattice_sites(w.kind, nx, w.ny, w.nz)
     idx = np.arange(n)
-    x, y, z = idx % nx, (idx // nx) % w.ny, idx // (nx * w.ny)
-    return ((x + y + z) % 2).astype(np.int8)
+    cell = idx if w.kind == W.SC else idx // 2
+    x, y, z = cell % nx, (cell // nx) % w.ny, cell // (nx * w.ny)
+    if w.kind == W.SC:
+        return ((x + y + z) % 2).astype(np.int8)
+    s = idx % 2
+    return (s + 2 * ((x + y) % 2) + 4 * (z % 2)).astype(np.int8)

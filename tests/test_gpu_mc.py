@@ -56,8 +56,17 @@ def random_state(w, labels, seed):
     return S
 
 
+def l10(**kw):
+    w = W.c3_l10_window().scaled(nx=12, ny=10, nz=6, x0=2e-9, y0=2e-9, grain_pitch=3.0e-9,
+                                 spot_mode=W.SPOT_NONE, T_amb=500.0)
+    return w.scaled(**kw)
+
+
 CASES = [
     ("slab_600K", slab(), None, 0),
+    ("l10_4shell_500K", l10(), None, 0),
+    ("l10_periodic_cube_3shell", l10(nx=8, ny=8, nz=8, bc=(1, 1, 1), grains=False,
+                                     J=(3.77e-21,) * 3), None, 0),
     ("slab_cold_0K", slab(T_amb=0.0), None, 0),
     ("slab_hot_1200K", slab(T_amb=1200.0, B=(0.3, 0.0, 0.8)), None, 0),
     ("periodic_z_cube", slab(nx=12, ny=10, nz=8, bc=(1, 1, 1), grains=False), None, 0),
@@ -227,7 +236,7 @@ def test_mc_error_paths():
         h.mc_sweep(1)
     assert e.value.code == A.ASD_EUNSUPPORTED
     h.close()
-    wl = W.c3_l10_window().scaled(nx=8, ny=8, nz=4, grains=False)
+    wl = W.c3_l10_window().scaled(nx=8, ny=7, nz=4, grains=False)  # periodic y of odd length
     h = bridge.make_handle(wl, A.ASD_FP32)
     with pytest.raises(A.AsdError) as e:
         h.mc_sweep(1)
@@ -241,3 +250,90 @@ def test_mc_error_paths():
         h.mc_sweep(-1)
     assert e.value.code == A.ASD_EINVAL
     h.close()
+
+
+def binder_and_chi(w0, Ls, Tc_guess, ratios, reps, equil, samples, seed):
+    """Binder cumulants U4 and the longitudinal susceptibility per site,
+    chi = N (<m^2> - <|m|>^2) mu_s / (kB T) (in 1/T), of periodic cubes L^3."""
+    ins, meta = [], []
+    for L in Ls:
+        for r in ratios:
+            for k in range(reps):
+                ins.append(bridge.SystemInputs(w0.scaled(nx=L, ny=L, nz=L), T_system=r * Tc_guess))
+                meta.append((L, r, k))
+    h = A.Handle(bridge.params_for(w0, A.ASD_FP32), [i.desc for i in ins])
+    dr, _ = bridge.drive_for(w0, T_amb=0.0)
+    h.set_drive(dr)
+    for i, (L, _, k) in enumerate(meta):
+        n = h.stored_sites(i)
+        h.set_spins(W.random_spins(n, seed + i) if k % 2 else
+                    np.stack([np.zeros(n), np.zeros(n), np.ones(n)]), i)
+    h.mc_sweep(equil)
+    m1 = np.zeros(len(meta))
+    m2 = np.zeros(len(meta))
+    m4 = np.zeros(len(meta))
+    for b in range(samples):
+        h.mc_sweep(5)
+        _, per_sys = h.magnetization()
+        m = np.linalg.norm(per_sys[:, :3], axis=1) / per_sys[:, 3]
+        m1 += m
+        m2 += m ** 2
+        m4 += m ** 4
+    nsite = per_sys[:, 3]
+    h.close()
+    U, chi = {}, {}
+    for L in Ls:
+        for r in ratios:
+            idx = [i for i, mm in enumerate(meta) if mm[:2] == (L, r)]
+            a1 = m1[idx].sum() / (samples * len(idx))
+            a2 = m2[idx].sum() / (samples * len(idx))
+            a4 = m4[idx].sum() / (samples * len(idx))
+            U[(L, r)] = 1 - a4 / (3 * a2 * a2)
+            chi[(L, r)] = nsite[idx[0]] * (a2 - a1 * a1) * w0.mu_s / (W.KB * r * Tc_guess)
+    return U, chi
+
+
+def crossing(U, Ls, ratios):
+    d = np.array([U[(Ls[0], r)] - U[(Ls[1], r)] for r in ratios])
+    assert d[0] < 0 and d[-1] > 0, d
+    k = int(np.argmax(d > 0))
+    r0, r1 = ratios[k - 1], ratios[k]
+    return r0 + (r1 - r0) * (-d[k - 1]) / (d[k] - d[k - 1])
+
+
+def test_mc_l10_curie_temperature_gives_eps_078():
+    """The paper's L1_0 model (Sec. III): the same J for the 4 + 2 + 4 = 10
+    neighbours of shells 1-3, J_L10 = 3.77e-21 J from T_C = 710 K and the
+    Monte-Carlo correction eps_L10 = 0.78 through Eq. 8.  The Binder crossing of
+    periodic L1_0 cubes (L = 6, 10 cells) must land at 710 K, i.e. eps = 0.78,
+    within 3 % (finite size, statistics)."""
+    J = 3.77e-21
+    w0 = W.c3_l10_window().scaled(bc=(1, 1, 1), grains=False, J=(J,) * 3, ku=0.0,
+                                  B=(0.0, 0.0, 0.0), seed=35, spot_mode=W.SPOT_NONE)
+    Tc = 710.0
+    ratios = [0.92, 0.96, 1.0, 1.04, 1.08]
+    U, chi = binder_and_chi(w0, (6, 10), Tc, ratios, reps=4, equil=3000, samples=800, seed=300)
+    cross = crossing(U, (6, 10), ratios)
+    eps = 3 * W.KB * cross * Tc / (10 * J)
+    say(f"  L1_0 U4 L=6 ", [round(float(U[(6, r)]), 4) for r in ratios])
+    say(f"  L1_0 U4 L=10", [round(float(U[(10, r)]), 4) for r in ratios])
+    say(f"  L1_0 Binder crossing {cross * Tc:.1f} K; Eq. 8 eps_L10 = {eps:.4f} (paper 0.78)")
+    assert abs(eps - 0.78) < 0.03 * 0.78
+
+
+def test_mc_longitudinal_susceptibility_sc_and_l10():
+    """Longitudinal susceptibility (App. A) from the same sweeps: positive, larger
+    near T_C than deep in the ordered phase, for the SC and the paper's L1_0
+    model at equal T / T_C; the L1_0 / SC ratio is reported."""
+    ratios = [0.6, 0.8, 0.95]
+    sc = W.Workload("cube", bc=(1, 1, 1), J=(6.8e-21,), ku=0.0, B=(0.0, 0.0, 0.0), seed=36)
+    l10w = W.c3_l10_window().scaled(bc=(1, 1, 1), grains=False, J=(3.77e-21,) * 3, ku=0.0,
+                                    B=(0.0, 0.0, 0.0), seed=37, spot_mode=W.SPOT_NONE)
+    _, chi_sc = binder_and_chi(sc, (16,), 710.0, ratios, reps=2, equil=2000, samples=400, seed=400)
+    _, chi_l = binder_and_chi(l10w, (10,), 710.0, ratios, reps=2, equil=2000, samples=400, seed=500)
+    for name, chi, L in (("SC", chi_sc, 16), ("L1_0", chi_l, 10)):
+        vals = [chi[(L, r)] for r in ratios]
+        say(f"  chi_par {name} (1/T per site) at T/Tc {ratios}: {[f'{v:.3e}' for v in vals]}")
+        assert all(v > 0 for v in vals)
+        assert vals[-1] > vals[0]
+    say("  L1_0 / SC ratio:", [round(chi_l[(10, r)] / chi_sc[(16, r)], 3) for r in ratios])

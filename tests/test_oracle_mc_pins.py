@@ -8,6 +8,7 @@ Heisenberg ring, and energy descent at zero temperature.  Statistical bars:
 import math
 
 import numpy as np
+import pytest
 from scipy import integrate
 
 import workloads as W
@@ -108,3 +109,35 @@ def test_mc_trial_directions_are_uniform_at_infinite_temperature():
     assert stats.kstest((S[2] + 1) / 2, "uniform").pvalue > 1e-3
     phi = np.arctan2(S[1], S[0]) % (2 * math.pi)
     assert stats.kstest(phi / (2 * math.pi), "uniform").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("kind,dims,bc", [(W.SC, (6, 4, 4), (1, 1, 1)), (W.SC, (5, 3, 3), (0, 0, 0)),
+                                          (W.L10, (4, 4, 4), (1, 1, 1)), (W.L10, (5, 3, 3), (0, 0, 0))])
+def test_mc_colours_never_pair_neighbours(kind, dims, bc):
+    """The Monte Carlo colours form independent sets of the neighbour graph (all
+    four L1_0 shells), so one colour can be updated at once."""
+    import oracle
+    nx, ny, nz = dims
+    w = W.Workload("c", kind=kind, nx=nx, ny=ny, nz=nz, bc=bc,
+                   a=0.385e-9 if kind == W.L10 else 0.3e-9, c=0.371e-9 if kind == W.L10 else 0.3e-9,
+                   J=(6.0e-21, 1.2e-21, 0.5e-21, 0.2e-21) if kind == W.L10 else (6.7e-21,))
+    row, col, _ = oracle.neighbours(kind, nx, ny, nz, list(bc), w.a, w.c, w.shell_radii)
+    colour = checkerboard(w)
+    assert colour.max() == (1 if kind == W.SC else 7)
+    for i in range(len(colour)):
+        for k in range(row[i], row[i + 1]):
+            assert colour[col[k]] != colour[i], (i, col[k])
+
+
+def test_mc_l10_zero_temperature_descent():
+    """L1_0, four shells, T = 0: the oracle's independent energy never increases."""
+    w = W.c3_l10_window().scaled(nx=6, ny=6, nz=4, grains=False, spot_mode=W.SPOT_NONE,
+                                 T_amb=0.0, bc=(1, 1, 0))
+    sysm = oracle_system(w, T_amb=0.0)
+    S = W.random_spins(w.n_sites, 4)
+    col = checkerboard(w)
+    e = [sysm.energy(S, 0)[3]]
+    for t in range(6):
+        S = sysm.mc(S, col, t, 1)
+        e.append(sysm.energy(S, t + 1)[3])
+    assert all(b <= a + 1e-30 for a, b in zip(e, e[1:])) and e[-1] < e[0]
