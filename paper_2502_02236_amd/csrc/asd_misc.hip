@@ -256,47 +256,49 @@ int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, do
 }
 
 // ---------------------------------------------------------------- transfer
-// Eq. 6 read forwards (Sec. II).  A workgroup takes kCgX neighbouring
-// coarse cells along x of one (j, k) layer; thread (tx, tz) sums, for cell
-// tx, the planes tz, tz + kCgZ, ... of the cell (rows in index order, each
-// row's sites contiguous, so neighbouring threads read neighbouring
-// memory), then thread tz = 0 adds the kCgZ partial sums in order: the same
-// FP64 result every run.
+// Eq. 6 read forwards (Sec. II).  A workgroup takes kCgX consecutive coarse
+// cells (i, j) of one layer k, i fastest (neighbouring cells along x, or
+// along y when the columns hold fewer than kCgX cells, as a strip of one
+// coarse column does); thread (tx, tz) sums, for its cell, the lattice rows
+// tz, tz + kCgZ, ... of the cell (rows numbered y fastest, each row's sites
+// contiguous), then thread tz = 0 adds the kCgZ partial sums in order: the
+// same FP64 result every run.  Non-magnetic sites hold S = 0, so only the
+// count looks at the label and the loads of a row do not wait on it.
 constexpr int kCgX = 32, kCgZ = 8;
 
 template <typename T>
 __global__ __launch_bounds__(kCgX * kCgZ) void k_coarse_grain(TransferArgs a)
 {
     const int tx = threadIdx.x % kCgX, tz = threadIdx.x / kCgX;
-    const int i = blockIdx.x * kCgX + tx;
-    const int jk = blockIdx.y;
-    const int j = jk % a.ncy, k = jk / a.ncy;
+    const int ij = blockIdx.x * kCgX + tx;  // cell i + ncx j of layer k
+    const bool live = ij < a.ncx * a.ncy;
+    const int j = ij / a.ncx, i = ij - j * a.ncx, k = blockIdx.y;
+    const int jk = j + a.ncy * k;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < a.ncx) {
+    if (live) {
         const int xb = a.x0 + i * a.cx, yb = j * a.cy, zb = k * a.cz;
         const int wx = min(a.cx, a.x0 + a.ncols - xb), wy = min(a.cy, a.d.ny - yb),
                   wz = min(a.cz, a.d.nz - zb);
         const T *S = (const T *)a.S[0];
         const int nq = a.per * wx;
-        for (int zz = tz; zz < wz; zz += kCgZ)
-            for (int yy = 0; yy < wy; ++yy) {
-                const int64_t row =
-                    a.d.base + a.per * ((int64_t)xb + (int64_t)a.d.sx *
-                                                          ((yb + yy) + (int64_t)a.d.ny * (zb + zz)));
-                for (int q = 0; q < nq; ++q) {
-                    const int64_t g = row + q;
-                    if (a.label[g] == kNoGrain) continue;
-                    acc[0] += (double)S[g];
-                    acc[1] += (double)S[a.ncs + g];
-                    acc[2] += (double)S[2 * a.ncs + g];
-                    acc[3] += 1.0;
-                }
+        for (int r = tz; r < wy * wz; r += kCgZ) {
+            const int zz = r / wy, yy = r - zz * wy;
+            const int64_t row =
+                a.d.base + a.per * ((int64_t)xb + (int64_t)a.d.sx *
+                                                      ((yb + yy) + (int64_t)a.d.ny * (zb + zz)));
+            for (int q = 0; q < nq; ++q) {
+                const int64_t g = row + q;
+                acc[0] += (double)S[g];
+                acc[1] += (double)S[a.ncs + g];
+                acc[2] += (double)S[2 * a.ncs + g];
+                acc[3] += a.label[g] != kNoGrain ? 1.0 : 0.0;
             }
+        }
     }
     __shared__ double red[4][kCgZ][kCgX];
     for (int m = 0; m < 4; ++m) red[m][tz][tx] = acc[m];
     __syncthreads();
-    if (tz == 0 && i < a.ncx) {
+    if (tz == 0 && live) {
         const int64_t c = i + (int64_t)a.ncx * jk;
         for (int m = 0; m < 4; ++m) {
             double t = red[m][0][tx];
@@ -310,7 +312,7 @@ int launch_coarse_grain(const TransferArgs &a, void *stream)
 {
     if (a.ncell == 0) return 0;
     const int ncz = a.ncell / (a.ncx * a.ncy);
-    const dim3 grid((a.ncx + kCgX - 1) / kCgX, a.ncy * ncz);
+    const dim3 grid((a.ncx * a.ncy + kCgX - 1) / kCgX, ncz);
     if (a.prec == ASD_FP64)
         hipLaunchKernelGGL(k_coarse_grain<double>, grid, dim3(kCgX * kCgZ), 0, (hipStream_t)stream,
                            a);
