@@ -8,7 +8,8 @@ the oracle sums Eq. 7 directly.  Bars:
     falls like R^-3, so two correct evaluations in a different order differ by
     ~27 eps (R/d)^3 / 4 pi per entry: ~1e-14 at the R <= 10 cells of these
     meshes, summed over at most a few hundred cells.  FP32: the cell sums
-    and log2(P) radix-2 stages each round at ~6e-8 relative.
+    and the FFT stages (radix 4, one radix-2 stage for odd log2 P) each round
+    at ~6e-8 relative.
   * spins after Heun steps with the field: the FP64 and FP32 bars of the
     other parity tests (1e-12, 1e-4 per component).
 """
