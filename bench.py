@@ -13,10 +13,10 @@ each at its own temperature, moment statistics every 10 steps), track
 per-grain anisotropy spread and bit-timed write field).
 
 Prints one JSON line: spin-updates/s (magnetic sites x steps / s) with the
-roofline of the dominant kernel (algorithmic VALU work or bytes per launch /
-its average duration from HIP events on the handle's stream; the FP32 path is
-bound by VALU issue and reports the HBM fraction beside it) and the FP64 CPU
-oracle timed on a bounded sample.
+roofline of the dominant kernel (algorithmic bytes or VALU work per launch / its
+average duration from HIP events on the handle's stream; the bound is whichever
+of the two takes longer at its peak, and the other is reported beside it) and
+the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -32,9 +32,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one non-packed FP32
-# or INT32 operation per lane per cycle (quarter-rate transcendentals take 4)
-VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
+# VALU issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz non-packed FP32 FMAs
+# per second (the published 157.3 TFLOP/s FP32 vector peak, two flops per FMA).
+# An FP32 add, multiply or 32-bit integer operation costs one such slot; the
+# other classes the step uses are weighed by their issue cost relative to the
+# FMA, as measured by `bench.py --issue-rates` on the MI355X:
+VALU_PEAK_T = 256 * 4 * 32 * 2.4e9 / 1e12
+W_PRODUCT = 1.56  # v_mad_u64_u32: the 32 x 32 -> 64 product of a Philox round
+W_TRANS = 2.75    # v_log_f32, v_rsq_f32 (and the other transcendentals)
 
 
 def parse():
@@ -55,7 +60,41 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto ~15 s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of known size (HBM counter calibration)")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only measure the VALU issue cost of the instruction classes the "
+                         "cost model weighs, and print them")
     return ap.parse_args()
+
+
+def issue_rates():
+    """SIMD cycles per wave64 instruction of each calibrated class (independent
+    chains, 32 waves per SIMD, nominal 2.4 GHz clock), and its weight relative
+    to a non-packed FP32 FMA."""
+    import ctypes
+
+    import torch
+    from paper_2502_02236_amd import build as B
+    if not os.path.exists(B.RATE_LIB):
+        raise RuntimeError(f"{B.RATE_LIB} is not built")
+    lib = ctypes.CDLL(B.RATE_LIB)
+    lib.issue_rate_name.restype = ctypes.c_char_p
+    lib.issue_rate_time.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_float)]
+    blocks, iters, simds = 256 * 32, 4096, 256 * 4
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    waves = blocks * 256 / 64
+    res = {}
+    for k in range(lib.issue_rate_classes()):
+        ms = ctypes.c_float()
+        rc = lib.issue_rate_time(k, ctypes.c_void_p(out.data_ptr()), blocks, iters, ctypes.byref(ms))
+        if rc:
+            raise RuntimeError(f"issue_rate_time({k}) returned {rc}")
+        instr = waves * iters * lib.issue_rate_chains()
+        res[lib.issue_rate_name(k).decode()] = ms.value * 1e-3 * 2.4e9 * simds / instr
+    base = res["v_fma_f32"]
+    return {name: {"cycles_per_wave64_instruction": c, "fma_f32_equivalents": c / base}
+            for name, c in res.items()}
 
 
 def bytes_per_site(precision: str, workload: str, kernel_name: str) -> int:
@@ -71,17 +110,20 @@ def bytes_per_site(precision: str, workload: str, kernel_name: str) -> int:
     return b
 
 
-def alu_cycles_per_site(precision: str, workload: str):
-    """Algorithmic VALU lane-cycles per magnetic site and Heun step of the FP32
-    path (nothing recomputed, no halo): Philox4x32-10 40 (20 64-bit products, 20
-    three-way xors), uniforms 8, Box-Muller radii 6 and angles 3, scaling 3;
-    per stage exchange 18 (SC) or 54 (L1_0, four shells), field assembly 4 (+3
-    once), LL right-hand side 18; predictor update 10, corrector update 13.
-    166 operations of which 9 transcendental (4 cycles each): 193 for SC, 265
-    for L1_0.  None for FP64 (software transcendentals; reported against HBM)."""
+def alu_ops_per_site(precision: str, workload: str):
+    """Algorithmic VALU work per magnetic site and Heun step of the FP32 path
+    (nothing recomputed, no halo), in FP32-FMA issue slots.  Operations:
+    Philox4x32-10 40 (20 32 x 32 -> 64 products, 20 three-way xors), uniforms
+    8, Box-Muller radii 6 and angles 3, scaling 3; per stage exchange 18 (SC) or
+    54 (L1_0, four shells), field assembly 4 (+3 once), LL right-hand side 18;
+    predictor update 10, corrector update 13: 166 operations for SC (238 for
+    L1_0), of which 20 products (weight W_PRODUCT) and 9 transcendentals
+    (weight W_TRANS): 192.95 slots for SC, 264.95 for L1_0.  None for FP64
+    (software transcendentals; reported against HBM)."""
     if precision != "fp32":
         return None
-    return 265 if workload == "l10" else 193
+    ops = 166 + (2 * (54 - 18) if workload == "l10" else 0)
+    return round(ops - 20 - 9 + 20 * W_PRODUCT + 9 * W_TRANS, 6)
 
 
 def kernel_sources_hash():
@@ -391,17 +433,19 @@ def multiscale_run(args):
     return dict(t=t, n_atoms=n_atoms, n_cells=2 * 84 * 50 * 11, kernel=kname, name=w.name)
 
 
-MC_ALU_CYCLES = 101
+# 89 operations: 20 products, 4 transcendentals, 65 others
+MC_ALU_OPS = round(65 + 20 * W_PRODUCT + 4 * W_TRANS, 6)
 
 
 def mc_run(args):
     """Metropolis sweeps of the 200x200x33 granular slab at its 300 K ambient
     temperature (the exchange calibration of Sec. III with Eq. 8), timed with HIP
-    events on the handle's stream.  Algorithmic VALU lane-cycles per visited
-    magnetic site: Philox4x32-10 40, uniforms 6, trial S_z and radius 6 (one
-    square root), azimuth sine and cosine 10, exchange sum and scale 18, local
-    field 3, energy change 11, Boltzmann factor and test 7 (the four
-    transcendentals count 4 each): 101."""
+    events on the handle's stream.  Algorithmic VALU operations per visited
+    magnetic site: Philox4x32-10 40 (20 products), uniforms 6, trial S_z and
+    radius 2 + a square root, azimuth sine and cosine 2 + 2 transcendentals,
+    exchange sum and scale 18, local field 3, energy change 11, Boltzmann factor
+    and test 3 + an exponential: 89, weighed as in alu_ops_per_site: 107.2
+    FP32-FMA slots."""
     import torch
     from paper_2502_02236_amd import asd as A
 
@@ -453,6 +497,11 @@ def main():
                                    "library drives a single device, and runs over several "
                                    "GPUs are not provided"}))
         sys.exit(2)
+    if args.issue_rates:
+        r = issue_rates()
+        print(json.dumps({"metric": "VALU issue cost per wave64 instruction", "unit": "SIMD cycles",
+                          "clock_ghz": 2.4, "classes": r}), flush=True)
+        return
     if args.workload == "transfer":
         t = transfer_run(args)
         cg, th = t["res"]["coarse_grain"], t["res"]["thermalise"]
@@ -507,7 +556,8 @@ def main():
             "config": {"workload": "mm_window300x60x8_cells1x1x2nm_spot800K_locked",
                        "cells": r["n"], "dt_fs": 20.0, "precision": args.precision},
             "roofline": {"bound": "alu", "achieved": alu, "peak": peak,
-                         "unit": "T VALU lane-ops/s", "frac": alu / peak,
+                         "unit": "T FP32-FMA slots/s" if args.precision == "fp32"
+                         else "T FP64-FMA slots/s", "frac": alu / peak,
                          "alu_ops_per_cell_step": 4 * MM_ALU_PER_STAGE,
                          "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": hbm / HBM_PEAK_GBS, "bytes_per_cell": 6 * e},
@@ -519,16 +569,18 @@ def main():
         per_sweep = r["t"] / args.steps
         e = 4 if args.precision == "fp32" else 8
         hbm = 2 * 3 * e * r["n_sites"] / per_sweep / 1e9
+        roof = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm / HBM_PEAK_GBS, "bytes_per_site": 6 * e}
         if args.precision == "fp32":
-            ach = MC_ALU_CYCLES * r["n_mag"] / per_sweep / 1e12
-            roof = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_T,
-                    "unit": "T VALU lane-cycles/s", "frac": ach / VALU_PEAK_T,
-                    "alu_cycles_per_magnetic_site": MC_ALU_CYCLES,
-                    "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": hbm / HBM_PEAK_GBS, "bytes_per_site": 6 * e}}
-        else:
-            roof = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": hbm / HBM_PEAK_GBS, "bytes_per_site": 6 * e}
+            ach = MC_ALU_OPS * r["n_mag"] / per_sweep / 1e12
+            alu = {"achieved": ach, "peak": VALU_PEAK_T, "unit": "T FP32-FMA slots/s",
+                   "frac": ach / VALU_PEAK_T, "alu_ops_per_magnetic_site": MC_ALU_OPS}
+            if ach / VALU_PEAK_T > hbm / HBM_PEAK_GBS:  # the longer of the two at peak
+                roof = dict(bound="alu", **alu)
+                roof["hbm"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": hbm / HBM_PEAK_GBS, "bytes_per_site": 6 * e}
+            else:
+                roof["alu"] = alu
         roof.update({"traffic": None, "kernel": "k_mc_colour (two launches per sweep)"})
         print(json.dumps({
             "metric": "Metropolis spin-updates/s (magnetic sites x sweeps)",
@@ -580,18 +632,23 @@ def main():
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
            "algorithmic_bytes_per_launch": alg_bytes}
-    cyc = alu_cycles_per_site(args.precision, args.workload)
+    cyc = alu_ops_per_site(args.precision, args.workload)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
+            "algorithmic_bytes_per_launch": alg_bytes}
     if cyc is not None:
-        # the kernel is bound by VALU issue, not by HBM: report that roofline,
-        # with the HBM fraction beside it
-        alu_ach = cyc * r["n_mag"] / launch_s / 1e12
-        roof = {"bound": "alu", "achieved": alu_ach, "peak": VALU_PEAK_T,
-                "unit": "T VALU lane-cycles/s", "frac": alu_ach / VALU_PEAK_T,
-                "alu_cycles_per_magnetic_site": cyc, "hbm": hbm}
-    else:
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
-                "algorithmic_bytes_per_launch": alg_bytes}
+        # the bound is whichever of the algorithmic HBM bytes and VALU work takes
+        # longer at its peak; the other roofline is reported beside it
+        alu_ops = cyc * r["n_mag"]
+        alu_ach = alu_ops / launch_s / 1e12
+        alu = {"achieved": alu_ach, "peak": VALU_PEAK_T, "unit": "T FP32-FMA slots/s",
+               "frac": alu_ach / VALU_PEAK_T, "alu_ops_per_magnetic_site": cyc,
+               "alu_ops_per_launch": alu_ops}
+        if alu_ops / (VALU_PEAK_T * 1e12) > alg_bytes / (HBM_PEAK_GBS * 1e9):
+            roof = dict(bound="alu", **alu)
+            roof["hbm"] = hbm
+        else:
+            roof["alu"] = alu
     roof.update({"traffic": traffic, "traffic_source": traffic_src, "kernel": r["kname"],
                  "launch_us_mean": 1e6 * launch_s,
                  "launch_us_eager_events_median": 1e6 * r["step_med"]})

@@ -1,4 +1,6 @@
-"""Build libasd.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc.
+"""Build libasd.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc, and
+libissue_rate.so, the benchmark's VALU issue-rate calibration (not part of the
+step library).
 
 Usage: python -m paper_2502_02236_amd.build   (or paper_2502_02236_amd.build.build())
 """
@@ -16,6 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libasd.so")
+RATE_LIB = os.path.join(PKG, "libissue_rate.so")
+RATE_SOURCE = ("issue_rate.hip", ["-ffp-contract=fast"])
 ARCH = os.environ.get("ASD_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
@@ -52,19 +56,25 @@ def _compile(src: str, flags: list) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link libasd.so next to this file."""
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda sf: _compile(*sf), SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs: list, lib: str) -> None:
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source for gfx950 and link libasd.so (and the issue-rate
+    calibration library) next to this file."""
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        objs = list(ex.map(lambda sf: _compile(*sf), SOURCES + [RATE_SOURCE]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], RATE_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {RATE_LIB}")
     return LIB
 
 

@@ -16,14 +16,36 @@ def test_bench_refuses_more_than_one_gpu():
 
 
 def test_alu_work_count():
-    """The per-site VALU count adds up from its parts (see the docstring)."""
+    """The per-site VALU count adds up from its parts (see the docstring), and
+    the peak is the published FP32 vector rate in FMAs."""
     sys.path.insert(0, ROOT)
     import bench
     thermal = 40 + 8 + 6 + 3 + 3
     stage = lambda exch: exch + 4 + 18
     ops = thermal + 3 + stage(18) * 2 + 10 + 13
     assert ops == 166
-    assert bench.alu_cycles_per_site("fp32", "slab") == ops - 9 + 9 * 4
-    assert bench.alu_cycles_per_site("fp32", "l10") == ops + 2 * (54 - 18) - 9 + 9 * 4
-    assert bench.alu_cycles_per_site("fp64", "slab") is None
-    assert abs(bench.VALU_PEAK_T - 39.3216) < 1e-9
+    weigh = lambda n: n - 20 - 9 + 20 * bench.W_PRODUCT + 9 * bench.W_TRANS
+    assert abs(bench.alu_ops_per_site("fp32", "slab") - weigh(ops)) < 1e-9
+    assert abs(bench.alu_ops_per_site("fp32", "l10") - weigh(ops + 2 * (54 - 18))) < 1e-9
+    assert bench.alu_ops_per_site("fp64", "slab") is None
+    assert abs(bench.VALU_PEAK_T - 157.2864 / 2) < 1e-9
+    mc = 40 + 6 + (2 + 1) + (2 + 2) + 18 + 3 + 11 + (3 + 1)
+    assert mc == 89 and abs(bench.MC_ALU_OPS - (mc - 20 - 4 + 20 * bench.W_PRODUCT
+                                                 + 4 * bench.W_TRANS)) < 1e-9
+
+
+def test_issue_rate_calibration_library_loads():
+    """The benchmark's VALU issue-rate calibration is its own library (never
+    linked into the step library); it loads and names its classes without a GPU."""
+    import ctypes
+    sys.path.insert(0, ROOT)
+    from paper_2502_02236_amd import build as B
+    lib = ctypes.CDLL(B.RATE_LIB)
+    lib.issue_rate_name.restype = ctypes.c_char_p
+    names = [lib.issue_rate_name(k).decode() for k in range(lib.issue_rate_classes())]
+    assert names[0] == "v_fma_f32" and "v_mad_u64_u32" in names and "v_log_f32" in names
+    assert lib.issue_rate_name(len(names)) is None and lib.issue_rate_chains() == 8
+    f = ctypes.c_float()
+    assert lib.issue_rate_time(-1, None, 1, 1, ctypes.byref(f)) == -1
+    from paper_2502_02236_amd import asd as A
+    assert not hasattr(A.lib(), "issue_rate_time")
