@@ -55,7 +55,7 @@ extern "C" {
 #define ASD_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
 #define ASD_ESTATE (-4)       /* call not valid in the handle's state */
 #define ASD_ENONFINITE (-5)   /* a reduction met a non-finite spin */
-#define ASD_EUNSUPPORTED (-6) /* valid request this build cannot serve */
+#define ASD_EUNSUPPORTED (-6) /* valid request this library cannot serve */
 
 /* ---- enumerations ---- */
 #define ASD_FP64 0 /* every per-spin quantity in FP64 */
