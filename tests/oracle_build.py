@@ -21,13 +21,21 @@ def oracle_labels(w: W.Workload, seeds=None, nx_extent=None) -> np.ndarray:
     return oracle.voronoi_labels(w.kind, nx, w.ny, w.nz, per, W.Q_UNITS, seeds, w.w_units)
 
 
-def oracle_system(w: W.Workload, labels=None, ku_grain=None, sys_id=0, active=None, origin=0,
-                  T_amb=None) -> oracle.System:
-    """Oracle system over the full stored lattice (track length when x is a track)."""
+def oracle_geometry(w: W.Workload):
+    """The oracle's neighbour shells and site positions of the stored lattice:
+    ((row_ptr, col, shell), (px, py)); they depend on the geometry only, so
+    callers may reuse them for every system of one lattice."""
     nx = w.track_nx or w.nx
     per = [int(b == W.BC_PERIODIC) for b in w.bc]
-    row, col, sh = oracle.neighbours(w.kind, nx, w.ny, w.nz, per, w.a, w.c, w.shell_radii)
-    px, py = oracle.site_positions(w.kind, nx, w.ny, w.nz, w.a)
+    return (oracle.neighbours(w.kind, nx, w.ny, w.nz, per, w.a, w.c, w.shell_radii),
+            oracle.site_positions(w.kind, nx, w.ny, w.nz, w.a))
+
+
+def oracle_system(w: W.Workload, labels=None, ku_grain=None, sys_id=0, active=None, origin=0,
+                  T_amb=None, geometry=None) -> oracle.System:
+    """Oracle system over the full stored lattice (track length when x is a track);
+    `geometry`: oracle_geometry(w), when already built."""
+    (row, col, sh), (px, py) = geometry if geometry is not None else oracle_geometry(w)
     if labels is None:
         labels = oracle_labels(w)
     n = len(labels)
