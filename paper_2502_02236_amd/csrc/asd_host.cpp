@@ -15,6 +15,7 @@
 
 #include "asd.h"
 #include "asd_internal.h"
+#include "asd_pair.h"
 #include "asd_variants.h"
 
 using namespace asd;
@@ -1467,6 +1468,38 @@ int asd_set_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32_t cx, 
     h->stray_dirty = true;
     return ASD_OK;
 }
+
+namespace asd {
+
+int coarse_grain_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols, int32_t cx,
+                      int32_t cy, int32_t cz, double *outa, double *outb)
+{
+    TransferArgs a, b;
+    int rc = transfer_args(h, s, xa, ncols, cx, cy, cz, &a);
+    if (rc || (rc = transfer_args(h, s, xb, ncols, cx, cy, cz, &b))) return rc;
+    if (!outa || !outb) return fail(h, ASD_EINVAL, "NULL output");
+    a.out = outa;
+    b.out = outb;
+    if (launch_coarse_grain_pair(a, b, h->stream)) return fail(h, ASD_EHIP, "coarse-grain launch failed");
+    return ASD_OK;
+}
+
+int set_columns_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols, int32_t cx,
+                     int32_t cy, int32_t cz, const double *ma, const double *mb)
+{
+    TransferArgs a, b;
+    int rc = transfer_args(h, s, xa, ncols, cx, cy, cz, &a);
+    if (rc || (rc = transfer_args(h, s, xb, ncols, cx, cy, cz, &b))) return rc;
+    if (!ma || !mb) return fail(h, ASD_EINVAL, "NULL cell direction");
+    a.mcell = ma;
+    b.mcell = mb;
+    a.exact = b.exact = 1;
+    if (launch_cone_columns_pair(a, b, h->stream)) return fail(h, ASD_EHIP, "column launch failed");
+    h->stray_dirty = true;
+    return ASD_OK;
+}
+
+}  // namespace asd
 
 int asd_window_size(asd_t *h, int32_t s, int32_t *nx, int32_t *ny, int32_t *nz)
 {

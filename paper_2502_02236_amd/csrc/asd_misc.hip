@@ -4,6 +4,7 @@
 #include "asd_device.h"
 #include "asd_internal.h"
 #include "asd.h"
+#include "asd_pair.h"
 
 namespace asd {
 
@@ -267,12 +268,12 @@ int launch_energy_finish(const double *partial, const SysDev *sys, int n_sys, do
 constexpr int kCgX = 32, kCgZ = 8;
 
 template <typename T>
-__global__ __launch_bounds__(kCgX * kCgZ) void k_coarse_grain(TransferArgs a)
+__device__ __forceinline__ void coarse_grain_block(const TransferArgs &a, int bx, int by)
 {
     const int tx = threadIdx.x % kCgX, tz = threadIdx.x / kCgX;
-    const int ij = blockIdx.x * kCgX + tx;  // cell i + ncx j of layer k
+    const int ij = bx * kCgX + tx;  // cell i + ncx j of layer k
     const bool live = ij < a.ncx * a.ncy;
-    const int j = ij / a.ncx, i = ij - j * a.ncx, k = blockIdx.y;
+    const int j = ij / a.ncx, i = ij - j * a.ncx, k = by;
     const int jk = j + a.ncy * k;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (live) {
@@ -308,6 +309,39 @@ __global__ __launch_bounds__(kCgX * kCgZ) void k_coarse_grain(TransferArgs a)
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kCgX * kCgZ) void k_coarse_grain(TransferArgs a)
+{
+    coarse_grain_block<T>(a, blockIdx.x, blockIdx.y);
+}
+
+// two strips of the same shape in one launch: blocks [0, gx) of a layer take
+// strip a0, the others strip a1
+template <typename T>
+__global__ __launch_bounds__(kCgX * kCgZ) void k_coarse_grain_pair(TransferArgs a0, TransferArgs a1,
+                                                                   int gx)
+{
+    if ((int)blockIdx.x < gx)
+        coarse_grain_block<T>(a0, blockIdx.x, blockIdx.y);
+    else
+        coarse_grain_block<T>(a1, blockIdx.x - gx, blockIdx.y);
+}
+
+int launch_coarse_grain_pair(const TransferArgs &a0, const TransferArgs &a1, void *stream)
+{
+    if (a0.ncx != a1.ncx || a0.ncy != a1.ncy || a0.ncell != a1.ncell || a0.prec != a1.prec) return -1;
+    if (a0.ncell == 0) return 0;
+    const int gx = (a0.ncx * a0.ncy + kCgX - 1) / kCgX;
+    const dim3 grid(2 * gx, a0.ncell / (a0.ncx * a0.ncy));
+    if (a0.prec == ASD_FP64)
+        hipLaunchKernelGGL(k_coarse_grain_pair<double>, grid, dim3(kCgX * kCgZ), 0,
+                           (hipStream_t)stream, a0, a1, gx);
+    else
+        hipLaunchKernelGGL(k_coarse_grain_pair<float>, grid, dim3(kCgX * kCgZ), 0,
+                           (hipStream_t)stream, a0, a1, gx);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_coarse_grain(const TransferArgs &a, void *stream)
 {
     if (a.ncell == 0) return 0;
@@ -339,10 +373,9 @@ __device__ __forceinline__ double cone_theta_max(double m)
 // orthonormal basis of Duff et al. (JCGT 2017) around the cell direction.
 // FP64 throughout; both spin buffers receive the result.
 template <typename T>
-__global__ void k_cone_columns(TransferArgs a)
+__device__ __forceinline__ void cone_column_site(const TransferArgs &a, int64_t t)
 {
     const int64_t n = (int64_t)a.per * a.ncols * a.d.ny * a.d.nz;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int s = (int)(t % a.per);
     int64_t r = t / a.per;
@@ -398,6 +431,38 @@ __global__ void k_cone_columns(TransferArgs a)
         S[a.ncs + g] = (T)vy;
         S[2 * a.ncs + g] = (T)vz;
     }
+}
+
+template <typename T>
+__global__ void k_cone_columns(TransferArgs a)
+{
+    cone_column_site<T>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// two strips of the same shape in one launch: blocks [0, b0) take strip a0
+template <typename T>
+__global__ void k_cone_columns_pair(TransferArgs a0, TransferArgs a1, int b0)
+{
+    if ((int)blockIdx.x < b0)
+        cone_column_site<T>(a0, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    else
+        cone_column_site<T>(a1, (int64_t)(blockIdx.x - b0) * blockDim.x + threadIdx.x);
+}
+
+int launch_cone_columns_pair(const TransferArgs &a0, const TransferArgs &a1, void *stream)
+{
+    const int64_t n = (int64_t)a0.per * a0.ncols * a0.d.ny * a0.d.nz;
+    if (n != (int64_t)a1.per * a1.ncols * a1.d.ny * a1.d.nz || a0.prec != a1.prec) return -1;
+    if (n == 0) return 0;
+    const int64_t b0 = (n + 255) / 256;
+    if (2 * b0 > INT32_MAX) return -1;
+    if (a0.prec == ASD_FP64)
+        hipLaunchKernelGGL(k_cone_columns_pair<double>, dim3((unsigned)(2 * b0)), dim3(256), 0,
+                           (hipStream_t)stream, a0, a1, (int)b0);
+    else
+        hipLaunchKernelGGL(k_cone_columns_pair<float>, dim3((unsigned)(2 * b0)), dim3(256), 0,
+                           (hipStream_t)stream, a0, a1, (int)b0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_cone_columns(const TransferArgs &a, void *stream)

@@ -30,6 +30,7 @@
 
 #include "asd.h"
 #include "asd_device.h"
+#include "asd_pair.h"
 
 namespace asd {
 namespace {
@@ -131,9 +132,8 @@ __device__ __forceinline__ int64_t mm_nb(const MMArgs &a, int i, int j, int k, i
 // stage s: k_s from the stage input (m for s = 0, else the buffer the
 // previous stage wrote); s < 3 writes the next input, s = 3 the new m
 template <typename T>
-__global__ __launch_bounds__(kMMTile) void k_mm_stage(MMArgs a, int s)
+__device__ __forceinline__ void mm_stage_cell(const MMArgs &a, int s, int c)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n) return;
     const int64_t n = a.n;
     const int i = c % a.nx, j = (c / a.nx) % a.ny, k = c / (a.nx * a.ny);
@@ -205,6 +205,25 @@ __global__ __launch_bounds__(kMMTile) void k_mm_stage(MMArgs a, int s)
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kMMTile) void k_mm_stage(MMArgs a, int s)
+{
+    mm_stage_cell<T>(a, s, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// stage s of two regions in one launch: blocks [0, blocks0) take region a0,
+// the rest region a1 (the regions share nothing, so the results equal those
+// of one launch per region)
+template <typename T>
+__global__ __launch_bounds__(kMMTile) void k_mm_stage_pair(MMArgs a0, MMArgs a1, int s, int blocks0)
+{
+    const int b = blockIdx.x;
+    if (b < blocks0)
+        mm_stage_cell<T>(a0, s, b * kMMTile + threadIdx.x);
+    else
+        mm_stage_cell<T>(a1, s, (b - blocks0) * kMMTile + threadIdx.x);
+}
+
 // face neighbours from vectors (normalised; zero stays zero)
 __global__ void k_mm_set_face(double *ghost, const double *vec, int stride, int nyz)
 {
@@ -218,20 +237,63 @@ __global__ void k_mm_set_face(double *ghost, const double *vec, int stride, int 
     ghost[3 * c + 2] = r > 0.0 ? z / r : 0.0;
 }
 
+// both regions' faces in one launch: threads [0, nyz) take g0/v0, the next
+// nyz take g1/v1
+__global__ void k_mm_set_face_pair(double *g0, const double *v0, double *g1, const double *v1,
+                                   int stride, int nyz)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * nyz) return;
+    const bool second = t >= nyz;
+    const int c = second ? t - nyz : t;
+    const double *vec = second ? v1 : v0;
+    double *ghost = second ? g1 : g0;
+    const double x = vec[(int64_t)c * stride], y = vec[(int64_t)c * stride + 1],
+                 z = vec[(int64_t)c * stride + 2];
+    const double r = sqrt((x * x + y * y) + z * z);
+    ghost[3 * c] = r > 0.0 ? x / r : 0.0;
+    ghost[3 * c + 1] = r > 0.0 ? y / r : 0.0;
+    ghost[3 * c + 2] = r > 0.0 ? z / r : 0.0;
+}
+
 // directions of the cells of x face `face`
 template <typename T>
-__global__ void k_mm_get_face(MMArgs a, int face, double *dirs)
+__device__ __forceinline__ void mm_face_cell(const MMArgs &a, int face, double *dirs, int c)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ny * a.nz) return;
     const int64_t cell = (face == 0 ? 0 : a.nx - 1) + (int64_t)a.nx * c;
     const T *m = (const T *)a.m;
     for (int d = 0; d < 3; ++d) dirs[3 * c + d] = (double)m[d * (int64_t)a.n + cell];
 }
 
+template <typename T>
+__global__ void k_mm_get_face(MMArgs a, int face, double *dirs)
+{
+    mm_face_cell<T>(a, face, dirs, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// two regions' faces in one launch: blocks [0, b0) take region a0
+template <typename T>
+__global__ void k_mm_get_face_pair(MMArgs a0, int f0, double *d0, MMArgs a1, int f1, double *d1,
+                                   int b0)
+{
+    if ((int)blockIdx.x < b0)
+        mm_face_cell<T>(a0, f0, d0, blockIdx.x * blockDim.x + threadIdx.x);
+    else
+        mm_face_cell<T>(a1, f1, d1, (blockIdx.x - b0) * blockDim.x + threadIdx.x);
+}
+
 __global__ void k_mm_advance(int64_t *step, int64_t n)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *step += n;
+}
+
+__global__ void k_mm_advance_pair(int64_t *step0, int64_t *step1, int64_t n)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *step0 += n;
+        *step1 += n;
+    }
 }
 
 size_t align_up(size_t v) { return (v + kMMAlign - 1) / kMMAlign * kMMAlign; }
@@ -598,6 +660,36 @@ int asd_mm_get_face(asd_mm_t *h, int32_t face, double *dirs)
     return ASD_OK;
 }
 
+// one RK4 step of two regions on one stream (same precision, spots that do
+// not move): the launches of asd_mm_step(h, 1) for both, with the stages of
+// the two merged into one launch each
+static int mm_step_pair(asd_mm_t *L, asd_mm_t *R)
+{
+    asd_mm_t *r[2] = {L, R};
+    for (asd_mm_t *h : r)
+        if (!h->params_valid) {
+            const MMArgs a = mm_args(h, 0);
+            hipLaunchKernelGGL(k_mm_params, dim3((unsigned)((h->n + kMMTile - 1) / kMMTile)),
+                               dim3(kMMTile), 0, h->stream, a, 0.0);
+            h->params_valid = true;
+        }
+    const MMArgs a0 = mm_args(L, 0), a1 = mm_args(R, 0);
+    const int b0 = (int)((L->n + kMMTile - 1) / kMMTile), b1 = (int)((R->n + kMMTile - 1) / kMMTile);
+    const dim3 grid((unsigned)(b0 + b1)), blk(kMMTile);
+    for (int s = 0; s < 4; ++s) {
+        if (L->elem == 8)
+            hipLaunchKernelGGL(k_mm_stage_pair<double>, grid, blk, 0, L->stream, a0, a1, s, b0);
+        else
+            hipLaunchKernelGGL(k_mm_stage_pair<float>, grid, blk, 0, L->stream, a0, a1, s, b0);
+    }
+    hipLaunchKernelGGL(k_mm_advance_pair, dim3(1), dim3(1), 0, L->stream,
+                       (int64_t *)(L->ws + L->off_step), (int64_t *)(R->ws + R->off_step), (int64_t)1);
+    MM_HIP(L, hipGetLastError());
+    L->step += 1;
+    R->step += 1;
+    return ASD_OK;
+}
+
 int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
                         int32_t cy, int32_t cz, int64_t n)
 {
@@ -621,6 +713,47 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
         if (m->p.bc_x == ASD_BC_PERIODIC) return mm_fail(m, ASD_EINVAL, "region x axis is periodic");
     }
     if (nx < cx || org < cx) return mm_fail(nullptr, ASD_EINVAL, "window too narrow or too close to the track start");
+    // both regions in the same precision under a spot that does not move: one
+    // launch per RK4 stage for the two
+    const bool pair = left && right && left->elem == right->elem &&
+                      left->drive.spot_mode != ASD_SPOT_MOVING &&
+                      right->drive.spot_mode != ASD_SPOT_MOVING;
+    if (pair && n > 0) {
+        // the window's two boundary strips, the regions' facing faces and the
+        // frozen columns beside the window: one launch for both sides each
+        const int nyz = left->p.ny * left->p.nz;
+        double *sumL = (double *)(left->ws + left->off_fsum), *sumR = (double *)(right->ws + right->off_fsum);
+        double *dirL = (double *)(left->ws + left->off_fdir), *dirR = (double *)(right->ws + right->off_fdir);
+        for (int f = 0; f < 2; ++f) {
+            asd_mm_t *m = f == 0 ? left : right;
+            const int face = f == 0 ? 1 : 0;
+            if (!m->ghost_on[face]) {
+                m->ghost_on[face] = true;
+                mm_drop_graph(m);  // graphs bake the face pointers in
+            }
+        }
+        const MMArgs aL = mm_args(left, 0), aR = mm_args(right, 0);
+        const int bf = (nyz + 255) / 256;
+        for (int64_t t = 0; t < n; ++t) {
+            if ((rc = coarse_grain_pair(atoms, sys, org, org + nx - cx, cx, cx, cy, cz, sumL, sumR)))
+                return rc;
+            hipLaunchKernelGGL(k_mm_set_face_pair, dim3((unsigned)(2 * bf)), dim3(256), 0, left->stream,
+                               (double *)(left->ws + left->off_ghost[1]), sumL,
+                               (double *)(right->ws + right->off_ghost[0]), sumR, 4, nyz);
+            if (left->elem == 8)
+                hipLaunchKernelGGL(k_mm_get_face_pair<double>, dim3((unsigned)(2 * bf)), dim3(256), 0,
+                                   left->stream, aL, 1, dirL, aR, 0, dirR, bf);
+            else
+                hipLaunchKernelGGL(k_mm_get_face_pair<float>, dim3((unsigned)(2 * bf)), dim3(256), 0,
+                                   left->stream, aL, 1, dirL, aR, 0, dirR, bf);
+            MM_HIP(left, hipGetLastError());
+            if ((rc = set_columns_pair(atoms, sys, org - cx, org + nx, cx, cx, cy, cz, dirL, dirR)))
+                return rc;
+            if ((rc = asd_step(atoms, 1))) return rc;
+            if ((rc = mm_step_pair(left, right))) return rc;
+        }
+        return ASD_OK;
+    }
     for (int64_t t = 0; t < n; ++t) {
         // window -> regions: averaged boundary coarse columns
         if (left) {

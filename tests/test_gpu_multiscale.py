@@ -5,7 +5,8 @@ either side of the atomistic window, exchange-coupled through their faces
 Bars: FP64 within 1e-12 per component of the atomistic spins and of both
 regions after 30 coupled steps (the only difference in arithmetic is the
 order of the FP64 cell sums that become the regions' face neighbours);
-FP32 within 1e-4 (atoms) and 2e-5 (regions).
+FP32, or an FP32 region beside FP64 atoms, within 1e-4 (atoms) and 2e-5
+(regions).
 """
 import sys
 
@@ -82,9 +83,14 @@ def random_m(n, seed):
     return m / np.linalg.norm(m, axis=0)
 
 
-@pytest.mark.parametrize("prec,grains", [(A.ASD_FP64, False), (A.ASD_FP64, True),
-                                         (A.ASD_FP32, True)], ids=["fp64", "fp64_grains", "fp32_grains"])
-def test_multiscale_window_matches_oracle(prec, grains):
+@pytest.mark.parametrize("prec,grains,right_prec",
+                         [(A.ASD_FP64, False, None), (A.ASD_FP64, True, None),
+                          (A.ASD_FP32, True, None), (A.ASD_FP64, True, A.ASD_FP32)],
+                         ids=["fp64", "fp64_grains", "fp32_grains", "fp64_with_fp32_right_region"])
+def test_multiscale_window_matches_oracle(prec, grains, right_prec):
+    """Two regions of the same precision take the paired launches (one per
+    stage and per face operation for both sides); a right region in FP32 beside
+    FP64 atoms and left region takes one launch sequence per region."""
     steps = 30
     cx, cy, cz = CELL
     w = atoms_workload(grains)
@@ -95,7 +101,7 @@ def test_multiscale_window_matches_oracle(prec, grains):
     S0 = W.initial_spins(len(lab), 5)
     S0[:, lab < 0] = 0
     h.set_spins(S0)
-    pl, pr = mm_params(w, prec, 5), mm_params(w, prec, 4)
+    pl, pr = mm_params(w, prec, 5), mm_params(w, right_prec or prec, 4)
     L = A.MMHandle(pl, stream=h.stream)
     R = A.MMHandle(pr, stream=h.stream)
     dr = A.asd_drive()
@@ -131,7 +137,7 @@ def test_multiscale_window_matches_oracle(prec, grains):
     dL = float(np.max(np.abs(gL.astype(np.float64) - mL)))
     dR = float(np.max(np.abs(gR.astype(np.float64) - mR)))
     say(f"  max |dS| atoms {dS:.3e}, left region {dL:.3e}, right region {dR:.3e}")
-    tol_a, tol_m = (1e-12, 1e-12) if prec == A.ASD_FP64 else (1e-4, 2e-5)
+    tol_a, tol_m = (1e-12, 1e-12) if prec == A.ASD_FP64 and right_prec is None else (1e-4, 2e-5)
     assert dS <= tol_a and dL <= tol_m and dR <= tol_m
     # the coupling mattered: the regions alone land elsewhere
     alone = mm_oracle(pl)
