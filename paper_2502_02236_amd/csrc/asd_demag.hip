@@ -16,8 +16,9 @@
 // the full row is rebuilt before the inverse x transform.
 // The spectrum carries -mu0 mu_s / (V Px Py Pz), so the result is the flux
 // density mu0 H_d in tesla from plain spin sums.  Every transform is a
-// radix-2 Stockham FFT over a batch of lines held in LDS (ping-pong
-// buffers), one barrier per stage; the padded sizes are powers of two.
+// Stockham FFT over a batch of lines held in LDS (ping-pong buffers): radix-4
+// stages, after one radix-2 stage when log2 of the length is odd, one barrier
+// per stage; the padded sizes are powers of two.
 #include <hip/hip_runtime.h>
 
 #include "asd.h"
