@@ -400,7 +400,12 @@ int asd_mm_get_face(asd_mm_t *h, int32_t face, double *dirs);
  * cx frozen columns just outside the window (the atomistic exchange
  * neighbours there); then one Heun step of the atoms and one RK4 step of each
  * region, all on the atomistic handle's stream (both handles must have been
- * created on it).  Needs cx <= origin and origin + nx + cx <= track_nx. */
+ * created on it).  Needs cx <= origin and origin + nx + cx <= track_nx.
+ * With both regions of one precision under a spot that does not move, each
+ * face operation and each RK4 stage runs as one launch for the two sides;
+ * the results are those of the per-region sequence.  Errors: ASD_EINVAL for
+ * bad sizes, streams or meshes (nothing enqueued); a failure part-way through
+ * the n steps returns at once, after the steps already enqueued. */
 int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
                         int32_t cy, int32_t cz, int64_t n);
 const char *asd_mm_last_error(const asd_mm_t *h);
