@@ -204,6 +204,10 @@ EDGE_CASES = [
     ("l10_periodic_z_3", c3_crop(nz=3, bc=(W.BC_PERIODIC,) * 3, seed=38)),
     ("l10_3x3_periodic", c3_crop(nx=3, ny=3, nz=2, grains=False, bc=(W.BC_PERIODIC,) * 2 + (W.BC_OPEN,),
                                  seed=36)),
+    # one site (no neighbours: anisotropy, field and noise only) and a line
+    ("sc_single_site", W.c1_plain_sc().scaled(nx=1, ny=1, nz=1, bc=(0, 0, 0), seed=39)),
+    ("sc_line_x", W.c1_plain_sc().scaled(nx=7, ny=1, nz=1, bc=(W.BC_PERIODIC, 0, 0), seed=40)),
+    ("sc_column_z", W.c1_plain_sc().scaled(nx=1, ny=1, nz=9, bc=(0, 0, 0), seed=44)),
 ]
 
 
@@ -228,6 +232,38 @@ def test_degenerate_lattices(name, w):
             tile += 1
             if tile >= n_var:
                 break
+
+
+def test_system_without_magnetic_sites():
+    """A system whose every site is non-magnetic beside an ordinary one: its
+    spins stay zero, its sums and counts are zero, and the other system is
+    unaffected (equal to the oracle)."""
+    w = W.c1_plain_sc().scaled(nx=9, ny=7, nz=3, bc=(0, 0, 0), seed=45)
+    n = w.nx * w.ny * w.nz
+    empty = np.full(n, -1, dtype=np.int32)
+    full = np.zeros(n, dtype=np.int32)
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        for kernel in (A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED):
+            ins = [bridge.SystemInputs(w, labels=empty), bridge.SystemInputs(w, labels=full)]
+            h = A.Handle(bridge.params_for(w, precision), [i.desc for i in ins])
+            dr, _ = bridge.drive_for(w)
+            h.set_drive(dr)
+            h._inputs = ins
+            h.set_variant(kernel, 0)
+            S1 = initial_state(w, full)
+            h.set_spins(np.zeros((3, n)), 0)
+            h.set_spins(S1, 1)
+            h.step(25)
+            assert np.all(h.get_spins(0) == 0)
+            _, ps = h.magnetization()
+            assert np.all(ps[0] == 0) and ps[1, 3] == n
+            E = h.energy()
+            assert np.all(E[0] == 0)
+            _, So = run_oracle(w, full, S1, 25, sys_id=1)
+            err = maxdiff(h.get_spins(1), So)
+            say("empty system", precision, kernel, err)
+            assert err <= TOL[precision]
+            h.close()
 
 
 @pytest.mark.parametrize("precision", [A.ASD_FP64, A.ASD_FP32])
