@@ -71,6 +71,10 @@ CASES = [
     ("slab_hot_1200K", slab(T_amb=1200.0, B=(0.3, 0.0, 0.8)), None, 0),
     ("periodic_z_cube", slab(nx=12, ny=10, nz=8, bc=(1, 1, 1), grains=False), None, 0),
     ("track_window_ku_spread_shifted", track(), "ku", 5),
+    # open boxes of odd lengths (the colours need even lengths only on
+    # periodic axes) and a single site without neighbours
+    ("odd_open_box", slab(nx=7, ny=5, nz=3, grains=False, bc=(0, 0, 0)), None, 0),
+    ("single_site_1200K", slab(nx=1, ny=1, nz=1, grains=False, bc=(0, 0, 0), T_amb=1200.0), None, 0),
 ]
 
 

@@ -88,6 +88,9 @@ CASES = [
     ("locked_spot_above_Tc_core", (18, 12, 2), (1e-9, 1e-9, 2e-9), (0, 1, 0),
      dict(B=(0.0, 0.0, -0.8), spot=A.ASD_SPOT_LOCKED, x0=9e-9, y0=6e-9, **SPOT)),
     ("cold_zero_field", (10, 10, 5), (1e-9, 1e-9, 1e-9), (1, 1, 1), dict(B=(0.0, 0.0, 0.0))),
+    # one cell (no exchange neighbours) and a periodic line of odd length
+    ("single_cell", (1, 1, 1), (1e-9, 1e-9, 2e-9), (0, 0, 0), dict(B=(0.3, 0.0, -0.8), T_amb=300.0)),
+    ("periodic_line_x", (9, 1, 1), (1e-9, 1e-9, 2e-9), (1, 0, 0), dict(B=(0.0, 0.0, -0.8), T_amb=400.0)),
 ]
 
 
