@@ -364,6 +364,40 @@ def test_window_end_transfer_matches_oracle(name, w):
         h.close()
 
 
+@pytest.mark.parametrize("x0,ncols,cell", [(4, 3, (1, 1, 1)), (0, 37, (37, 29, 7)),
+                                           (6, 11, (5, 40, 9)), (20, 1, (2, 2, 2))],
+                         ids=["site_cells", "one_cell_whole_lattice", "cells_beyond_y_z",
+                              "one_column"])
+def test_transfer_cell_shapes(x0, ncols, cell):
+    """Coarse cells of one site (the sums are the spins), one cell over the whole
+    lattice, cells taller and deeper than the lattice (one ragged cell across y
+    and z), and a strip of one column: sums to FP64 rounding with exact counts,
+    cone spins bit-identical to the oracle (FP64)."""
+    w = c2_crop(seed=46)
+    kind = oracle.SC
+    cx, cy, cz = cell
+    h, lab, _ = run_gpu(w, A.ASD_FP64, 10)
+    S = h.get_spins().astype(np.float64)
+    got = h.coarse_grain(0, x0, ncols, cx, cy, cz).cpu().numpy()
+    ref = oracle.coarse_grain(kind, w.nx, w.ny, w.nz, lab, S, x0, ncols, cx, cy, cz)
+    assert got.shape == ref.shape
+    np.testing.assert_array_equal(got[:, 3], ref[:, 3])
+    assert np.max(np.abs(got[:, :3] - ref[:, :3])) < 1e-12 * max(1.0, np.abs(ref).max())
+    if cell == (1, 1, 1):  # one site per cell: the sums are the spins themselves
+        sub = S.reshape(3, w.nz, w.ny, w.nx)[:, :, :, x0:x0 + ncols].reshape(3, -1)
+        np.testing.assert_array_equal(got[:, :3].T, sub)
+    rng = np.random.default_rng(9)
+    nc = h.coarse_cells(0, ncols, cx, cy, cz)
+    assert nc == len(ref)
+    mcell = rng.normal(size=(nc, 3))
+    mcell *= (rng.uniform(0.2, 1, nc) / np.linalg.norm(mcell, axis=1))[:, None]
+    h.thermalise_columns(0, x0, ncols, cx, cy, cz, mcell, 91)
+    So = oracle.cone_columns(kind, w.nx, w.ny, w.nz, lab, S, x0, ncols, cx, cy, cz, mcell, 10,
+                             w.seed, 91, 0)
+    np.testing.assert_array_equal(h.get_spins(), So)
+    h.close()
+
+
 def test_error_paths_leave_the_handle_usable():
     """Invalid calls fail with their codes before anything is enqueued and
     leave the handle's state as it was: afterwards the handle still steps
