@@ -206,3 +206,42 @@ def test_x_face_coupling_converges_to_the_unsplit_mesh():
     a = L.rk4(np.ascontiguousarray(M0[:, :, :, :8]).reshape(3, -1), 0, 200)
     drift = np.max(np.abs(a.reshape(3, 2, 3, 8) - ref[:, :, :, :8]))
     assert drift > 10 * errs[-1]
+
+
+@pytest.mark.parametrize("kind,cell", [(oracle.SC, (3, 4, 2)), (oracle.L10, (2, 3, 3))])
+def test_set_columns_writes_each_cell_direction(kind, cell):
+    """The regions' faces written into atomistic columns: every magnetic site of
+    a coarse cell takes the cell's unit direction (+z for a zero cell), the
+    non-magnetic sites stay zero and the other columns are untouched; so
+    coarse-graining the written columns gives count x direction."""
+    sx, ny, nz = 11, 7, 5
+    cx, cy, cz = cell
+    per = 1 if kind == oracle.SC else 2
+    n = per * sx * ny * nz
+    rng = np.random.default_rng(12)
+    lab = np.where(rng.uniform(size=n) < 0.2, -1, 0).astype(np.int32)
+    S0 = rng.normal(size=(3, n))
+    S0 /= np.linalg.norm(S0, axis=0)
+    S0[:, lab < 0] = 0.0
+    x0, ncols = 4, 5
+    ncell = -(-ncols // cx) * -(-ny // cy) * -(-nz // cz)
+    mcell = rng.normal(size=(ncell, 3)) * rng.uniform(0.1, 2.0, size=(ncell, 1))
+    mcell[1] = 0.0
+    S = oracle.set_columns(kind, sx, ny, nz, lab, S0, x0, ncols, cx, cy, cz, mcell)
+    unit = mcell / np.maximum(np.linalg.norm(mcell, axis=1), 1e-300)[:, None]
+    unit[1] = (0.0, 0.0, 1.0)
+    site = np.arange(n)
+    x = (site // per) % sx
+    y = (site // per // sx) % ny
+    z = site // per // sx // ny
+    inside = (x >= x0) & (x < x0 + ncols)
+    c = (x - x0) // cx + -(-ncols // cx) * (y // cy + -(-ny // cy) * (z // cz))
+    mag = lab >= 0
+    np.testing.assert_array_equal(S[:, ~inside], S0[:, ~inside])
+    np.testing.assert_array_equal(S[:, inside & ~mag], 0.0)
+    w = inside & mag
+    np.testing.assert_allclose(S[:, w], unit[c[w]].T, rtol=0, atol=1e-15)
+    out = oracle.coarse_grain(kind, sx, ny, nz, lab, S, x0, ncols, cx, cy, cz)
+    counts = np.bincount(c[w], minlength=ncell)
+    np.testing.assert_array_equal(out[:, 3], counts)
+    np.testing.assert_allclose(out[:, :3], counts[:, None] * unit, rtol=1e-13, atol=1e-13)
