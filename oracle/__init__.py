@@ -102,6 +102,11 @@ def _declare(L):
     L.orc_heun_steps.restype = C.c_int
     L.orc_magnetisation.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int, f64p, f64p]
     L.orc_energy.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int64, f64p]
+    L.orc_site_temperature.argtypes = [P(OrcSystem), C.c_int64, C.c_int64]
+    L.orc_site_temperature.restype = C.c_double
+    L.orc_polarity.argtypes = [P(OrcSystem), C.c_int64]
+    L.orc_polarity.restype = C.c_double
+    L.orc_field.argtypes = [P(OrcSystem), f64p, f64p, f64p, C.c_int64, C.c_int64, f64p]
     L.orc_coarse_grain.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p, f64p, f64p,
                                    C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
     L.orc_newell_tensor.argtypes = [C.c_double] * 6 + [f64p]
@@ -115,6 +120,10 @@ def _declare(L):
     L.orc_mm_me.restype = C.c_double
     L.orc_mm_rk4.argtypes = [P(OrcMM), f64p, C.c_int64, C.c_int64]
     L.orc_mm_rk4.restype = C.c_int
+    L.orc_mm_temperature.argtypes = [P(OrcMM), C.c_int, C.c_int, C.c_double]
+    L.orc_mm_temperature.restype = C.c_double
+    L.orc_mm_polarity.argtypes = [P(OrcMM), C.c_int64]
+    L.orc_mm_polarity.restype = C.c_double
     L.orc_set_columns.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p, f64p, f64p,
                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
     L.orc_cone_theta_max.argtypes = [C.c_double]
@@ -306,6 +315,29 @@ class System:
                                 n_grains, _ptr(pg, f64p), _ptr(tot, f64p))
         return pg[:n_grains], tot
 
+    def temperature(self, step: int, sites=None) -> np.ndarray:
+        """Spot temperature (K) of the given sites (default: all) at `step`."""
+        idx = range(len(self.label)) if sites is None else sites
+        return np.array([lib().orc_site_temperature(C.byref(self._s), int(i), step) for i in idx])
+
+    def polarity(self, step: int) -> float:
+        return lib().orc_polarity(C.byref(self._s), step)
+
+    def field(self, S, step: int, sites=None) -> np.ndarray:
+        """Deterministic field (T) at the given sites, float[len, 3]: exchange,
+        anisotropy and the polarised write field as a Heun stage assembles them
+        (no thermal or demagnetising term)."""
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(3, -1)
+        Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
+        idx = range(len(self.label)) if sites is None else sites
+        out = []
+        for i in idx:
+            b = np.zeros(3)
+            lib().orc_field(C.byref(self._s), _ptr(Sx, f64p), _ptr(Sy, f64p), _ptr(Sz, f64p),
+                            int(i), step, _ptr(b, f64p))
+            out.append(b)
+        return np.array(out).reshape(-1, 3)
+
     def energy(self, S, step: int) -> np.ndarray:
         S = np.ascontiguousarray(S, dtype=np.float64).reshape(3, -1)
         Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
@@ -430,6 +462,13 @@ class MM:
         seen by the boundary cells' exchange stencil; None removes it."""
         self.ghosts[face] = None if dirs is None else np.ascontiguousarray(dirs, np.float64)
         self._p.ghost[face] = _ptr(self.ghosts[face], f64p)
+
+    def temperature(self, i: int, j: int, t: float) -> float:
+        """Temperature (K) of cell (i, j) at time t (s)."""
+        return lib().orc_mm_temperature(C.byref(self._p), i, j, t)
+
+    def polarity(self, step: int) -> float:
+        return lib().orc_mm_polarity(C.byref(self._p), step)
 
     def face(self, face: int, m) -> np.ndarray:
         """Directions [ny*nz, 3] of the boundary cells on x face `face`."""

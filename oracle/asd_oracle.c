@@ -457,12 +457,18 @@ static void normalise(double v[3])
     v[2] = v[2] / n;
 }
 
-/* write-field polarity at step n (bit sequence by field polarity) */
+/* write-field polarity at step n (bit sequence by field polarity): bit
+ * (n / steps_per_bit) mod n_bits, +1 when set; +1 without a pattern */
+static double bit_polarity(int n_bits, const uint8_t *bits, int64_t steps_per_bit, int64_t n)
+{
+    if (n_bits <= 0 || steps_per_bit <= 0) return 1.0;
+    int64_t k = (n / steps_per_bit) % n_bits;
+    return bits[k] ? 1.0 : -1.0;
+}
+
 static double polarity(const orc_system *s, int64_t n)
 {
-    if (s->n_bits <= 0 || s->steps_per_bit <= 0) return 1.0;
-    int64_t k = (n / s->steps_per_bit) % s->n_bits;
-    return s->bits[k] ? 1.0 : -1.0;
+    return bit_polarity(s->n_bits, s->bits, s->steps_per_bit, n);
 }
 
 /* Gaussian laser spot (Sec. III, Fig. 2): T = Tamb + (Tpk-Tamb) exp(-r^2/2s^2),
@@ -595,6 +601,25 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
     }
     free(Px); free(Py); free(Pz); free(f0); free(bth); free(bd);
     return 0;
+}
+
+/* The per-site drive and the deterministic field, exported so that tests
+ * can check them against closed forms: the spot temperature of site i at
+ * step n, the write-field polarity of step n, and B_i without the thermal
+ * and demagnetising terms (exchange, anisotropy and the polarised write
+ * field, exactly as the Heun stages assemble it). */
+double orc_site_temperature(const orc_system *s, int64_t i, int64_t n)
+{
+    return site_temperature(s, i, n);
+}
+
+double orc_polarity(const orc_system *s, int64_t n) { return polarity(s, n); }
+
+void orc_field(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+               int64_t i, int64_t n, double B[3])
+{
+    const double none[3] = {0.0, 0.0, 0.0};
+    field(s, Sx, Sy, Sz, i, polarity(s, n), none, NULL, B);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1044,6 +1069,16 @@ static double mm_temperature(const orc_mm *p, int i, int j, double t)
     return p->T_amb + (p->T_peak - p->T_amb) * orc_exp(-q);
 }
 
+double orc_mm_temperature(const orc_mm *p, int i, int j, double t)
+{
+    return mm_temperature(p, i, j, t);
+}
+
+double orc_mm_polarity(const orc_mm *p, int64_t n)
+{
+    return bit_polarity(p->n_bits, p->bits, p->steps_per_bit, n);
+}
+
 /* neighbour of cell (i, j, k) along axis ax, direction d (+-1), or -1 */
 static int64_t mm_nb(const orc_mm *p, int i, int j, int k, int ax, int d)
 {
@@ -1116,9 +1151,7 @@ int orc_mm_rk4(const orc_mm *p, double *m, int64_t step0, int64_t nsteps)
     const double dt = p->dt;
     for (int64_t s = 0; s < nsteps; ++s) {
         int64_t step = step0 + s;
-        double pol = 1.0;
-        if (p->n_bits > 0 && p->steps_per_bit > 0)
-            pol = p->bits[(step / p->steps_per_bit) % p->n_bits] ? 1.0 : -1.0;
+        double pol = bit_polarity(p->n_bits, p->bits, p->steps_per_bit, step);
         double t = (double)step * dt;
         mm_rhs(p, m, t, pol, k1);
         for (int64_t q = 0; q < 3 * n; ++q) u[q] = m[q] + (0.5 * dt) * k1[q];

@@ -83,6 +83,13 @@ void orc_voronoi_labels(int kind, int nx, int ny, int nz, const int periodic[2],
 
 int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int64_t step0,
                    int64_t nsteps);
+/* spot temperature (K) of site i at step n; write-field polarity (+-1) of
+ * step n; deterministic field (T) at site i: exchange + anisotropy +
+ * polarised write field (no thermal or demagnetising term) */
+double orc_site_temperature(const orc_system *s, int64_t i, int64_t n);
+double orc_polarity(const orc_system *s, int64_t n);
+void orc_field(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
+               int64_t i, int64_t n, double B[3]);
 void orc_magnetisation(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                        int n_grains, double *per_grain, double tot[4]);
 /* window-end transfer (Sec. II, Eq. 6): coarse cells of cx x cy x cz
@@ -134,6 +141,9 @@ typedef struct orc_mm {
 double orc_langevin(double x);
 double orc_mm_me(double T, double Tc, double b);
 int orc_mm_rk4(const orc_mm *p, double *m, int64_t step0, int64_t nsteps);
+/* temperature (K) of cell (i, j) at time t (s); polarity of step n */
+double orc_mm_temperature(const orc_mm *p, int i, int j, double t);
+double orc_mm_polarity(const orc_mm *p, int64_t n);
 void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                 int64_t step, double out[4]);
 
