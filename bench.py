@@ -1,22 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the sLLG Heun step on one MI355X.
 
-Default workload (--workload slab): the 200x200x33 simple-cubic granular slab
-(1.32M sites, Voronoi 8 nm grains with 1 nm non-magnetic boundaries, 800 K
-Gaussian laser spot moving at 10 m/s over 300 K, -0.8 T write field), seeded
-synthetic input.  A step is one full Heun step of every site (spot
-temperature, Philox noise, Box-Muller, exchange, anisotropy, Zeeman,
-predictor, corrector).  Other workloads: l10 (L1_0 Fe sublattice window,
-four shells, 2.19M sites), cylinders (512 isolated grains of uneven size,
-each at its own temperature, moment statistics every 10 steps), track
-(16 seeds of a 400x200x33 moving window in an 800-column track with
-per-grain anisotropy spread and bit-timed write field).
+Default workload (--workload track): the moving-window recording batch, 16
+seeds of a 400x200x33 simple-cubic window (120x60x10 nm at a = 0.3 nm) in
+800-column tracks, each seed with its own Voronoi grain map (8 nm grains, 1 nm
+non-magnetic boundaries) and a 5 % per-grain anisotropy spread, an 800 K
+Gaussian laser spot locked to the window, a +-0.8 T write field carrying
+20 nm bits at 20 m/s, FP32, 42.2M lattice sites in one launch per step;
+seeded synthetic input.  A step is one full Heun step of every window site
+(spot temperature, Philox noise, Box-Muller, exchange, anisotropy, Zeeman,
+predictor, corrector); the window shifts by one column every 15 000 steps.
+The timed steps run as HIP-graph segments (the largest even divisor of
+--steps up to 1000 steps, so exactly --steps steps are timed).
+
+Other workloads: slab (the 200x200x33 granular slab, cache-resident), l10
+(L1_0 Fe sublattice window, four shells, 2.19M sites), cylinders (512 isolated
+grains of uneven size, each at its own temperature, moment statistics every 10
+steps), and the rows beyond the step (transfer, demag, mc, mm, multiscale).
 
 Prints one JSON line: spin-updates/s (magnetic sites x steps / s) with the
 roofline of the dominant kernel (algorithmic bytes or VALU work per launch / its
 average duration from HIP events on the handle's stream; the bound is whichever
-of the two takes longer at its peak, and the other is reported beside it) and
-the FP64 CPU oracle timed on a bounded sample.
+of the two takes longer at its peak, and the other is reported beside it),
+the same step on other lattices and precisions, and the FP64 CPU oracle timed
+on a cropped window of the same workload.
 """
 from __future__ import annotations
 
@@ -42,6 +49,9 @@ W_PRODUCT = 1.56  # v_mad_u64_u32: the 32 x 32 -> 64 product of a Philox round
 W_TRANS = 2.75    # v_log_f32, v_rsq_f32 (and the other transcendentals)
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_2502_02236_amd", "tune_mi355x.json")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,21 +59,39 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track", "transfer",
-                                           "demag", "mc", "mm", "multiscale"], default="slab")
+                                           "demag", "mc", "mm", "multiscale"], default="track")
     ap.add_argument("--demag-cell", type=int, nargs=3, default=[4, 4, 3],
                     help="coarse cell of the demag workload, in lattice cells")
     ap.add_argument("--kernel", choices=["auto", "plain", "fused"], default="auto")
     ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--graph-steps", type=int, default=-1,
+                    help="steps per HIP-graph segment (-1: the largest even divisor of "
+                         "--steps up to 1000; 0: eager launches)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache (the tile picks measured on MI355X)")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto ~15 s)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other lattices and precisions beside the headline")
+    ap.add_argument("--cpu-steps", type=int, default=1000, help="oracle steps per CPU process")
+    ap.add_argument("--cpu-worker", type=int, default=-1, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of known size (HBM counter calibration)")
     ap.add_argument("--issue-rates", action="store_true",
                     help="only measure the VALU issue cost of the instruction classes the "
                          "cost model weighs, and print them")
     return ap.parse_args()
+
+
+def segment_steps(steps: int, cap: int = 1000) -> int:
+    """Steps per graph segment: the largest even divisor of `steps` (of steps - 1
+    when odd) not above `cap`; 0 when there is none (eager launches)."""
+    n = steps if steps % 2 == 0 else steps - 1
+    best = 0
+    for g in range(2, min(cap, n) + 1, 2):
+        if n % g == 0:
+            best = g
+    return best
 
 
 def issue_rates():
@@ -74,9 +102,9 @@ def issue_rates():
 
     import torch
     from paper_2502_02236_amd import build as B
-    if not os.path.exists(B.RATE_LIB):
-        raise RuntimeError(f"{B.RATE_LIB} is not built")
-    lib = ctypes.CDLL(B.RATE_LIB)
+    # a measurement-only probe, not part of libasd: built here on demand
+    src = os.path.join(ROOT, "tests", "helpers", "issue_rate.hip")
+    lib = ctypes.CDLL(B.build_probe(src, os.path.join(ROOT, "_build", "libissue_rate.so")))
     lib.issue_rate_name.restype = ctypes.c_char_p
     lib.issue_rate_time.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_float)]
@@ -253,7 +281,9 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps, workl
                                                       args.demag_cell)
     if kern == A.ASD_KERNEL_AUTO:
         os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
-        h.autotune(os.path.join(ROOT, "_build", "asd_tune.json"))
+        cache = (os.path.join(ROOT, "_build", "asd_tune_fresh.json") if args.retune
+                 else args.tune_cache)
+        h.autotune(cache)
         for k, S0 in enumerate(S0s):
             h.set_spins(S0, k)
         h.set_step(0)
@@ -280,7 +310,62 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps, workl
     norm_err = float(np.max(np.abs(np.sqrt((S[:, mag] ** 2).sum(0)) - 1)))
     h.close()
     return dict(w=w, t=t, n_mag=n_mag, n_sites=n_sites, steps=steps, kernel=kernel_used,
-                tile=tile_used, step_med=med, step_mean=mean, norm_err=norm_err, kname=kname)
+                tile=tile_used, step_med=med, step_mean=mean, norm_err=norm_err, kname=kname,
+                graph_steps=graph_steps, workload=workload, precision=precision_name,
+                eager_steps=steps - (steps // graph_steps) * graph_steps if graph_steps else steps)
+
+
+def step_roofline(r):
+    """Roofline of the step kernel of a gpu_run result: algorithmic bytes and (FP32)
+    VALU work per launch over the average launch duration in the timed region."""
+    precision, workload = r["precision"], r["workload"]
+    bps = bytes_per_site(precision, workload, r["kname"])
+    alg_bytes = bps * r["n_sites"]
+    # average launch duration of the step kernel over the timed region (kernels
+    # back to back on the handle's stream; includes the gaps between them)
+    launch_s = r["t"] / r["steps"]
+    achieved = alg_bytes / launch_s / 1e9
+    traffic, traffic_src = measured_traffic(r["kname"], workload, precision, r["tile"])
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
+           "algorithmic_bytes_per_launch": alg_bytes}
+    roof = dict(bound="hbm", **hbm)
+    cyc = alu_ops_per_site(precision, workload)
+    if cyc is not None:
+        # the bound is whichever of the algorithmic HBM bytes and VALU work takes
+        # longer at its peak; the other roofline is reported beside it
+        alu_ops = cyc * r["n_mag"]
+        alu_ach = alu_ops / launch_s / 1e12
+        alu = {"achieved": alu_ach, "peak": VALU_PEAK_T, "unit": "T FP32-FMA slots/s",
+               "frac": alu_ach / VALU_PEAK_T, "alu_ops_per_magnetic_site": cyc,
+               "alu_ops_per_launch": alu_ops}
+        if alu_ops / (VALU_PEAK_T * 1e12) > alg_bytes / (HBM_PEAK_GBS * 1e9):
+            roof = dict(bound="alu", **alu)
+            roof["hbm"] = hbm
+        else:
+            roof["alu"] = alu
+    roof.update({"traffic": traffic, "traffic_source": traffic_src, "kernel": r["kname"],
+                 "launch_us_mean": 1e6 * launch_s,
+                 "launch_us_eager_events_median": 1e6 * r["step_med"]})
+    return roof
+
+
+def step_summary(r, **extra):
+    """One workload beside the headline: rate, step time and roofline fractions."""
+    roof = step_roofline(r)
+    out = {"workload": r["w"].name, "precision": r["precision"],
+           "kernel": {1: "plain", 2: "fused"}.get(r["kernel"], "?"), "tile": r["tile"],
+           "kernel_name": r["kname"], "steps": r["steps"], "graph_steps": r["graph_steps"],
+           "value": r["n_mag"] * r["steps"] / r["t"], "unit": "spin-updates/s",
+           "ms_per_step": 1e3 * r["t"] / r["steps"], "sites": r["n_sites"],
+           "magnetic_sites": r["n_mag"], "bound": roof["bound"], "frac": roof["frac"],
+           "hbm_frac": roof["hbm"]["frac"] if "hbm" in roof else roof["frac"]}
+    if "alu" in roof:
+        out["alu_frac"] = roof["alu"]["frac"]
+    elif roof["bound"] == "alu":
+        out["alu_frac"] = roof["frac"]
+    out.update(extra)
+    return out
 
 
 def transfer_run(args, cell=7, reps=20):
@@ -466,32 +551,99 @@ def mc_run(args):
     return dict(w=w, t=t, n_mag=n_mag, n_sites=n_sites, mz=mz)
 
 
-def cpu_baseline(target_s=15.0, steps=0):
-    """The FP64 oracle, single-threaded plain C, on the full lattice for a few steps."""
+def cpu_crop(k: int = 0):
+    """The track workload cropped for the CPU oracle: a 64x64x33 window at the
+    start of a 128-column track (the same lattice, grains of the same size law,
+    per-grain anisotropy spread, window-locked 800 K spot centred in the crop,
+    20 nm bits); seed k of the batch."""
+    import workloads as W
+    w = W.c5_track_window()
+    c = w.scaled(nx=64, ny=64, nz=33, track_nx=128, x0=32 * w.a, y0=32 * w.a, seed=w.seed + k)
+    return c
+
+
+def cpu_worker(k: int, steps: int) -> dict:
+    """One oracle run of the cropped track window (seed k, system id k):
+    `steps` Heun steps from the seeded initial spins; returns the magnetic
+    spin-updates and the seconds the steps took."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import workloads as W
-    from oracle_build import oracle_labels, oracle_system
+    from oracle_build import oracle_labels, oracle_system, window_mask
 
-    w = W.c2_granular_slab()
-    lab = oracle_labels(w)
-    sysm = oracle_system(w, labels=lab)
+    w = cpu_crop(k)
+    seeds = W.voronoi_seeds(w)
+    lab = oracle_labels(w, seeds=seeds)
+    ku = W.grain_ku(len(seeds), w.ku, w.ku_spread, w.seed)
+    win = window_mask(w, 0)
+    sysm = oracle_system(w, labels=lab, ku_grain=ku, sys_id=k, active=win, origin=0)
     S = W.initial_spins(len(lab), w.seed + 100)
     S[:, lab < 0] = 0
     t0 = time.perf_counter()
-    S = sysm.heun(S, 0, 1)
-    one = time.perf_counter() - t0
-    k = steps if steps > 0 else max(2, int(target_s / max(one, 1e-3)))
-    t0 = time.perf_counter()
-    sysm.heun(S, 1, k)
+    sysm.heun(S, 0, steps)
     dt = time.perf_counter() - t0
-    n_mag = int((lab >= 0).sum())
-    return dict(value=n_mag * k / dt, unit="spin-updates/s", cores=1, kind="oracle",
-                sample=f"full 200x200x33 slab, {k} Heun steps (steps 1..{k}), FP64, "
-                       f"single-threaded plain C, {dt:.1f} s")
+    n_mag = int(((lab >= 0) & (win > 0)).sum())
+    return {"updates": n_mag * steps, "seconds": dt, "magnetic_sites": n_mag}
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(steps: int = 1000):
+    """The FP64 oracle (single-threaded plain C, as it stands) on the GPU machine's
+    host: the cropped track window for `steps` Heun steps, once alone (per-core
+    rate) and then as one independent seed per core in separate processes
+    (aggregate rate), at most 16 processes (the host share of one GPU)."""
+    import subprocess
+    model, nproc, usable = cpu_info()
+    P = max(1, min(usable, 16))
+
+    def launch(k):
+        return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(k),
+                                 "--cpu-steps", str(steps)], stdout=subprocess.PIPE, text=True)
+
+    def collect(procs):
+        res = []
+        for p in procs:
+            out, _ = p.communicate()
+            if p.returncode != 0:
+                raise RuntimeError(f"oracle worker failed with {p.returncode}")
+            res.append(json.loads(out.strip().splitlines()[-1]))
+        return res
+
+    one = collect([launch(0)])[0]
+    many = collect([launch(k) for k in range(P)])
+    per_core = one["updates"] / one["seconds"]
+    aggregate = sum(r["updates"] / r["seconds"] for r in many)
+    w = cpu_crop(0)
+    return dict(value=aggregate, unit="spin-updates/s", cores=P, kind="oracle",
+                sample=f"track window cropped to {w.nx}x{w.ny}x{w.nz} in a {w.track_nx}-column "
+                       f"track ({one['magnetic_sites']} magnetic sites), {steps} Heun steps per "
+                       f"process, FP64 single-threaded plain C; per core: one process alone "
+                       f"({one['seconds']:.1f} s); all cores: {P} seeds in {P} concurrent "
+                       f"processes (sum of their rates)",
+                per_core_value=per_core, all_core_value=aggregate, processes=P,
+                cpu_model=model, nproc=nproc, usable_cpus=usable)
 
 
 def main():
     args = parse()
+    if args.cpu_worker >= 0:
+        print(json.dumps(cpu_worker(args.cpu_worker, args.cpu_steps)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the step "
                                    "library drives a single device, and runs over several "
@@ -592,12 +744,13 @@ def main():
                        "magnetic_sites": r["n_mag"], "precision": args.precision},
             "roofline": roof, "final_mz": r["mz"]}), flush=True)
         return
-    r = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, args.graph_steps)
+    g = segment_steps(args.steps) if args.graph_steps < 0 else args.graph_steps
+    r = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, g)
     demag = None
     if args.workload == "demag":
         # the same two-pass variant without the field: the difference is the
         # time of the two demagnetising-field evaluations of each step
-        r0 = gpu_run(args, args.precision, "plain", args.steps, args.warmup, args.graph_steps,
+        r0 = gpu_run(args, args.precision, "plain", args.steps, args.warmup, g,
                      workload="slab", tile=r["tile"])
         per_eval = (r["t"] - r0["t"]) / (2 * r["steps"])
         cx, cy, cz = args.demag_cell
@@ -622,36 +775,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     value = r["n_mag"] * r["steps"] / r["t"]
-    bps = bytes_per_site(args.precision, args.workload, r["kname"])
-    alg_bytes = bps * r["n_sites"]
-    # average launch duration of the step kernel over the timed region (kernels
-    # back to back on the handle's stream; includes the gaps between them)
-    launch_s = r["t"] / r["steps"]
-    achieved = alg_bytes / launch_s / 1e9
-    traffic, traffic_src = measured_traffic(r["kname"], args.workload, args.precision, r["tile"])
-    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
-           "algorithmic_bytes_per_launch": alg_bytes}
-    cyc = alu_ops_per_site(args.precision, args.workload)
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": bps,
-            "algorithmic_bytes_per_launch": alg_bytes}
-    if cyc is not None:
-        # the bound is whichever of the algorithmic HBM bytes and VALU work takes
-        # longer at its peak; the other roofline is reported beside it
-        alu_ops = cyc * r["n_mag"]
-        alu_ach = alu_ops / launch_s / 1e12
-        alu = {"achieved": alu_ach, "peak": VALU_PEAK_T, "unit": "T FP32-FMA slots/s",
-               "frac": alu_ach / VALU_PEAK_T, "alu_ops_per_magnetic_site": cyc,
-               "alu_ops_per_launch": alu_ops}
-        if alu_ops / (VALU_PEAK_T * 1e12) > alg_bytes / (HBM_PEAK_GBS * 1e9):
-            roof = dict(bound="alu", **alu)
-            roof["hbm"] = hbm
-        else:
-            roof["alu"] = alu
-    roof.update({"traffic": traffic, "traffic_source": traffic_src, "kernel": r["kname"],
-                 "launch_us_mean": 1e6 * launch_s,
-                 "launch_us_eager_events_median": 1e6 * r["step_med"]})
+    roof = step_roofline(r)
+    if args.workload == "track" and args.precision == "fp32":
+        # the goal for this path: 60 % of the HBM peak
+        hf = roof["frac"] if roof["bound"] == "hbm" else roof["hbm"]["frac"]
+        roof["hbm_target_frac"] = 0.60
+        roof["hbm_frac_of_target"] = hf / 0.60
     out = {
         "metric": "atomistic spin-updates/s (spins x Heun steps)",
         "value": value,
@@ -665,11 +794,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": r["w"].name, "lattice": "l10" if args.workload == "l10" else "sc",
+        "config": {"workload": r["w"].name + ("_x16seeds" if args.workload == "track" else ""),
+                   "lattice": "l10" if args.workload == "l10" else "sc",
                    "sites": r["n_sites"],
                    "magnetic_sites": r["n_mag"], "dt_fs": 1.0, "precision": args.precision,
                    "kernel": {1: "plain", 2: "fused"}.get(r["kernel"], "?"), "tile": r["tile"],
-                   "graph_steps": args.graph_steps},
+                   "graph_steps": r["graph_steps"],
+                   "timed_graph_segments": r["steps"] // r["graph_steps"] if r["graph_steps"] else 0,
+                   "timed_eager_steps": r["eager_steps"],
+                   "cache_resident": args.workload in ("slab", "l10")},
         "roofline": roof,
         "lattice_site_updates_per_s": r["n_sites"] * r["steps"] / r["t"],
         "max_norm_error": r["norm_err"],
@@ -678,15 +811,20 @@ def main():
         out["metric"] = "atomistic spin-updates/s (spins x Heun steps) with the demagnetising field"
         out["config"]["workload"] = f"{r['w'].name}+demag{cx}x{cy}x{cz}"
         out["demag"] = demag
-    if not args.no_fp64_compare and args.precision == "fp32" and args.workload == "slab":
-        r64 = gpu_run(args, "fp64", "plain", max(200, args.steps // 10), 20, 0)
-        v64 = r64["n_mag"] * r64["steps"] / r64["t"]
-        out["fp64_plain_value"] = v64
-        out["speedup_vs_fp64_plain"] = value / v64
-        # the FP64 fused kernel (bit-identical to the FP64 oracle), autotuned
-        r64f = gpu_run(args, "fp64", "auto", max(200, args.steps // 10), 20, args.graph_steps)
-        out["fp64_fused_value"] = r64f["n_mag"] * r64f["steps"] / r64f["t"]
-    if not args.no_cpu_baseline and args.workload == "slab":
+    if not args.no_extras and args.workload == "track" and args.precision == "fp32":
+        # the same step beside the headline: the plain FP64 two-pass kernels and the
+        # FP64 fused kernel on the same lattice, and the cache-resident lattices
+        n64 = 200
+        r64 = gpu_run(args, "fp64", "plain", n64, 20, segment_steps(n64), workload="track")
+        r64f = gpu_run(args, "fp64", "auto", n64, 20, segment_steps(n64), workload="track")
+        out["fp64_plain"] = step_summary(r64)
+        out["fp64_fused"] = step_summary(r64f)
+        out["speedup_vs_fp64_plain"] = value / out["fp64_plain"]["value"]
+        rs = gpu_run(args, "fp32", "auto", 2000, 200, segment_steps(2000), workload="slab")
+        rl = gpu_run(args, "fp32", "auto", 1000, 100, segment_steps(1000), workload="l10")
+        out["slab_fp32"] = step_summary(rs, cache_resident=True)
+        out["l10_fp32"] = step_summary(rl, cache_resident=True)
+    if not args.no_cpu_baseline and args.workload == "track":
         out["cpu_baseline"] = cpu_baseline(steps=args.cpu_steps)
     print(json.dumps(out), flush=True)
 

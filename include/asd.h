@@ -216,8 +216,10 @@ int asd_reduce_magnetization(asd_t *h, double *per_grain, double *per_system);
 int asd_reduce_energy(asd_t *h, double *per_system);
 
 /* Accumulate M-statistics of every system from its current spins: with
- * m = |sum_i S_i| / N_magnetic, per system [5]: (samples, sum m, sum m^2,
- * sum m^4, reserved).  reset != 0 clears before adding.  Enqueued on the
+ * m = |sum_i S_i| / N_magnetic over the window (Eq. 6 sums, FP64), per
+ * system [5]: (samples, sum m, sum m^2, sum m^4, reserved, always 0);
+ * these give <|m|>, the susceptibility N (<m^2> - <|m|>^2) mu_s / kB T and
+ * the Binder cumulant 1 - <m^4> / 3 <m^2>^2.  reset != 0 clears before adding.  Enqueued on the
  * stream; read with asd_get_moment_stats (synchronises). */
 int asd_accumulate_moments(asd_t *h, int32_t reset);
 int asd_get_moment_stats(asd_t *h, double *per_system /* [5 n_sys] */);
@@ -271,7 +273,6 @@ int asd_coarse_grain(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int32_t c
 int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int32_t cx,
                            int32_t cy, int32_t cz, const double *mcell, uint32_t step);
 
-/* Step counter and window origin of system sys (host copies). */
 /* n Metropolis Monte Carlo sweeps of the same Hamiltonian (exchange,
  * anisotropy, write field with its polarity at the sweep index; no thermal
  * field) at each system's ambient temperature: the calibration of the
@@ -306,6 +307,8 @@ int asd_get_stream(asd_t *h, void **stream);
  * ASD_ESTATE when the handle was created without demag_cell. */
 int asd_demag_field(asd_t *h, double *per_cell, int32_t *mesh);
 
+/* Step counter of the handle and window origin (in lattice columns) of
+ * system sys, from the host copies (no synchronisation). */
 int asd_get_state(asd_t *h, int32_t sys, int64_t *step, int32_t *origin);
 /* Set the step counter (resume from a checkpoint). */
 int asd_set_step(asd_t *h, int64_t step);
@@ -400,7 +403,10 @@ int asd_mm_get_face(asd_mm_t *h, int32_t face, double *dirs);
  * cx frozen columns just outside the window (the atomistic exchange
  * neighbours there); then one Heun step of the atoms and one RK4 step of each
  * region, all on the atomistic handle's stream (both handles must have been
- * created on it).  Needs cx <= origin and origin + nx + cx <= track_nx.
+ * created on it).  Needs cx <= origin and origin + nx + cx <= track_nx, each
+ * region's dt equal to the atomistic dt (one RK4 step per Heun step) and its
+ * cell edges h equal to (cx a, cy a, cz a) for SC or (cx a, cy a, cz c) for
+ * L1_0 (relative tolerance 1e-9), so its faces line up with the coarse cells.
  * With both regions of one precision under a spot that does not move, each
  * face operation and each RK4 stage runs as one launch for the two sides;
  * the results are those of the per-region sequence.  Errors: ASD_EINVAL for

@@ -1,6 +1,4 @@
-"""Build libasd.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc, and
-libissue_rate.so, the benchmark's VALU issue-rate calibration (not part of the
-step library).
+"""Build libasd.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc.
 
 Usage: python -m paper_2502_02236_amd.build   (or paper_2502_02236_amd.build.build())
 """
@@ -18,8 +16,6 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libasd.so")
-RATE_LIB = os.path.join(PKG, "libissue_rate.so")
-RATE_SOURCE = ("issue_rate.hip", ["-ffp-contract=fast"])
 ARCH = os.environ.get("ASD_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
@@ -46,10 +42,10 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def _compile(src: str, flags: list) -> str:
+def _compile(src: str, flags: list, srcdir: str = CSRC) -> str:
     obj = os.path.join(BUILD, src + ".o")
     lang = ["-x", "hip"]
-    cmd = [hipcc(), *lang, *COMMON, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *lang, *COMMON, *flags, "-c", os.path.join(srcdir, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -66,16 +62,23 @@ def _link(objs: list, lib: str) -> None:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link libasd.so (and the issue-rate
-    calibration library) next to this file."""
+    """Compile every source for gfx950 and link libasd.so next to this file."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
-        objs = list(ex.map(lambda sf: _compile(*sf), SOURCES + [RATE_SOURCE]))
-    _link(objs[:-1], LIB)
-    _link(objs[-1:], RATE_LIB)
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(lambda sf: _compile(*sf), SOURCES))
+    _link(objs, LIB)
     if verbose:
-        print(f"built {LIB} and {RATE_LIB}")
+        print(f"built {LIB}")
     return LIB
+
+
+def build_probe(src: str, lib: str) -> str:
+    """Compile one measurement-only HIP source (not part of libasd) into its own
+    shared library `lib` with the library's flags."""
+    os.makedirs(BUILD, exist_ok=True)
+    obj = _compile(os.path.basename(src), ["-ffp-contract=fast"], os.path.dirname(src))
+    _link([obj], lib)
+    return lib
 
 
 if __name__ == "__main__":

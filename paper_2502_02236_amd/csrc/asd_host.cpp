@@ -1064,6 +1064,8 @@ static int capture_graph(asd_t *h, int cur)
     e = hipGraphInstantiate(&h->graph[cur], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(h, ASD_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    // move the graph to the device now, so its first launch does not pay for it
+    HIP_OK(h, hipGraphUpload(h->graph[cur], h->stream));
     h->graph_kernel = h->kernel;
     h->graph_tile = h->tile_cfg;
     return ASD_OK;
@@ -1470,6 +1472,13 @@ int asd_set_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32_t cx, 
 }
 
 namespace asd {
+
+void lattice_cell(const asd_t *h, double *dt, double edge[3])
+{
+    *dt = h->p.dt;
+    edge[0] = edge[1] = h->p.a;
+    edge[2] = h->p.lattice == ASD_L10 ? h->p.c : h->p.a;
+}
 
 int coarse_grain_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols, int32_t cx,
                       int32_t cy, int32_t cz, double *outa, double *outb)

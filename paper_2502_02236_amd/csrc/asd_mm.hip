@@ -703,9 +703,22 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
     if ((rc = asd_get_state(atoms, sys, &step, &org))) return rc;
     void *st = nullptr;
     if ((rc = asd_get_stream(atoms, &st))) return rc;
+    double dt, edge[3];
+    lattice_cell(atoms, &dt, edge);
+    const int32_t cell[3] = {cx, cy, cz};
     asd_mm_t *r[2] = {left, right};
     for (asd_mm_t *m : r) {
         if (!m) continue;
+        // one RK4 step of a region per Heun step of the atoms, on cells that
+        // line up with the window's coarse cells
+        if (std::fabs(m->p.dt - dt) > 1e-9 * dt)
+            return mm_fail(m, ASD_EINVAL, "region dt %g s differs from the atomistic dt %g s",
+                           m->p.dt, dt);
+        for (int k = 0; k < 3; ++k)
+            if (std::fabs(m->p.h[k] - cell[k] * edge[k]) > 1e-9 * cell[k] * edge[k])
+                return mm_fail(m, ASD_EINVAL,
+                               "region cell edge %d is %g m, not %d lattice cells (%g m)", k,
+                               m->p.h[k], cell[k], cell[k] * edge[k]);
         if (m->stream != (hipStream_t)st)
             return mm_fail(m, ASD_EINVAL, "the region must run on the atomistic handle's stream");
         if (m->p.ny != (ny + cy - 1) / cy || m->p.nz != (nz + cz - 1) / cz)

@@ -18,6 +18,9 @@ int launch_cone_columns_pair(const TransferArgs &a0, const TransferArgs &a1, voi
 // [xb, xb + ncols) into outb, in one launch; same checks and error codes
 int coarse_grain_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols, int32_t cx,
                       int32_t cy, int32_t cz, double *outa, double *outb);
+// the handle's time step and lattice cell edges (x, y: a; z: a for SC, c for
+// L1_0), for the checks of the multiscale window
+void lattice_cell(const asd_t *h, double *dt, double edge[3]);
 // asd_set_columns of two strips in one launch
 int set_columns_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols, int32_t cx,
                      int32_t cy, int32_t cz, const double *ma, const double *mb);

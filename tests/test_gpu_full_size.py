@@ -10,8 +10,10 @@ with the oracle at every site of the L1_0 window, of a sample of cylinders (the
 first, last, smallest, largest and two in between) and of the first and last
 track seeds; then 100 more steps are checked by invariants on every system:
 unit length of magnetic spins, zero at non-magnetic sites, per-system magnetic
-site counts.  Bars: FP64 within 1e-12 per component, FP32 within 1e-4 (the
-FP32 path at every stage against the FP64 oracle).
+site counts.  The track is also run for 100 steps as one graph segment, a
+shift and two more steps, with a seed compared against the oracle at every
+site.  Bars: FP64 within 1e-12 per component, FP32 within 1e-4 (the FP32 path
+at every stage against the FP64 oracle).
 """
 import sys
 
@@ -46,7 +48,7 @@ def gpu():
 def bench_handle(name, prec, tmp_path):
     """The benchmark's handle for a workload, autotuned as bench.py does."""
     w, h, S0s, n_mag, n_sites, extra = bench.build_workload(name, prec, 100)
-    h.autotune(str(tmp_path / f"tune_{name}_{prec}.json"))
+    h.autotune(bench.TUNE_CACHE)  # the tile picks bench.py times
     for k, S0 in enumerate(S0s):
         h.set_spins(S0, k)
     h.set_step(0)
@@ -157,3 +159,38 @@ def test_full_size_track_seeds(prec, tmp_path):
         assert err <= TOL[prec], (k, err)
     check_invariants(h, labs, prec, window=window_mask(w, 1).astype(bool))
     h.close()
+
+
+_LONG = {}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
+def test_full_size_track_seed_100_steps(prec, tmp_path):
+    """The 16-seed track in the benchmark's autotuned variant: 100 steps as one
+    graph segment, a shift of one column, two more steps; the last seed (all
+    2.64M window sites of an 800-column track) against the oracle."""
+    w, h, S0s = bench_handle("track", prec, tmp_path)
+    ins, _ = h._inputs
+    k = len(ins) - 1
+    h.step(100)
+    h.shift_window(1)
+    h.step(2)
+    Sg = h.get_spins(k).astype(np.float64)
+    lab = h.labels(k)
+    h.close()
+    if "S" not in _LONG:
+        olab = oracle_labels(w, seeds=ins[k].seeds)
+        assert np.array_equal(lab, olab)
+        say("  oracle: neighbour shells of the 800-column track ...")
+        sysm = oracle_system(w, labels=olab, ku_grain=ins[k].ku, sys_id=k,
+                             active=window_mask(w, 0), origin=0)
+        S = np.array(S0s[k], np.float64)
+        for n0 in range(0, 100, 10):
+            S = sysm.heun(S, n0, 10)
+            say(f"  oracle step {n0 + 10}/100")
+        sysm.set_active(window_mask(w, 1), 1)
+        _LONG["S"] = sysm.heun(S, 100, 2)
+    err = float(np.max(np.abs(Sg - _LONG["S"])))
+    say(f"  track seed {k}, 102 steps with a shift: max |dS| {err:.3e}")
+    assert err <= TOL[prec], err

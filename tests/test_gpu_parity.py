@@ -499,6 +499,73 @@ def test_batched_uneven_systems_match_single_runs():
         assert st.shape == (5, 5)
 
 
+def _host_moments(sysm, S, acc):
+    """Add one sample of m = |sum S| / N over the oracle system's window (its
+    compensated Eq. 6 sums of the given spins) to acc = [samples, m, m^2, m^4]."""
+    _, tot = sysm.magnetisation(S, 0)
+    m = math.sqrt(tot[0] ** 2 + tot[1] ** 2 + tot[2] ** 2) / tot[3]
+    acc[0] += 1.0
+    acc[1] += m
+    acc[2] += m * m
+    acc[3] += m ** 4
+
+
+@pytest.mark.parametrize("precision", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
+def test_moment_accumulators_match_host_sums(precision):
+    """asd_accumulate_moments every 5 steps, on a track crop with a window shift
+    between samples and on five uneven cylinders each at its own temperature:
+    (samples, sum m, sum m^2, sum m^4) per system against the same sums taken
+    on the host from the GPU's own spins at each sample with the oracle's
+    compensated magnetisation; slot 4 stays 0.  Bar: 1e-12 relative."""
+    w = c5_crop()
+    h, lab, S0 = run_gpu(w, precision, 0, kernel=A.ASD_KERNEL_FUSED)
+    sysm = oracle_system(w, labels=lab, active=window_mask(w, 0), origin=0)
+    acc = np.zeros(4)
+    org = 0
+    for k in range(6):
+        h.step(5)
+        if k == 3:
+            h.shift_window(2)
+            org += 2
+            sysm.set_active(window_mask(w, org), org)
+        h.accumulate_moments(reset=(k == 0))
+        _host_moments(sysm, h.get_spins().astype(np.float64), acc)
+    st = h.moment_stats()
+    say("track moments", st[0], acc)
+    assert st[0, 0] == 6 and st[0, 4] == 0.0
+    np.testing.assert_allclose(st[0, :4], acc, rtol=1e-12, atol=0)
+    # reset starts over
+    h.accumulate_moments(reset=True)
+    acc1 = np.zeros(4)
+    _host_moments(sysm, h.get_spins().astype(np.float64), acc1)
+    np.testing.assert_allclose(h.moment_stats()[0, :4], acc1, rtol=1e-12, atol=0)
+    h.close()
+
+    cyl = W.cylinder_batch(n=5, d_range=(2.0e-9, 4.5e-9), h_range=(1.5e-9, 3.0e-9), T0=500.0,
+                           dT=150.0)
+    w0 = W.Workload("cyl", bc=(0, 0, 0), B=(0.0, 0.0, 0.0), seed=4, alpha=0.1)
+    ins = [bridge.SystemInputs(w0.scaled(nx=c.nx, ny=c.ny, nz=c.nz), labels=c.labels,
+                               T_system=c.T) for c in cyl]
+    h = A.Handle(bridge.params_for(w0, precision), [i.desc for i in ins])
+    dr, _ = bridge.drive_for(w0, T_amb=0.0)
+    h.set_drive(dr)
+    h.set_variant(A.ASD_KERNEL_FUSED, 0)
+    systems = []
+    for k, c in enumerate(cyl):
+        h.set_spins(initial_state(w0, c.labels), k)
+        systems.append(oracle_system(w0.scaled(nx=c.nx, ny=c.ny, nz=c.nz), labels=c.labels))
+    accs = np.zeros((len(cyl), 4))
+    for k in range(8):
+        h.step(5)
+        h.accumulate_moments(reset=(k == 0))
+        for s, sysm in enumerate(systems):
+            _host_moments(sysm, h.get_spins(s).astype(np.float64), accs[s])
+    st = h.moment_stats()
+    assert np.all(st[:, 0] == 8) and np.all(st[:, 4] == 0.0)
+    np.testing.assert_allclose(st[:, :4], accs, rtol=1e-12, atol=0)
+    h.close()
+
+
 @pytest.mark.parametrize("kernel", [A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED])
 def test_graph_capture_equals_eager_and_resume_is_exact(kernel):
 
