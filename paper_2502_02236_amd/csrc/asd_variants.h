@@ -15,20 +15,24 @@ struct FusedVariant {
     int txe, waves, rows, lz;
 };
 
-inline int fused_variant_count(bool fp64) { return fp64 ? 7 : 13; }
+inline int fused_variant_count(bool fp64) { return fp64 ? 9 : 18; }
 
 // Variant 0 is the default before any tuning (narrow tiles, z-chunks of 11:
 // enough workgroups for ~1M-site lattices); the others cover wider tiles for
-// large batches and the R = 2 and 16-lane shapes.
+// large batches and the R = 2 and 16-lane shapes.  The twelve-wave tiles fill
+// a CU with one workgroup at three waves per SIMD (the occupancy of the R = 1
+// kernels' register count), on taller tiles: 32 x 24 extended columns
+// recompute 1.16x the interior where 64 x 8 recompute 1.38x.
 inline FusedVariant fused_variant(bool fp64, int v)
 {
-    static const FusedVariant f32v[13] = {
+    static const FusedVariant f32v[18] = {
         {32, 4, 1, 11}, {64, 4, 2, 0},  {16, 4, 2, 11}, {32, 8, 1, 11}, {32, 4, 1, 17},
         {32, 8, 1, 17}, {32, 8, 1, 0},  {32, 4, 2, 11}, {64, 8, 2, 17}, {16, 4, 1, 11},
-        {16, 8, 1, 11}, {16, 8, 1, 0},  {32, 8, 2, 8}};
-    static const FusedVariant f64v[7] = {{32, 4, 1, 11}, {64, 4, 2, 0},  {32, 8, 1, 17},
+        {16, 8, 1, 11}, {16, 8, 1, 0},  {32, 8, 2, 8},  {32, 12, 1, 0}, {64, 12, 1, 0},
+        {16, 12, 1, 0}, {32, 12, 1, 11}, {32, 6, 1, 0}};
+    static const FusedVariant f64v[9] = {{32, 4, 1, 11}, {64, 4, 2, 0},  {32, 8, 1, 17},
                                          {32, 4, 1, 0},  {32, 8, 1, 11}, {16, 4, 1, 11},
-                                         {32, 4, 2, 11}};
+                                         {32, 4, 2, 11}, {32, 12, 1, 0}, {32, 12, 1, 11}};
     const int n = fused_variant_count(fp64);
     if (v < 0 || v >= n) v = 0;
     return fp64 ? f64v[v] : f32v[v];
