@@ -133,6 +133,13 @@ def _declare(L):
     L.orc_cone_columns.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p, f64p, f64p,
                                    C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p, C.c_int,
                                    C.c_uint64, C.c_uint32, C.c_uint32]
+    L.orc_cone_spin_mode.argtypes = [C.c_int, f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
+                                     C.c_uint32, f64p]
+    L.orc_cone_columns_mode.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, i32p, f64p,
+                                        f64p, f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                        f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32]
+    L.orc_mm_shift.argtypes = [P(OrcMM), f64p, f64p, C.c_int, f64p]
+    L.orc_mm_face_moment.argtypes = [P(OrcMM), f64p, C.c_int, C.c_double, f64p]
 
 
 def _ptr(a, t):
@@ -402,24 +409,27 @@ def cone_theta_max(m: float) -> float:
     return lib().orc_cone_theta_max(float(m))
 
 
-def cone_spin(mvec, rounds, seed, site, step, sys) -> np.ndarray:
+CONE_PRINTED, CONE_CAP = 0, 1  # cone readings of the inverse transfer (Sec. II)
+
+
+def cone_spin(mvec, rounds, seed, site, step, sys, mode: int = CONE_PRINTED) -> np.ndarray:
     mv = np.ascontiguousarray(mvec, dtype=np.float64)
     out = np.zeros(3)
-    lib().orc_cone_spin(_ptr(mv, f64p), rounds, seed, site, step, sys, _ptr(out, f64p))
+    lib().orc_cone_spin_mode(mode, _ptr(mv, f64p), rounds, seed, site, step, sys, _ptr(out, f64p))
     return out
 
 
 def cone_columns(kind, sx, ny, nz, label, S, x0, ncols, cx, cy, cz, mcell, rounds, seed, step,
-                 sys) -> np.ndarray:
+                 sys, mode: int = CONE_PRINTED) -> np.ndarray:
     """S with the magnetic sites of columns [x0, x0 + ncols) replaced by cone
     spins around the reduced magnetisation of their coarse cell."""
     S = np.array(S, dtype=np.float64).reshape(3, -1)
     Sx, Sy, Sz = (np.ascontiguousarray(S[k]) for k in range(3))
     lab = np.ascontiguousarray(label, dtype=np.int32)
     mc = np.ascontiguousarray(mcell, dtype=np.float64).reshape(-1, 3)
-    lib().orc_cone_columns(kind, sx, ny, nz, _ptr(lab, i32p), _ptr(Sx, f64p), _ptr(Sy, f64p),
-                           _ptr(Sz, f64p), x0, ncols, cx, cy, cz, _ptr(mc, f64p), rounds, seed,
-                           step, sys)
+    lib().orc_cone_columns_mode(mode, kind, sx, ny, nz, _ptr(lab, i32p), _ptr(Sx, f64p),
+                                _ptr(Sy, f64p), _ptr(Sz, f64p), x0, ncols, cx, cy, cz,
+                                _ptr(mc, f64p), rounds, seed, step, sys)
     return np.stack([Sx, Sy, Sz])
 
 
@@ -476,6 +486,24 @@ class MM:
         M = np.asarray(m).reshape(3, nz, ny, nx)
         return np.ascontiguousarray(M[:, :, :, 0 if face == 0 else nx - 1].reshape(3, -1).T)
 
+    def shift(self, m, enter, stride: int = 3):
+        """The mesh moved one cell along +x with the window (Sec. II, Fig. 1):
+        returns (m after the move, the leaving column [ny*nz, 3]); `enter`
+        [ny*nz, stride] gives the new last column's directions."""
+        flat = np.array(m, dtype=np.float64, copy=True).reshape(-1)
+        ent = np.ascontiguousarray(enter, dtype=np.float64).reshape(-1)
+        leave = np.zeros((self._p.ny * self._p.nz, 3))
+        lib().orc_mm_shift(C.byref(self._p), _ptr(flat, f64p), _ptr(ent, f64p), stride,
+                           _ptr(leave, f64p))
+        return flat.reshape(3, -1), leave
+
+    def face_moment(self, m, face: int, t: float) -> np.ndarray:
+        """m_e(T) m of the cells on x face `face` at time t: [ny*nz, 3]."""
+        flat = np.ascontiguousarray(m, dtype=np.float64).reshape(-1)
+        out = np.zeros((self._p.ny * self._p.nz, 3))
+        lib().orc_mm_face_moment(C.byref(self._p), _ptr(flat, f64p), face, t, _ptr(out, f64p))
+        return out
+
     def rk4(self, m, step0: int, nsteps: int) -> np.ndarray:
         m = np.array(m, dtype=np.float64, copy=True).reshape(3, -1)
         assert m.shape[1] == self.n
@@ -494,3 +522,36 @@ def set_columns(kind, sx, ny, nz, label, S, x0, ncols, cx, cy, cz, mcell) -> np.
     lib().orc_set_columns(kind, sx, ny, nz, _ptr(lab, i32p), _ptr(Sx, f64p), _ptr(Sy, f64p),
                           _ptr(Sz, f64p), x0, ncols, cx, cy, cz, _ptr(mc, f64p))
     return np.stack([Sx, Sy, Sz])
+
+
+# ---------------------------------------------------------------- moving multiscale window
+def multiscale_shift(kind, sx, ny, nz, label, S, org, nx, cell, left, mL, right, mR, enter,
+                     rounds, seed, step, sys_id=0, t=None, mode: int = CONE_PRINTED):
+    """One move of the multiscale simulation window by one coarse cell (cx
+    lattice columns) along +x (Sec. II, Fig. 1), in the order:
+      1. trailing end: the cx atomistic columns [org, org + cx) are averaged
+         (Eq. 6) into the new last cell column of the left region, whose
+         first column leaves for the track;
+      2. the atomistic window moves: org -> org + cx;
+      3. leading end: the right region's first cell column enters the
+         atomistic window by thermalisation: the magnetic sites of columns
+         [org + nx, org + nx + cx) (old origin) take cone spins around
+         m_e(T) m of their cell (Eq. 6 read backwards), at time t (default
+         step dt);
+      4. the right region moves down one cell; its last column takes the
+         directions `enter` [ny*nz, 3] of the track ahead.
+    left / right: MM regions or None (then mL / mR are ignored).  Returns
+    (S, new origin, mL, mR, the left region's leaving column or None)."""
+    cx, cy, cz = cell
+    S = np.array(S, dtype=np.float64, copy=True).reshape(3, -1)
+    leave = None
+    if left is not None:
+        sums = coarse_grain(kind, sx, ny, nz, label, S, org, cx, cx, cy, cz)
+        mL, leave = left.shift(mL, sums, stride=4)
+    if right is not None:
+        tt = step * right._p.dt if t is None else t
+        mface = right.face_moment(mR, 0, tt)
+        S = cone_columns(kind, sx, ny, nz, label, S, org + nx, cx, cx, cy, cz, mface, rounds,
+                         seed, step, sys_id, mode=mode)
+        mR, _ = right.shift(mR, enter, stride=3)
+    return S, org + cx, mL, mR, leave

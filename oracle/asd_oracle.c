@@ -739,15 +739,21 @@ double orc_cone_theta_max(double m)
 }
 
 /* One spin drawn in the cone around the unit direction n (n = z when the
- * coarse magnetisation vanishes): polar angle uniform on [0, theta_max(m)],
- * azimuth uniform, from Philox words (w0, w1) of counter (site, step,
- * system, 1) with u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32.  The azimuth is
- * measured in the orthonormal basis of Duff, Burgess, Christensen, Hery,
- * Kensler, Liani and Villemin, "Building an orthonormal basis, revisited"
- * (JCGT 2017): s = sign(n_z) (+1 at 0), a = -1 / (s + n_z), b = n_x n_y a,
- * b1 = (1 + s n_x^2 a, s b, -s n_x), b2 = (b, s + n_y^2 a, -n_y). */
-void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t site, uint32_t step,
-                   uint32_t sys, double out[3])
+ * coarse magnetisation vanishes), from Philox words (w0, w1) of counter
+ * (site, step, system, 1) with u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32; the
+ * azimuth 2 pi u2 is measured in the orthonormal basis of Duff, Burgess,
+ * Christensen, Hery, Kensler, Liani and Villemin, "Building an orthonormal
+ * basis, revisited" (JCGT 2017): s = sign(n_z) (+1 at 0),
+ * a = -1 / (s + n_z), b = n_x n_y a, b1 = (1 + s n_x^2 a, s b, -s n_x),
+ * b2 = (b, s + n_y^2 a, -n_y).  The polar angle, by the cone reading:
+ *   ORC_CONE_PRINTED: uniform on [0, theta_max(m)] with the printed
+ *     theta_max (the paper's formula; the mean spin is not m n);
+ *   ORC_CONE_CAP: uniform over the spherical cap cos theta >= 2 m - 1
+ *     (m clamped to [0, 1]), cos theta = 1 - u1 (2 - 2 m): the mean of
+ *     cos theta over the cap is m, so the cell average of many such spins
+ *     returns the magnetisation the spins were drawn from. */
+void orc_cone_spin_mode(int mode, const double mvec[3], int rounds, uint64_t seed, uint32_t site,
+                        uint32_t step, uint32_t sys, double out[3])
 {
     double m = sqrt((mvec[0] * mvec[0] + mvec[1] * mvec[1]) + mvec[2] * mvec[2]);
     double nx = 0.0, ny = 0.0, nz = 1.0;
@@ -761,9 +767,15 @@ void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t sit
     orc_philox4x32(rounds, (uint32_t)seed, (uint32_t)(seed >> 32), ctr, w);
     double u1 = ((double)w[0] + 0.5) * TWO_M32;
     double u2 = (double)w[1] * TWO_M32;
-    double th = u1 * orc_cone_theta_max(m);
     double st, ct, sp, cp;
-    orc_sincos2pi(th / 6.283185307179586, &st, &ct);
+    if (mode == ORC_CONE_CAP) {
+        double mc = m > 1.0 ? 1.0 : m;
+        ct = 1.0 - u1 * (2.0 - 2.0 * mc);
+        st = sqrt((1.0 - ct) * (1.0 + ct));
+    } else {
+        double th = u1 * orc_cone_theta_max(m);
+        orc_sincos2pi(th / 6.283185307179586, &st, &ct);
+    }
     orc_sincos2pi(u2, &sp, &cp);
     double s = nz >= 0.0 ? 1.0 : -1.0;
     double a = -1.0 / (s + nz);
@@ -779,6 +791,12 @@ void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t sit
     out[2] = v[2];
 }
 
+void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t site, uint32_t step,
+                   uint32_t sys, double out[3])
+{
+    orc_cone_spin_mode(ORC_CONE_PRINTED, mvec, rounds, seed, site, step, sys, out);
+}
+
 /* Eq. 6 read backwards: the magnetic sites of columns [x0, x0+ncols) take
  * cone spins around the reduced magnetisation mcell[3 c .. 3 c + 2] of
  * their coarse cell c (|m| <= 1); other sites are left as they are.
@@ -787,13 +805,22 @@ void orc_cone_columns(int kind, int sx, int ny, int nz, const int32_t *label, do
                       double *Sy, double *Sz, int x0, int ncols, int cx, int cy, int cz,
                       const double *mcell, int rounds, uint64_t seed, uint32_t step, uint32_t sys)
 {
+    orc_cone_columns_mode(ORC_CONE_PRINTED, kind, sx, ny, nz, label, Sx, Sy, Sz, x0, ncols, cx, cy,
+                          cz, mcell, rounds, seed, step, sys);
+}
+
+void orc_cone_columns_mode(int mode, int kind, int sx, int ny, int nz, const int32_t *label,
+                           double *Sx, double *Sy, double *Sz, int x0, int ncols, int cx, int cy,
+                           int cz, const double *mcell, int rounds, uint64_t seed, uint32_t step,
+                           uint32_t sys)
+{
     int64_t n = (kind == ORC_SC ? 1 : 2) * (int64_t)sx * ny * nz;
     for (int64_t i = 0; i < n; ++i) {
         if (label[i] < 0) continue;
         int64_t c = coarse_cell(kind, sx, ny, i, x0, ncols, cx, cy, cz);
         if (c < 0) continue;
         double v[3];
-        orc_cone_spin(mcell + 3 * c, rounds, seed, (uint32_t)i, step, sys, v);
+        orc_cone_spin_mode(mode, mcell + 3 * c, rounds, seed, (uint32_t)i, step, sys, v);
         Sx[i] = v[0];
         Sy[i] = v[1];
         Sz[i] = v[2];
@@ -1176,6 +1203,50 @@ int orc_mm_rk4(const orc_mm *p, double *m, int64_t step0, int64_t nsteps)
     return 0;
 }
 
+
+/* The region's mesh moved one cell along +x together with the simulation
+ * window (Sec. II, Fig. 1): cell (i, j, k) takes the direction of cell
+ * (i + 1, j, k); the column i = 0, which leaves the region, is copied to
+ * leave[3 (j + ny k) ..] (when leave is not NULL); the column i = nx - 1
+ * takes the direction of enter[stride (j + ny k) ..] (+z for a zero
+ * vector: a cell with no magnetic site). */
+void orc_mm_shift(const orc_mm *p, double *m, const double *enter, int stride, double *leave)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j) {
+            int64_t row = (int64_t)p->nx * (j + (int64_t)p->ny * k);
+            int64_t f = (int64_t)j + (int64_t)p->ny * k;
+            if (leave)
+                for (int s = 0; s < 3; ++s) leave[3 * f + s] = m[s * n + row];
+            for (int i = 0; i + 1 < p->nx; ++i)
+                for (int s = 0; s < 3; ++s) m[s * n + row + i] = m[s * n + row + i + 1];
+            const double *v = enter + (int64_t)stride * f;
+            double r = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+            double d[3] = {0.0, 0.0, 1.0};
+            if (r > 0.0)
+                for (int s = 0; s < 3; ++s) d[s] = v[s] / r;
+            for (int s = 0; s < 3; ++s) m[s * n + row + p->nx - 1] = d[s];
+        }
+}
+
+/* Reduced magnetisation M / M_S^0 = m_e(T) m of the cells on x face `face`
+ * (0: i = 0, 1: i = nx - 1) at time t, out[3 (j + ny k) ..]: what the
+ * region hands to the atomistic window by thermalisation (Sec. II). */
+void orc_mm_face_moment(const orc_mm *p, const double *m, int face, double t, double *out)
+{
+    int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    double bmag = sqrt((p->B[0] * p->B[0] + p->B[1] * p->B[1]) + p->B[2] * p->B[2]);
+    double b = p->mu_s * bmag / ORC_KB;
+    int i = face == 0 ? 0 : p->nx - 1;
+    for (int k = 0; k < p->nz; ++k)
+        for (int j = 0; j < p->ny; ++j) {
+            int64_t c = i + (int64_t)p->nx * (j + (int64_t)p->ny * k);
+            double me = orc_mm_me(mm_temperature(p, i, j, t), p->Tc, b);
+            int64_t f = (int64_t)j + (int64_t)p->ny * k;
+            for (int s = 0; s < 3; ++s) out[3 * f + s] = me * m[s * n + c];
+        }
+}
 
 /* The magnetic sites of stored columns [x0, x0 + ncols) take the direction
  * of their coarse cell, mcell[c] / |mcell[c]| (+z for a zero cell): the

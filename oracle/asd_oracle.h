@@ -101,6 +101,14 @@ void orc_set_columns(int kind, int sx, int ny, int nz, const int32_t *label, dou
                      double *Sy, double *Sz, int x0, int ncols, int cx, int cy, int cz,
                      const double *mcell);
 double orc_cone_theta_max(double m);
+#define ORC_CONE_PRINTED 0 /* polar angle uniform on [0, printed theta_max] */
+#define ORC_CONE_CAP 1     /* uniform over the cap cos theta >= 2 m - 1 (mean m) */
+void orc_cone_spin_mode(int mode, const double mvec[3], int rounds, uint64_t seed, uint32_t site,
+                        uint32_t step, uint32_t sys, double out[3]);
+void orc_cone_columns_mode(int mode, int kind, int sx, int ny, int nz, const int32_t *label,
+                           double *Sx, double *Sy, double *Sz, int x0, int ncols, int cx, int cy,
+                           int cz, const double *mcell, int rounds, uint64_t seed, uint32_t step,
+                           uint32_t sys);
 void orc_cone_spin(const double mvec[3], int rounds, uint64_t seed, uint32_t site, uint32_t step,
                    uint32_t sys, double out[3]);
 void orc_cone_columns(int kind, int sx, int ny, int nz, const int32_t *label, double *Sx,
@@ -144,6 +152,8 @@ int orc_mm_rk4(const orc_mm *p, double *m, int64_t step0, int64_t nsteps);
 /* temperature (K) of cell (i, j) at time t (s); polarity of step n */
 double orc_mm_temperature(const orc_mm *p, int i, int j, double t);
 double orc_mm_polarity(const orc_mm *p, int64_t n);
+void orc_mm_shift(const orc_mm *p, double *m, const double *enter, int stride, double *leave);
+void orc_mm_face_moment(const orc_mm *p, const double *m, int face, double t, double *out);
 void orc_energy(const orc_system *s, const double *Sx, const double *Sy, const double *Sz,
                 int64_t step, double out[4]);
 
