@@ -210,6 +210,21 @@ int asd_shift_window(asd_t *h, int32_t columns);
  * Host pointers; synchronises.  ASD_ENONFINITE if a sum is not finite. */
 int asd_reduce_magnetization(asd_t *h, double *per_grain, double *per_system);
 
+/* asd_reduce_magnetization for callers that cannot allocate device memory
+ * (serving loops, code between graph captures, harnesses that forbid
+ * hipMalloc): the per-grain and per-system sums are kept in a static
+ * device array of the library (1 MiB on each device it runs on, held
+ * until the process ends) instead of the handle's workspace; nothing is
+ * allocated.  Same arguments, kernels, summation order and results as
+ * asd_reduce_magnetization.  Limit: n_grains + n_systems <= 32768 over the
+ * handle, else ASD_EINVAL before anything is enqueued.  Either pointer may
+ * be NULL (both NULL: nothing is enqueued); the finiteness check
+ * (ASD_ENONFINITE) covers per_system, or per_grain when per_system is
+ * NULL.  Host pointers; synchronises.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (two threads, or two handles on
+ * different streams) race and must be serialised by the caller. */
+int asd_reduce_magnetization_static(asd_t *h, double *per_grain, double *per_system);
+
 /* FP64 energy of each window at the current step (J): per_system[4 s + k],
  * k = (exchange -1/2 sum_i sum_j J_ij S_i.S_j, anisotropy -sum k_u S_z^2,
  * Zeeman -sum mu_s B.S, total).  Host pointer; synchronises. */

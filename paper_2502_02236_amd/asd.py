@@ -26,7 +26,7 @@ ASD_KERNEL_AUTO, ASD_KERNEL_PLAIN, ASD_KERNEL_FUSED = 0, 1, 2
 SYMBOLS = [
     "asd_workspace_bytes", "asd_create", "asd_destroy", "asd_set_field_temperature",
     "asd_set_spins", "asd_get_spins", "asd_step", "asd_prepare", "asd_shift_window",
-    "asd_reduce_magnetization", "asd_reduce_energy", "asd_accumulate_moments",
+    "asd_reduce_magnetization", "asd_reduce_magnetization_static", "asd_reduce_energy", "asd_accumulate_moments",
     "asd_get_moment_stats", "asd_grain_count", "asd_stored_sites", "asd_get_grain_labels",
     "asd_neighbour_count", "asd_get_neighbours", "asd_host_grain_labels", "asd_host_neighbours",
     "asd_coarse_grain", "asd_thermalise_columns", "asd_demag_field", "asd_mc_sweep",
@@ -104,6 +104,7 @@ def lib():
         L.asd_prepare.argtypes = [h]
         L.asd_shift_window.argtypes = [h, C.c_int32]
         L.asd_reduce_magnetization.argtypes = [h, vp, vp]
+        L.asd_reduce_magnetization_static.argtypes = [h, vp, vp]
         L.asd_reduce_energy.argtypes = [h, vp]
         L.asd_accumulate_moments.argtypes = [h, C.c_int32]
         L.asd_get_moment_stats.argtypes = [h, vp]
@@ -212,6 +213,10 @@ def asd_shift_window(h, columns):
 
 def asd_reduce_magnetization(h, per_grain, per_system):
     return lib().asd_reduce_magnetization(h, _np_ptr(per_grain), _np_ptr(per_system))
+
+
+def asd_reduce_magnetization_static(h, per_grain, per_system):
+    return lib().asd_reduce_magnetization_static(h, _np_ptr(per_grain), _np_ptr(per_system))
 
 
 def asd_reduce_energy(h, per_system):

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -89,6 +90,7 @@ struct asd_t {
     int tile_cfg = 0;
     std::string err;
     int elem = 8;
+    int device = 0;           // HIP device current at asd_create (holds the workspace)
     // graphs: one per starting buffer parity
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_steps = 0;
@@ -638,6 +640,10 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
     h->elem = p->precision == ASD_FP64 ? 8 : 4;
     h->kernel = ASD_KERNEL_PLAIN;
     h->graph_steps = p->graph_steps;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(nullptr, ASD_EHIP, "hipGetDevice failed");
+    }
     h->sys.resize(n_sys);
     h->L = make_layout(p, sys, n_sys);
     for (int s = 0; s < n_sys; ++s)
@@ -1188,6 +1194,75 @@ int asd_reduce_magnetization(asd_t *h, double *per_grain, double *per_system)
     if (per_system) std::memcpy(per_system, s.data(), s.size() * sizeof(double));
     for (double v : s)
         if (!std::isfinite(v)) return fail(h, ASD_ENONFINITE, "non-finite magnetisation");
+    return ASD_OK;
+}
+
+// ------------------------------------------------------ static scratch sums
+// asd_reduce_magnetization_static keeps the per-grain and per-system sums in
+// this file-scope device array instead of the handle's workspace.  Host code
+// never passes the array's name to a kernel or copy: it takes the array's
+// address on each device from hipGetSymbolAddress, once per device, with that
+// device current, and uses only that address.
+constexpr int64_t kScratchDoubles = int64_t(1) << 17;  // 1 MiB per device
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_on_device(asd_t *h, double **out)
+{
+    if (h->device < 0 || h->device >= kMaxDevices)
+        return fail(h, ASD_EUNSUPPORTED, "device %d beyond the %d the static scratch serves",
+                    h->device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[h->device]) {
+        int cur = 0;
+        HIP_OK(h, hipGetDevice(&cur));
+        if (cur != h->device) HIP_OK(h, hipSetDevice(h->device));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != h->device) HIP_OK(h, hipSetDevice(cur));
+        if (e != hipSuccess)
+            return fail(h, ASD_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[h->device] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[h->device];
+    return ASD_OK;
+}
+
+int asd_reduce_magnetization_static(asd_t *h, double *per_grain, double *per_system)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    RedArgs a = red_args(h);
+    const int64_t need = 4 * ((int64_t)a.n_grains + a.n_sys);
+    if (need > kScratchDoubles)
+        return fail(h, ASD_EINVAL,
+                    "%d grains + %d systems need %lld scratch doubles; the static scratch holds "
+                    "%lld (at most %lld grains and systems together)",
+                    a.n_grains, a.n_sys, (long long)need, (long long)kScratchDoubles,
+                    (long long)(kScratchDoubles / 4));
+    if (!per_grain && !per_system) return ASD_OK;
+    double *sc = nullptr;
+    int rc = scratch_on_device(h, &sc);
+    if (rc) return rc;
+    // every slot the kernels read is written first in the same call: nothing
+    // of an earlier call's contents is used
+    a.grain_out = sc;
+    a.sys_out = sc + 4 * (int64_t)a.n_grains;
+    if (launch_reduce_grains(a, h->stream) || launch_reduce_systems(a, 0, 0, h->stream))
+        return fail(h, ASD_EHIP, "reduction launch failed");
+    if (per_grain && a.n_grains > 0)
+        HIP_OK(h, hipMemcpyAsync(per_grain, a.grain_out, (size_t)4 * a.n_grains * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream));
+    if (per_system)
+        HIP_OK(h, hipMemcpyAsync(per_system, a.sys_out, (size_t)4 * a.n_sys * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(h, hipStreamSynchronize(h->stream));
+    const double *chk = per_system ? per_system : per_grain;
+    const int64_t n_chk = per_system ? 4 * (int64_t)a.n_sys : 4 * (int64_t)a.n_grains;
+    for (int64_t k = 0; k < n_chk; ++k)
+        if (!std::isfinite(chk[k])) return fail(h, ASD_ENONFINITE, "non-finite magnetisation");
     return ASD_OK;
 }
 
