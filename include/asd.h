@@ -284,9 +284,22 @@ int asd_coarse_grain(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int32_t c
  * u1 = (w0 + 1/2) 2^-32 sets the polar angle, u2 = w1 2^-32 the azimuth.
  * Computed in FP64, stored in the handle precision into both spin buffers
  * (like asd_set_spins).  mcell: caller-owned device pointer, [ncell][3]
- * doubles.  Asynchronous.  ASD_EINVAL as asd_coarse_grain. */
+ * doubles.  Asynchronous.  ASD_EINVAL as asd_coarse_grain.  The polar
+ * angle follows the handle's cone reading (asd_set_cone_reading): the one
+ * above by default. */
 int asd_thermalise_columns(asd_t *h, int32_t sys, int32_t x0, int32_t ncols, int32_t cx,
                            int32_t cy, int32_t cz, const double *mcell, uint32_t step);
+
+/* Cone readings of the inverse transfer (Sec. II).  The printed theta_max
+ * does not give back |m_c| when many cone spins are averaged again (a
+ * polar angle uniform on [0, theta_max] has mean cos = sin(theta_max) /
+ * theta_max); the cap reading draws cos theta uniform on [2 |m_c| - 1, 1]
+ * (|m_c| clamped to [0, 1]), cos theta = 1 - u1 (2 - 2 |m_c|), whose mean
+ * is |m_c|: the averaged spins return the magnetisation they were drawn
+ * from, which is what the angle is there for. */
+#define ASD_CONE_PRINTED 0 /* polar angle uniform on [0, theta_max], the printed formula */
+#define ASD_CONE_CAP 1     /* uniform over the cap cos theta >= 2 |m_c| - 1 */
+int asd_set_cone_reading(asd_t *h, int32_t reading);
 
 /* n Metropolis Monte Carlo sweeps of the same Hamiltonian (exchange,
  * anisotropy, write field with its polarity at the sweep index; no thermal
@@ -429,6 +442,30 @@ int asd_mm_get_face(asd_mm_t *h, int32_t face, double *dirs);
  * the n steps returns at once, after the steps already enqueued. */
 int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
                         int32_t cy, int32_t cz, int64_t n);
+/* Move the multiscale window of asd_multiscale_step by one coarse cell (cx
+ * lattice columns) along +x, the whole simulation region following the
+ * write head (Sec. II, Fig. 1), in this order:
+ *   1. trailing end (left region, if any): the first cx columns of the
+ *      atomistic window, averaged (Eq. 6), give the direction of the
+ *      region's new last cell column (+z for a cell with no magnetic site);
+ *      every other cell takes the direction of its +x neighbour, and the
+ *      first cell column leaves for the track: its directions are copied
+ *      to leave (device, [ny*nz][3] doubles, c = j + ny k) unless NULL;
+ *   2. leading end (right region, if any): the magnetic sites of stored
+ *      columns [origin + nx, origin + nx + cx) take cone spins (Eq. 6 read
+ *      backwards, as asd_thermalise_columns, with the handle's cone
+ *      reading and Philox counter word = the atomistic step counter)
+ *      around m_e(T) m of the region's first cells, m_e(T) at the
+ *      cell temperature at time step * dt (the equilibrium magnetisation
+ *      of the region's M_S(T), Sec. II); then every cell takes the
+ *      direction of its +x neighbour and the last cell column takes the
+ *      directions enter[3 c ..] of the track ahead (device, [ny*nz][3]
+ *      doubles, normalised; a zero vector gives +z);
+ *   3. the atomistic window moves by cx columns (asd_shift_window).
+ * Same region checks as asd_multiscale_step; enter is required with a right
+ * region.  Asynchronous, on the atomistic handle's stream. */
+int asd_multiscale_shift(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                         int32_t cy, int32_t cz, const double *enter, double *leave);
 const char *asd_mm_last_error(const asd_mm_t *h);
 
 const char *asd_strerror(int code);

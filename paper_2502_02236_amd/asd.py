@@ -22,6 +22,7 @@ ASD_SC, ASD_L10 = 0, 1
 ASD_BC_OPEN, ASD_BC_PERIODIC, ASD_BC_TRACK = 0, 1, 2
 ASD_SPOT_NONE, ASD_SPOT_MOVING, ASD_SPOT_LOCKED = 0, 1, 2
 ASD_KERNEL_AUTO, ASD_KERNEL_PLAIN, ASD_KERNEL_FUSED = 0, 1, 2
+ASD_CONE_PRINTED, ASD_CONE_CAP = 0, 1
 
 SYMBOLS = [
     "asd_workspace_bytes", "asd_create", "asd_destroy", "asd_set_field_temperature",
@@ -36,7 +37,8 @@ SYMBOLS = [
     "asd_last_error",
     "asd_mm_workspace_bytes", "asd_mm_create", "asd_mm_destroy", "asd_mm_set_field_temperature",
     "asd_mm_set_m", "asd_mm_get_m", "asd_mm_step", "asd_mm_get_step", "asd_mm_last_error",
-    "asd_mm_set_face", "asd_mm_get_face", "asd_multiscale_step", "asd_set_columns",
+    "asd_mm_set_face", "asd_mm_get_face", "asd_multiscale_step", "asd_multiscale_shift",
+    "asd_set_cone_reading", "asd_set_columns",
     "asd_window_size", "asd_get_stream",
 ]
 
@@ -140,6 +142,9 @@ def lib():
         L.asd_mm_get_face.argtypes = [vp, C.c_int32, vp]
         L.asd_multiscale_step.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32,
                                           C.c_int64]
+        L.asd_multiscale_shift.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32,
+                                           vp, vp]
+        L.asd_set_cone_reading.argtypes = [h, C.c_int32]
         L.asd_set_columns.argtypes = [h, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                       C.c_int32, vp]
         L.asd_window_size.argtypes = [h, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
@@ -368,6 +373,10 @@ class Handle:
                                             step), self.h)
         self.stream.synchronize()
 
+    def set_cone_reading(self, reading: int):
+        """ASD_CONE_PRINTED (default) or ASD_CONE_CAP for the inverse transfer."""
+        _check(lib().asd_set_cone_reading(self.h, reading), self.h)
+
     def mc_sweep(self, n: int):
         """n Metropolis sweeps at each system's ambient temperature."""
         _check(lib().asd_mc_sweep(self.h, n), self.h)
@@ -526,3 +535,22 @@ def multiscale_step(atoms: "Handle", sys: int, left, right, cell, n: int):
                                    right.h if right else None, cell[0], cell[1], cell[2], n)
     if rc != ASD_OK:
         raise AsdError(rc, lib().asd_strerror(rc).decode())
+
+
+def multiscale_shift(atoms: "Handle", sys: int, left, right, cell, enter=None, leave=None):
+    """Move the multiscale window by one coarse cell along +x (asd_multiscale_shift).
+    enter: the right region's new last column [ny*nz, 3] (host array or device
+    tensor); leave: optional float64 device tensor [ny*nz, 3] for the left region's
+    leaving column.  Complete when this returns."""
+    torch = atoms.torch
+    ent = None
+    if enter is not None:
+        ent = torch.as_tensor(enter, dtype=torch.float64, device=atoms.device).contiguous()
+        torch.cuda.current_stream(atoms.device).synchronize()  # the upload is complete
+    rc = lib().asd_multiscale_shift(atoms.h, sys, left.h if left else None,
+                                    right.h if right else None, cell[0], cell[1], cell[2],
+                                    ent.data_ptr() if ent is not None else None,
+                                    leave.data_ptr() if leave is not None else None)
+    if rc != ASD_OK:
+        raise AsdError(rc, lib().asd_strerror(rc).decode())
+    atoms.stream.synchronize()

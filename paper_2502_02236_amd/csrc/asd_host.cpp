@@ -91,6 +91,7 @@ struct asd_t {
     std::string err;
     int elem = 8;
     int device = 0;           // HIP device current at asd_create (holds the workspace)
+    int cone = ASD_CONE_PRINTED;  // reading of the inverse transfer's cone
     // graphs: one per starting buffer parity
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_steps = 0;
@@ -1480,8 +1481,18 @@ int asd_thermalise_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32
     a.k1 = (uint32_t)(h->p.seed >> 32);
     a.step = step;
     a.rounds = h->p.philox_rounds;
+    a.cap = h->cone == ASD_CONE_CAP;
     if (launch_cone_columns(a, h->stream)) return fail(h, ASD_EHIP, "cone launch failed");
     h->stray_dirty = true;
+    return ASD_OK;
+}
+
+int asd_set_cone_reading(asd_t *h, int32_t reading)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (reading != ASD_CONE_PRINTED && reading != ASD_CONE_CAP)
+        return fail(h, ASD_EINVAL, "cone reading must be ASD_CONE_PRINTED or ASD_CONE_CAP");
+    h->cone = reading;
     return ASD_OK;
 }
 
@@ -1566,6 +1577,12 @@ int coarse_grain_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols
     b.out = outb;
     if (launch_coarse_grain_pair(a, b, h->stream)) return fail(h, ASD_EHIP, "coarse-grain launch failed");
     return ASD_OK;
+}
+
+int32_t track_columns(const asd_t *h, int32_t s)
+{
+    if (!h || s < 0 || s >= (int)h->sys.size() || !h->dev[s].track) return 0;
+    return h->dev[s].sx;
 }
 
 int set_columns_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols, int32_t cx,

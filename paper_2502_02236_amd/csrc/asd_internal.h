@@ -188,6 +188,7 @@ struct TransferArgs {
     uint32_t k0, k1, step;    // cone: Philox key and counter word 1
     int32_t rounds;
     int32_t exact;            // 1: each magnetic site takes its cell's direction, no cone
+    int32_t cap;              // cone reading: 0 the printed theta_max, 1 the cap of mean m
 };
 int launch_coarse_grain(const TransferArgs &a, void *stream);
 int launch_cone_columns(const TransferArgs &a, void *stream);

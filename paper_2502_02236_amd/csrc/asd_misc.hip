@@ -368,10 +368,12 @@ __device__ __forceinline__ double cone_theta_max(double m)
 }
 
 // Eq. 6 read backwards (Sec. II): each magnetic site of the columns takes a
-// spin in the cone around its coarse cell's reduced magnetisation: polar
-// angle uniform on [0, theta_max], azimuth uniform, measured in the
-// orthonormal basis of Duff et al. (JCGT 2017) around the cell direction.
-// FP64 throughout; both spin buffers receive the result.
+// spin in the cone around its coarse cell's reduced magnetisation m: polar
+// angle uniform on [0, theta_max] (the printed reading), or cos theta
+// uniform on [2 m - 1, 1] (the cap reading, whose mean cos theta is m);
+// azimuth uniform, measured in the orthonormal basis of Duff et al. (JCGT
+// 2017) around the cell direction.  FP64 throughout; both spin buffers
+// receive the result.
 template <typename T>
 __device__ __forceinline__ void cone_column_site(const TransferArgs &a, int64_t t)
 {
@@ -408,9 +410,15 @@ __device__ __forceinline__ void cone_column_site(const TransferArgs &a, int64_t 
     const double TWO_M32 = 2.3283064365386962890625e-10;
     const double u1 = ((double)w.w0 + 0.5) * TWO_M32;
     const double u2 = (double)w.w1 * TWO_M32;
-    const double th = u1 * cone_theta_max(m);
     double st, ct, sp, cp;
-    f64::sincos2pi(th / 6.283185307179586, st, ct);
+    if (a.cap) {
+        const double mc = m > 1.0 ? 1.0 : m;
+        ct = 1.0 - u1 * (2.0 - 2.0 * mc);
+        st = sqrt((1.0 - ct) * (1.0 + ct));
+    } else {
+        const double th = u1 * cone_theta_max(m);
+        f64::sincos2pi(th / 6.283185307179586, st, ct);
+    }
     f64::sincos2pi(u2, sp, cp);
     const double sg = nz >= 0.0 ? 1.0 : -1.0;
     const double aa = -1.0 / (sg + nz);

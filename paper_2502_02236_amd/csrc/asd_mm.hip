@@ -283,6 +283,54 @@ __global__ void k_mm_get_face_pair(MMArgs a0, int f0, double *d0, MMArgs a1, int
         mm_face_cell<T>(a1, f1, d1, (blockIdx.x - b0) * blockDim.x + threadIdx.x);
 }
 
+// What a region hands to the atomistic window by thermalisation (Sec. II):
+// the reduced magnetisation M / M_S^0 = m_e(T) m of each cell of x face
+// `face` at time t (s), out[3 c ..] with c = j + ny k; T from the spot at the
+// cell centre as in k_mm_params
+template <typename T>
+__global__ void k_mm_face_moment(MMArgs a, int face, double t, double *out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ny * a.nz) return;
+    const int i = face == 0 ? 0 : a.nx - 1, j = c % a.ny;
+    double Tk = a.T_amb;
+    if (a.spot_mode != ASD_SPOT_NONE) {
+        const double xc = a.spot_mode == ASD_SPOT_MOVING ? a.x0 + a.v * t : a.x0;
+        const double dx = ((double)i + 0.5) * a.h[0] - xc;
+        const double dy = ((double)j + 0.5) * a.h[1] - a.y0;
+        const double q = (dx * dx + dy * dy) * a.inv2s2;
+        Tk = a.T_amb + (a.T_peak - a.T_amb) * f64::expn(-q);
+    }
+    const double me = equilibrium_m(Tk, a.Tc, a.b);
+    const int64_t cell = i + (int64_t)a.nx * c;
+    const T *m = (const T *)a.m;
+    for (int d = 0; d < 3; ++d) out[3 * c + d] = me * (double)m[d * (int64_t)a.n + cell];
+}
+
+// The mesh moves one cell along +x with the window (Sec. II, Fig. 1): in each
+// row (j, k) cell i takes the direction of cell i + 1 (rows run in order, so
+// a cell is read before it is overwritten); the first cell's direction is
+// copied to leave[3 c ..] (if given), the last takes enter[stride c ..]
+// normalised (+z for a zero vector: a coarse cell with no magnetic site)
+template <typename T>
+__global__ void k_mm_shift(MMArgs a, const double *enter, int stride, double *leave)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ny * a.nz) return;
+    const int64_t n = a.n, row = (int64_t)a.nx * c;
+    T *m = (T *)a.m;
+    if (leave)
+        for (int d = 0; d < 3; ++d) leave[3 * c + d] = (double)m[d * n + row];
+    for (int i = 0; i + 1 < a.nx; ++i)
+        for (int d = 0; d < 3; ++d) m[d * n + row + i] = m[d * n + row + i + 1];
+    const double *v = enter + (int64_t)stride * c;
+    const double r = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    double e[3] = {0.0, 0.0, 1.0};
+    if (r > 0.0)
+        for (int d = 0; d < 3; ++d) e[d] = v[d] / r;
+    for (int d = 0; d < 3; ++d) m[d * n + row + a.nx - 1] = (T)e[d];
+}
+
 __global__ void k_mm_advance(int64_t *step, int64_t n)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *step += n;
@@ -690,6 +738,24 @@ static int mm_step_pair(asd_mm_t *L, asd_mm_t *R)
     return ASD_OK;
 }
 
+// the checks asd_multiscale_step makes of a region beside the window
+static int region_fits(asd_mm_t *m, double dt, const double edge[3], const int32_t cell[3], int ny,
+                       int nz, void *st)
+{
+    if (std::fabs(m->p.dt - dt) > 1e-9 * dt)
+        return mm_fail(m, ASD_EINVAL, "region dt %g s differs from the atomistic dt %g s", m->p.dt, dt);
+    for (int k = 0; k < 3; ++k)
+        if (std::fabs(m->p.h[k] - cell[k] * edge[k]) > 1e-9 * cell[k] * edge[k])
+            return mm_fail(m, ASD_EINVAL, "region cell edge %d is %g m, not %d lattice cells (%g m)",
+                           k, m->p.h[k], cell[k], cell[k] * edge[k]);
+    if (m->stream != (hipStream_t)st)
+        return mm_fail(m, ASD_EINVAL, "the region must run on the atomistic handle's stream");
+    if (m->p.ny != (ny + cell[1] - 1) / cell[1] || m->p.nz != (nz + cell[2] - 1) / cell[2])
+        return mm_fail(m, ASD_EINVAL, "region ny, nz must equal the window's coarse cells");
+    if (m->p.bc_x == ASD_BC_PERIODIC) return mm_fail(m, ASD_EINVAL, "region x axis is periodic");
+    return ASD_OK;
+}
+
 int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
                         int32_t cy, int32_t cz, int64_t n)
 {
@@ -706,25 +772,10 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
     double dt, edge[3];
     lattice_cell(atoms, &dt, edge);
     const int32_t cell[3] = {cx, cy, cz};
-    asd_mm_t *r[2] = {left, right};
-    for (asd_mm_t *m : r) {
-        if (!m) continue;
-        // one RK4 step of a region per Heun step of the atoms, on cells that
-        // line up with the window's coarse cells
-        if (std::fabs(m->p.dt - dt) > 1e-9 * dt)
-            return mm_fail(m, ASD_EINVAL, "region dt %g s differs from the atomistic dt %g s",
-                           m->p.dt, dt);
-        for (int k = 0; k < 3; ++k)
-            if (std::fabs(m->p.h[k] - cell[k] * edge[k]) > 1e-9 * cell[k] * edge[k])
-                return mm_fail(m, ASD_EINVAL,
-                               "region cell edge %d is %g m, not %d lattice cells (%g m)", k,
-                               m->p.h[k], cell[k], cell[k] * edge[k]);
-        if (m->stream != (hipStream_t)st)
-            return mm_fail(m, ASD_EINVAL, "the region must run on the atomistic handle's stream");
-        if (m->p.ny != (ny + cy - 1) / cy || m->p.nz != (nz + cz - 1) / cz)
-            return mm_fail(m, ASD_EINVAL, "region ny, nz must equal the window's coarse cells");
-        if (m->p.bc_x == ASD_BC_PERIODIC) return mm_fail(m, ASD_EINVAL, "region x axis is periodic");
-    }
+    // one RK4 step of a region per Heun step of the atoms, on cells that line
+    // up with the window's coarse cells
+    for (asd_mm_t *m : {left, right})
+        if (m && (rc = region_fits(m, dt, edge, cell, ny, nz, st))) return rc;
     if (nx < cx || org < cx) return mm_fail(nullptr, ASD_EINVAL, "window too narrow or too close to the track start");
     // both regions in the same precision under a spot that does not move: one
     // launch per RK4 stage for the two
@@ -795,6 +846,69 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
         if (right && (rc = asd_mm_step(right, 1))) return rc;
     }
     return ASD_OK;
+}
+
+int asd_multiscale_shift(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                         int32_t cy, int32_t cz, const double *enter, double *leave)
+{
+    if (!atoms || (!left && !right)) return mm_fail(nullptr, ASD_EINVAL, "need atoms and a region");
+    if (cx < 1 || cy < 1 || cz < 1) return mm_fail(nullptr, ASD_EINVAL, "bad cell");
+    if (right && !enter) return mm_fail(right, ASD_EINVAL, "the right region needs the track ahead");
+    int32_t nx, ny, nz;
+    int rc = asd_window_size(atoms, sys, &nx, &ny, &nz);
+    if (rc) return rc;
+    int64_t step;
+    int32_t org;
+    if ((rc = asd_get_state(atoms, sys, &step, &org))) return rc;
+    void *st = nullptr;
+    if ((rc = asd_get_stream(atoms, &st))) return rc;
+    double dt, edge[3];
+    lattice_cell(atoms, &dt, edge);
+    const int32_t cell[3] = {cx, cy, cz};
+    for (asd_mm_t *m : {left, right})
+        if (m && (rc = region_fits(m, dt, edge, cell, ny, nz, st))) return rc;
+    if (nx < cx) return mm_fail(nullptr, ASD_EINVAL, "window narrower than a coarse cell");
+    // the entering columns and the moved window must lie on the track
+    const int32_t sx = track_columns(atoms, sys);
+    if (sx == 0) return mm_fail(nullptr, ASD_EINVAL, "system %d has no track", sys);
+    if ((int64_t)org + nx + cx > sx)
+        return mm_fail(nullptr, ASD_ESTATE, "the window would leave its track of %d columns", sx);
+    const int nyz = (left ? left : right)->p.ny * (left ? left : right)->p.nz;
+    const int blocks = (nyz + 255) / 256;
+    // 1. trailing end: the leaving atomistic columns, averaged, become the left
+    // region's new last cells
+    if (left) {
+        double *sum = (double *)(left->ws + left->off_fsum);
+        if ((rc = asd_coarse_grain(atoms, sys, org, cx, cx, cy, cz, sum))) return rc;
+        const MMArgs a = mm_args(left, 0);
+        if (left->elem == 8)
+            hipLaunchKernelGGL(k_mm_shift<double>, dim3(blocks), dim3(256), 0, left->stream, a, sum, 4, leave);
+        else
+            hipLaunchKernelGGL(k_mm_shift<float>, dim3(blocks), dim3(256), 0, left->stream, a, sum, 4, leave);
+        MM_HIP(left, hipGetLastError());
+    }
+    // 2. leading end: the right region's first cells enter the atoms by
+    // thermalisation around m_e(T) m, then the region moves down one cell
+    if (right) {
+        double *mface = (double *)(right->ws + right->off_fdir);
+        const MMArgs a = mm_args(right, 0);
+        const double t = (double)step * right->p.dt;
+        if (right->elem == 8) {
+            hipLaunchKernelGGL(k_mm_face_moment<double>, dim3(blocks), dim3(256), 0, right->stream, a, 0, t, mface);
+        } else {
+            hipLaunchKernelGGL(k_mm_face_moment<float>, dim3(blocks), dim3(256), 0, right->stream, a, 0, t, mface);
+        }
+        MM_HIP(right, hipGetLastError());
+        if ((rc = asd_thermalise_columns(atoms, sys, org + nx, cx, cx, cy, cz, mface, (uint32_t)step)))
+            return rc;
+        if (right->elem == 8)
+            hipLaunchKernelGGL(k_mm_shift<double>, dim3(blocks), dim3(256), 0, right->stream, a, enter, 3, nullptr);
+        else
+            hipLaunchKernelGGL(k_mm_shift<float>, dim3(blocks), dim3(256), 0, right->stream, a, enter, 3, nullptr);
+        MM_HIP(right, hipGetLastError());
+    }
+    // 3. the atomistic window moves
+    return asd_shift_window(atoms, cx);
 }
 
 const char *asd_mm_last_error(const asd_mm_t *h) { return h ? h->err.c_str() : g_mm_err.c_str(); }

@@ -21,6 +21,8 @@ int coarse_grain_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols
 // the handle's time step and lattice cell edges (x, y: a; z: a for SC, c for
 // L1_0), for the checks of the multiscale window
 void lattice_cell(const asd_t *h, double *dt, double edge[3]);
+// stored columns of track system s (0 for a system without a track or a bad index)
+int32_t track_columns(const asd_t *h, int32_t s);
 // asd_set_columns of two strips in one launch
 int set_columns_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols, int32_t cx,
                      int32_t cy, int32_t cz, const double *ma, const double *mb);

@@ -63,9 +63,9 @@ def mm_params(w, prec, nx):
     return p
 
 
-def mm_oracle(p):
+def mm_oracle(p, **drive):
     return oracle.MM(n=(p.nx, p.ny, p.nz), h=tuple(p.h), Ms0=p.Ms0, A0=p.A0, K0=p.K0,
-                     lam=p.lambda_, gamma=p.gamma, Tc=p.Tc, mu_s=p.mu_s, dt=p.dt)
+                     lam=p.lambda_, gamma=p.gamma, Tc=p.Tc, mu_s=p.mu_s, dt=p.dt, **drive)
 
 
 def face_dirs(sums):
@@ -166,4 +166,131 @@ def test_multiscale_errors():
         A.multiscale_step(h, 0, Lb, None, CELL, 1)
     A.multiscale_step(h, 0, L, None, CELL, 2)  # the valid pairing still runs
     for x in (L, other, Lb, h):
+        x.close()
+
+
+def oracle_coupled_steps(sysm, oL, oR, S, mL, mR, olab, org, sx, t0, n):
+    """n coupled steps of the oracle from step t0 (the sequence asd_multiscale_step runs)."""
+    cx, cy, cz = CELL
+    for t in range(t0, t0 + n):
+        oL.set_ghost(1, face_dirs(oracle.coarse_grain(W.SC, sx, NYA, NZA, olab, S, org, cx, cx, cy, cz)))
+        oR.set_ghost(0, face_dirs(oracle.coarse_grain(W.SC, sx, NYA, NZA, olab, S, org + NXA - cx,
+                                                      cx, cx, cy, cz)))
+        S = oracle.set_columns(W.SC, sx, NYA, NZA, olab, S, org - cx, cx, cx, cy, cz, oL.face(1, mL))
+        S = oracle.set_columns(W.SC, sx, NYA, NZA, olab, S, org + NXA, cx, cx, cy, cz, oR.face(0, mR))
+        S = sysm.heun(S, t, 1)
+        mL, mR = oL.rk4(mL, t, 1), oR.rk4(mR, t, 1)
+    return S, mL, mR
+
+
+@pytest.mark.parametrize("prec,right_prec,cone,spot",
+                         [(A.ASD_FP64, None, A.ASD_CONE_CAP, False),
+                          (A.ASD_FP64, None, A.ASD_CONE_PRINTED, True),
+                          (A.ASD_FP32, None, A.ASD_CONE_CAP, True),
+                          (A.ASD_FP64, A.ASD_FP32, A.ASD_CONE_CAP, False)],
+                         ids=["fp64_cap", "fp64_printed_spot", "fp32_cap_spot",
+                              "fp64_with_fp32_right_region"])
+def test_moving_multiscale_window_matches_oracle(prec, right_prec, cone, spot):
+    """The whole simulation region of Fig. 1 moves along the track (Sec. II):
+    coupled steps, a move by one coarse cell (the leaving atomistic columns
+    averaged into the left region, the right region's first cells thermalised
+    into the atoms around m_e(T) m, both regions moved down one cell), more
+    coupled steps, a second move, more steps; against the same sequence on the
+    oracle.  Bars as for the static window; the left region's leaving column
+    bit-identical in FP64."""
+    cx, cy, cz = CELL
+    shifts = 2
+    w = atoms_workload(True).scaled(track_nx=NXA + (2 + shifts) * cx)
+    if spot:  # a window-locked laser spot: cell temperatures above and below T_C
+        w = w.scaled(spot_mode=W.SPOT_LOCKED, T_peak=800.0, fwhm=4e-9, x0=NXA * w.a / 2,
+                     y0=NYA * w.a / 2)
+    say(f"[moving multiscale] prec={prec} right={right_prec} cone={cone} spot={spot}")
+    h = bridge.make_handle(w, prec)
+    h.set_cone_reading(cone)
+    h.shift_window(cx)
+    lab = h.labels()
+    S0 = W.initial_spins(len(lab), 6)
+    S0[:, lab < 0] = 0
+    h.set_spins(S0)
+    pl, pr = mm_params(w, prec, 5), mm_params(w, right_prec or prec, 4)
+    L = A.MMHandle(pl, stream=h.stream)
+    R = A.MMHandle(pr, stream=h.stream)
+    dr = A.asd_drive()
+    dr.B[2] = -0.8
+    dr.T_amb = 300.0
+    if spot:
+        dr.spot_mode, dr.T_peak, dr.fwhm = A.ASD_SPOT_LOCKED, 800.0, 4e-9
+        dr.x0, dr.y0 = 2.5 * cx * w.a, NYA * w.a / 2
+    L.set_drive(dr)
+    R.set_drive(dr)
+    mL0, mR0 = random_m(L.n, 3), random_m(R.n, 4)
+    L.set_m(mL0)
+    R.set_m(mR0)
+    rng = np.random.default_rng(7)
+    nyz = pl.ny * pl.nz
+    enters = [random_m(nyz, 10 + k).T.copy() for k in range(shifts)]
+    enters[0][0] = 0.0  # a cell of the track ahead with no magnetic site: +z
+    import torch
+    leaves = []
+    segs = [7, 6, 5]
+    for k, n in enumerate(segs):
+        A.multiscale_step(h, 0, L, R, CELL, n)
+        if k < shifts:
+            lv = torch.zeros((nyz, 3), dtype=torch.float64, device=h.device)
+            A.multiscale_shift(h, 0, L, R, CELL, enter=enters[k], leave=lv)
+            leaves.append(lv.cpu().numpy())
+    gS, gL, gR = h.get_spins(), L.get_m(), R.get_m()
+    assert h.state()[1] == (1 + shifts) * cx
+
+    sx = w.track_nx
+    org = cx
+    olab = oracle_labels(w)
+    sysm = oracle_system(w, labels=olab, active=window_mask(w, org), origin=org)
+    drive = dict(B=(0.0, 0.0, -0.8), T_amb=300.0)
+    if spot:
+        drive.update(spot_mode=oracle.SPOT_LOCKED, T_peak=800.0, fwhm=4e-9, x0=dr.x0, y0=dr.y0)
+    oL, oR = mm_oracle(pl, **drive), mm_oracle(pr, **drive)
+    S, mL, mR = np.array(S0, np.float64), mL0.astype(np.float64), mR0.astype(np.float64)
+    t = 0
+    oleaves = []
+    for k, n in enumerate(segs):
+        S, mL, mR = oracle_coupled_steps(sysm, oL, oR, S, mL, mR, olab, org, sx, t, n)
+        t += n
+        if k < shifts:
+            S, org, mL, mR, lv = oracle.multiscale_shift(
+                W.SC, sx, NYA, NZA, olab, S, org, NXA, CELL, oL, mL, oR, mR, enters[k], 10,
+                w.seed, t, 0, mode=cone)
+            oleaves.append(lv)
+            sysm.set_active(window_mask(w, org), org)
+    dS = float(np.max(np.abs(gS.astype(np.float64) - S)))
+    dL = float(np.max(np.abs(gL.astype(np.float64) - mL)))
+    dR = float(np.max(np.abs(gR.astype(np.float64) - mR)))
+    dV = max(float(np.max(np.abs(a - b))) for a, b in zip(leaves, oleaves))
+    say(f"  max |dS| atoms {dS:.3e}, left {dL:.3e}, right {dR:.3e}, leaving columns {dV:.3e}")
+    fp64 = prec == A.ASD_FP64 and right_prec is None
+    tol_a, tol_m = (1e-12, 1e-12) if fp64 else (1e-4, 2e-5)
+    assert dS <= tol_a and dL <= tol_m and dR <= tol_m and dV <= tol_m
+    # the moves mattered: the window's entering columns came from the right
+    # region (a static window would have kept the track's +z spins there)
+    for x in (L, R, h):
+        x.close()
+
+
+def test_moving_window_errors():
+    w = atoms_workload(False)
+    h = bridge.make_handle(w, A.ASD_FP64)
+    h.shift_window(CELL[0])
+    L = A.MMHandle(mm_params(w, A.ASD_FP64, 3), stream=h.stream)
+    R = A.MMHandle(mm_params(w, A.ASD_FP64, 3), stream=h.stream)
+    with pytest.raises(A.AsdError):  # the right region needs the track ahead
+        A.multiscale_shift(h, 0, None, R, CELL)
+    A.multiscale_shift(h, 0, L, None, CELL)  # origin cx -> 2 cx: the window reaches the track end
+    m_before = L.get_m()
+    with pytest.raises(A.AsdError):  # the window would leave its track: nothing is enqueued
+        A.multiscale_shift(h, 0, L, None, CELL)
+    assert h.state()[1] == 2 * CELL[0]
+    np.testing.assert_array_equal(L.get_m(), m_before)
+    with pytest.raises(A.AsdError):
+        h.set_cone_reading(7)
+    for x in (L, R, h):
         x.close()

@@ -364,6 +364,53 @@ def test_window_end_transfer_matches_oracle(name, w):
         h.close()
 
 
+@pytest.mark.parametrize("name,w", [("sc_track", c5_crop()), ("l10", c3_crop())])
+def test_cap_cone_thermalisation_matches_oracle(name, w):
+    """The cap reading of the inverse transfer (cos theta uniform on
+    [2 m - 1, 1]): bit-identical to the oracle's cap in FP64 and to its FP32
+    rounding in FP32; coarse-graining the thermalised columns again gives back
+    each cell's m along its direction within 5 standard errors of the cap's
+    spread (what the reading is for), where the printed cone gives more."""
+    kind = oracle.SC if w.kind == W.SC else oracle.L10
+    sx = w.track_nx or w.nx
+    per = 1 if w.kind == W.SC else 2
+    rng = np.random.default_rng(15)
+    x0, ncols, cell = 1, sx - 2, (7, 5, 5)
+    for precision in (A.ASD_FP64, A.ASD_FP32):
+        say("cap cone", name, precision)
+        h, lab, _ = run_gpu(w, precision, 5)
+        h.set_cone_reading(A.ASD_CONE_CAP)
+        S = h.get_spins().astype(np.float64)
+        nc = h.coarse_cells(0, ncols, *cell)
+        mcell = rng.normal(size=(nc, 3))
+        mags = rng.uniform(0.3, 0.95, nc)
+        mcell *= (mags / np.linalg.norm(mcell, axis=1))[:, None]
+        h.thermalise_columns(0, x0, ncols, *cell, mcell, 123)
+        Sg = h.get_spins()
+        So = oracle.cone_columns(kind, sx, w.ny, w.nz, lab, S, x0, ncols, *cell, mcell, 10, w.seed,
+                                 123, 0, mode=oracle.CONE_CAP)
+        if precision == A.ASD_FP64:
+            np.testing.assert_array_equal(Sg, So)
+        else:
+            np.testing.assert_array_equal(Sg, So.astype(np.float32))
+        sums = h.coarse_grain(0, x0, ncols, *cell).cpu().numpy()
+        n = sums[:, 3]
+        ok = n >= 20
+        dirs = mcell / mags[:, None]
+        along = np.einsum("ij,ij->i", sums[:, :3], dirs)[ok] / n[ok]
+        sd = (2.0 - 2.0 * mags[ok]) / np.sqrt(12.0)
+        z = (along - mags[ok]) / (sd / np.sqrt(n[ok]))
+        say(f"  cells {ok.sum()}, max |z| = {np.abs(z).max():.2f}")
+        assert np.abs(z).max() < 5.0
+        # the printed cone does not give m back: its average is larger
+        h.set_cone_reading(A.ASD_CONE_PRINTED)
+        h.thermalise_columns(0, x0, ncols, *cell, mcell, 124)
+        sums_p = h.coarse_grain(0, x0, ncols, *cell).cpu().numpy()
+        along_p = np.einsum("ij,ij->i", sums_p[:, :3], dirs)[ok] / n[ok]
+        assert np.mean(along_p - mags[ok]) > 0.02
+        h.close()
+
+
 @pytest.mark.parametrize("x0,ncols,cell", [(4, 3, (1, 1, 1)), (0, 37, (37, 29, 7)),
                                            (6, 11, (5, 40, 9)), (20, 1, (2, 2, 2))],
                          ids=["site_cells", "one_cell_whole_lattice", "cells_beyond_y_z",
