@@ -13,6 +13,7 @@ transfer to and from a coarse grid with cone thermalisation, Sec. II).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -79,7 +80,7 @@ class OrcMM(C.Structure):
         ("dt", C.c_double), ("B", C.c_double * 3), ("n_bits", C.c_int), ("bits", u8p),
         ("steps_per_bit", C.c_int64), ("spot_mode", C.c_int), ("T_amb", C.c_double),
         ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
-        ("v", C.c_double), ("ghost", f64p * 2),
+        ("v", C.c_double), ("ghost", f64p * 2), ("bd", f64p),
     ]
 
 
@@ -466,12 +467,31 @@ class MM:
         self._p = p
         self.n = n[0] * n[1] * n[2]
         self.ghosts = [None, None]
+        self.bd = None
 
     def set_ghost(self, face: int, dirs):
         """Direction [ny*nz, 3] of the region across x face `face` (0: -x, 1: +x)
         seen by the boundary cells' exchange stencil; None removes it."""
         self.ghosts[face] = None if dirs is None else np.ascontiguousarray(dirs, np.float64)
         self._p.ghost[face] = _ptr(self.ghosts[face], f64p)
+
+    def set_field(self, bd):
+        """A field (T) per cell [3, n] added at every RK4 stage and held through
+        the step; None removes it."""
+        self.bd = None if bd is None else np.ascontiguousarray(bd, np.float64).reshape(-1)
+        assert self.bd is None or len(self.bd) == 3 * self.n
+        self._p.bd = _ptr(self.bd, f64p)
+
+    def equilibrium(self, t: float) -> np.ndarray:
+        """m_e(T) of every cell (x fastest) at time t (s), T from the spot."""
+        p = self._p
+        bmag = math.sqrt((p.B[0] * p.B[0] + p.B[1] * p.B[1]) + p.B[2] * p.B[2])
+        b = p.mu_s * bmag / KB
+        me = np.empty(self.n)
+        for c in range(self.n):
+            i, j = c % p.nx, (c // p.nx) % p.ny
+            me[c] = lib().orc_mm_me(self.temperature(i, j, t), p.Tc, b)
+        return me
 
     def temperature(self, i: int, j: int, t: float) -> float:
         """Temperature (K) of cell (i, j) at time t (s)."""
@@ -555,3 +575,48 @@ def multiscale_shift(kind, sx, ny, nz, label, S, org, nx, cell, left, mL, right,
                          seed, step, sys_id, mode=mode)
         mR, _ = right.shift(mR, enter, stride=3)
     return S, org + cx, mL, mR, leave
+
+
+def multiscale_demag(left, mL, sums, ncx_atoms, right, mR, t, dd, mu_s):
+    """Eq. 7 on the multiscale window of Fig. 1 (Sec. II): the left region's
+    cells, the atomistic window's coarse cells and the right region's cells
+    laid along x as one mesh of equal cells of edges dd (NX = nL + ncx_atoms
+    + nR cells along x, x fastest).  Cell magnetisation (A/m): M_S0 m_e(T) m
+    in a region cell (T of the cell at time t), mu_s (sum m) / V in an
+    atomistic cell (sums: [ncell, >= 3] coarse-grain sums of the window,
+    cells x fastest); left / right may be None.  Returns (B_all, B_regions):
+    mu0 H_d in tesla, [3, NX ny nz], from every cell and from the regions'
+    cells alone (Eq. 7 by direct summation)."""
+    some = left if left is not None else right
+    ny, nz = some._p.ny, some._p.nz
+    nL = left._p.nx if left is not None else 0
+    nR = right._p.nx if right is not None else 0
+    NX = nL + ncx_atoms + nR
+    V = (dd[0] * dd[1]) * dd[2]
+    Mall = np.zeros((3, NX * ny * nz))
+    Mreg = np.zeros((3, NX * ny * nz))
+    sums = np.asarray(sums, np.float64)
+    for k in range(nz):
+        for j in range(ny):
+            row = NX * (j + ny * k)
+            for i in range(ncx_atoms):
+                Mall[:, row + nL + i] = mu_s * sums[i + ncx_atoms * (j + ny * k), :3] / V
+            for reg, m, off in ((left, mL, 0), (right, mR, nL + ncx_atoms)):
+                if reg is None:
+                    continue
+                me = reg.equilibrium(t)
+                m = np.asarray(m, np.float64).reshape(3, -1)
+                for i in range(reg._p.nx):
+                    c = i + reg._p.nx * (j + ny * k)
+                    v = reg._p.Ms0 * me[c] * m[:, c]
+                    Mall[:, row + off + i] = v
+                    Mreg[:, row + off + i] = v
+    Ball = MU0 * demag_direct(Mall, NX, ny, nz, *dd)
+    Breg = MU0 * demag_direct(Mreg, NX, ny, nz, *dd)
+    return Ball, Breg
+
+
+def mesh_part(B, NX, ny, nz, x0, nx):
+    """Cells [x0, x0 + nx) along x of a field [3, NX ny nz]: [3, nx ny nz]."""
+    return np.ascontiguousarray(np.asarray(B).reshape(3, nz, ny, NX)[:, :, :, x0:x0 + nx]
+                                .reshape(3, -1))

@@ -1155,6 +1155,8 @@ static void mm_rhs(const orc_mm *p, const double *u, double t, double pol, doubl
         double B[3];
         for (int s = 0; s < 3; ++s) B[s] = cex * lap[s] + pol * p->B[s];
         B[2] = B[2] + can * m[2];
+        if (p->bd)
+            for (int s = 0; s < 3; ++s) B[s] = B[s] + p->bd[s * n + c];
         double f[3];
         ll_rhs(gp, alpha, m, B, f);
         k[c] = f[0];

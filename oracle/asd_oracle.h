@@ -145,6 +145,10 @@ typedef struct orc_mm {
      * taken as the -x (ghost[0]) or +x (ghost[1]) neighbour of the boundary
      * cells of an open face; NULL: no neighbour */
     const double *ghost[2];
+    /* a field (T) per cell [3][n] added to the effective field at every
+     * stage, held through the step (the demagnetising field of the
+     * multiscale window, Sec. II, Eq. 7); NULL: none */
+    const double *bd;
 } orc_mm;
 double orc_langevin(double x);
 double orc_mm_me(double T, double Tc, double b);
