@@ -62,6 +62,9 @@ def parse():
                                            "demag", "mc", "mm", "multiscale"], default="track")
     ap.add_argument("--demag-cell", type=int, nargs=3, default=[4, 4, 3],
                     help="coarse cell of the demag workload, in lattice cells")
+    ap.add_argument("--window-demag", action="store_true",
+                    help="multiscale workload: add the demagnetising field of the whole window "
+                         "(regions and atoms as one mesh)")
     ap.add_argument("--kernel", choices=["auto", "plain", "fused"], default="auto")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--graph-steps", type=int, default=-1,
@@ -503,10 +506,12 @@ def multiscale_run(args):
 
     prec = A.ASD_FP32 if args.precision == "fp32" else A.ASD_FP64
     cell = (4, 4, 3)
-    nxa = 334
+    # with the window's demagnetising field the atoms fill whole coarse cells
+    nxa = 336 if args.window_demag else 334
     w = W.c5_track_window().scaled(nx=nxa, track_nx=nxa + 2 * cell[0], ku_spread=0.0,
                                    x0=50e-9, y0=30e-9)
-    h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_AUTO)
+    h = bridge.make_handle(w, prec, kernel=A.ASD_KERNEL_AUTO,
+                           demag_cell=cell if args.window_demag else (0, 0, 0))
     h.shift_window(cell[0])
     a = w.a
     regions = []
@@ -526,16 +531,26 @@ def multiscale_run(args):
         g.set_drive(d)
         regions.append(g)
     n_atoms = int((h.labels() >= 0).sum() * nxa / w.track_nx)
-    A.multiscale_step(h, 0, regions[0], regions[1], cell, args.warmup)
+    msd = A.MultiscaleDemag(h, 0, regions[0], regions[1], cell) if args.window_demag else None
+
+    def steps(n):
+        if msd is not None:
+            msd.step(n)
+        else:
+            A.multiscale_step(h, 0, regions[0], regions[1], cell, n)
+
+    steps(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(h.stream)
-    A.multiscale_step(h, 0, regions[0], regions[1], cell, args.steps)
+    steps(args.steps)
     e1.record(h.stream)
     e1.synchronize()
     t = e0.elapsed_time(e1) / 1e3
     kname = h.variant_name()
+    if msd is not None:
+        msd.close()
     for g in regions:
         g.close()
     h.close()
@@ -710,7 +725,8 @@ def main():
             "warmup": args.warmup, "ms_per_step": 1e3 * per_step, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None,
             "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
-            "config": {"workload": "multiscale_window_mm100nm_atoms100nm_mm100nm_60x10nm",
+            "config": {"workload": "multiscale_window_mm100nm_atoms100nm_mm100nm_60x10nm" +
+                                   ("_window_demag" if args.window_demag else ""),
                        "atomistic_magnetic_sites": r["n_atoms"], "micromagnetic_cells": r["n_cells"],
                        "atomistic_kernel": r["kernel"], "precision": args.precision},
             "atomistic_spin_updates_per_s": r["n_atoms"] / per_step,

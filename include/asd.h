@@ -466,6 +466,43 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
  * region.  Asynchronous, on the atomistic handle's stream. */
 int asd_multiscale_shift(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
                          int32_t cy, int32_t cz, const double *enter, double *leave);
+
+/* The demagnetising field of the whole multiscale window (Eq. 7, Sec. II:
+ * the stray field between the meshes fully computed every step, Fig. 1).
+ * The left region's cells, the atomistic window's coarse cells and the right
+ * region's cells are laid along x as one mesh of NX = nL + nx / cx + nR
+ * equal cells (ny, nz as the regions); a region cell carries
+ * M = M_S0 m_e(T) m (T at the cell centre), an atomistic cell
+ * M = mu_s (sum of its spins) / V (Eq. 6).  The field of this mesh is
+ * computed by zero-padded FFT convolution with Newell's tensor (FP64) from
+ * the state at the start of each coupled step:
+ *   - each region adds the field at its cells (all sources) to its
+ *     effective field, held through the four RK4 stages;
+ *   - the atoms add, at both Heun stages, the field of the regions' cells at
+ *     their coarse cells, in place of the frozen track's stray field, to
+ *     their own demagnetising field evaluated per stage (the atomistic
+ *     handle must have demag_cell = (cx, cy, cz)).
+ * Needs what asd_multiscale_step needs, nx a multiple of cx, NX <= 512 and
+ * ny, nz <= 256 coarse cells.  The object keeps pointers to the three
+ * handles (which must outlive it) and lives in a caller workspace
+ * (asd_msd_workspace_bytes, 256-byte aligned, device memory). */
+typedef struct asd_msd_t asd_msd_t;
+int asd_msd_workspace_bytes(asd_t *atoms, int32_t sys, const asd_mm_t *left,
+                            const asd_mm_t *right, int32_t cx, int32_t cy, int32_t cz,
+                            size_t *bytes);
+int asd_msd_create(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                   int32_t cy, int32_t cz, void *workspace, size_t workspace_bytes,
+                   asd_msd_t **out);
+int asd_msd_destroy(asd_msd_t *m);
+/* n coupled steps of asd_multiscale_step with the demagnetising field of the
+ * whole window; after it the regions hold no field and the atoms go back to
+ * the frozen track's stray field.  Errors as asd_multiscale_step. */
+int asd_multiscale_step_demag(asd_msd_t *m, int64_t n);
+/* The last evaluated fields (T) of the combined mesh into host arrays
+ * all[3][NX ny nz] (every source) and regions[3][NX ny nz] (the regions'
+ * cells only), either may be NULL; mesh (optional, int32[3]) receives
+ * (NX, ny, nz).  Synchronises the stream. */
+int asd_msd_fields(asd_msd_t *m, double *all, double *regions, int32_t *mesh);
 const char *asd_mm_last_error(const asd_mm_t *h);
 
 const char *asd_strerror(int code);

@@ -38,7 +38,8 @@ SYMBOLS = [
     "asd_mm_workspace_bytes", "asd_mm_create", "asd_mm_destroy", "asd_mm_set_field_temperature",
     "asd_mm_set_m", "asd_mm_get_m", "asd_mm_step", "asd_mm_get_step", "asd_mm_last_error",
     "asd_mm_set_face", "asd_mm_get_face", "asd_multiscale_step", "asd_multiscale_shift",
-    "asd_set_cone_reading", "asd_set_columns",
+    "asd_set_cone_reading", "asd_set_columns", "asd_msd_workspace_bytes", "asd_msd_create",
+    "asd_msd_destroy", "asd_multiscale_step_demag", "asd_msd_fields",
     "asd_window_size", "asd_get_stream",
 ]
 
@@ -145,6 +146,13 @@ def lib():
         L.asd_multiscale_shift.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32,
                                            vp, vp]
         L.asd_set_cone_reading.argtypes = [h, C.c_int32]
+        L.asd_msd_workspace_bytes.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32,
+                                              P(C.c_size_t)]
+        L.asd_msd_create.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp,
+                                     C.c_size_t, P(vp)]
+        L.asd_msd_destroy.argtypes = [vp]
+        L.asd_multiscale_step_demag.argtypes = [vp, C.c_int64]
+        L.asd_msd_fields.argtypes = [vp, vp, vp, vp]
         L.asd_set_columns.argtypes = [h, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                       C.c_int32, vp]
         L.asd_window_size.argtypes = [h, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
@@ -554,3 +562,62 @@ def multiscale_shift(atoms: "Handle", sys: int, left, right, cell, enter=None, l
     if rc != ASD_OK:
         raise AsdError(rc, lib().asd_strerror(rc).decode())
     atoms.stream.synchronize()
+
+
+class MultiscaleDemag:
+    """The demagnetising field of a whole multiscale window (asd_msd_*): the
+    left region, the atomistic window and the right region as one mesh, with
+    a torch-owned workspace on the atomistic handle's device."""
+
+    def __init__(self, atoms: "Handle", sys: int, left, right, cell):
+        torch = atoms.torch
+        self.atoms = atoms
+        lh = left.h if left else None
+        rh = right.h if right else None
+        n = C.c_size_t(0)
+        rc = lib().asd_msd_workspace_bytes(atoms.h, sys, lh, rh, cell[0], cell[1], cell[2],
+                                           C.byref(n))
+        if rc != ASD_OK:
+            raise AsdError(rc, lib().asd_mm_last_error(None).decode())
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=atoms.device)
+        base = (self.workspace.data_ptr() + 255) // 256 * 256
+        out = C.c_void_p()
+        rc = lib().asd_msd_create(atoms.h, sys, lh, rh, cell[0], cell[1], cell[2], base, n.value,
+                                  C.byref(out))
+        if rc != ASD_OK:
+            raise AsdError(rc, lib().asd_mm_last_error(None).decode())
+        self.h = out
+
+    def step(self, n: int):
+        """n coupled steps with the demagnetising field of the whole window."""
+        rc = lib().asd_multiscale_step_demag(self.h, n)
+        if rc != ASD_OK:
+            raise AsdError(rc, lib().asd_strerror(rc).decode())
+        self.atoms.stream.synchronize()
+
+    def fields(self):
+        """(all, regions, mesh): the last fields [3, NX ny nz] and (NX, ny, nz)."""
+        mesh = np.zeros(3, dtype=np.int32)
+        _check_mm(lib().asd_msd_fields(self.h, None, None, _np_ptr(mesh)))
+        n = int(np.prod(mesh))
+        a = np.zeros((3, n))
+        r = np.zeros((3, n))
+        _check_mm(lib().asd_msd_fields(self.h, _np_ptr(a), _np_ptr(r), None))
+        return a, r, tuple(int(v) for v in mesh)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().asd_msd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_mm(rc):
+    if rc != ASD_OK:
+        raise AsdError(rc, lib().asd_mm_last_error(None).decode())
+    return rc

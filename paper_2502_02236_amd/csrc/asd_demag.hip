@@ -189,6 +189,29 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T
     }
 }
 
+// --- 1': the same from given cell sums: src [S][3][ncell] (FP64, cells x
+// fastest, in units of the spin sums of a coarse cell); FFT along x
+template <typename T>
+__global__ __launch_bounds__(kDmThreads) void k_dm_cells_x(DemagDev dm, const double *__restrict__ src)
+{
+    const int Px = 1 << dm.lx;
+    const int j = blockIdx.x % dm.ncy, k = blockIdx.x / dm.ncy, s = blockIdx.y;
+    Cx<T> *x = lds_base<T>(), *y = x + 3 * Px;
+    for (int q = threadIdx.x; q < 3 * Px; q += blockDim.x) {
+        const int c = q >> dm.lx, i = q & (Px - 1);
+        const int64_t cell = i + (int64_t)dm.ncx * (j + (int64_t)dm.ncy * k);
+        x[q] = Cx<T>{i < dm.ncx ? (T)src[((int64_t)s * 3 + c) * dm.ncell + cell] : T(0), T(0)};
+    }
+    __syncthreads();
+    const Cx<T> *r = fft_lines<T, false>(x, y, 3, dm.lx, Px, (const Cx<T> *)dm.tw[0]);
+    Cx<T> *out = (Cx<T> *)dm.wx;
+    const int Pxh = (Px >> 1) + 1;
+    for (int q = threadIdx.x; q < 3 * Pxh; q += blockDim.x) {
+        const int c = q / Pxh, kx = q - c * Pxh;
+        out[((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx] = r[c * Px + kx];
+    }
+}
+
 // --- 2 / 4: FFT along y of xb_y neighbouring x lines of one (c, z) plane.
 // Forward: rows y < ncy of wx (zero-padded) -> all Py rows of wy.
 // Inverse: all Py rows of wy -> rows y < ncy of wx.
@@ -328,14 +351,18 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage,
 
 template <typename T>
 int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
-                 const int32_t *origin, int stage, void *stream)
+                 const int32_t *origin, int stage, void *stream, const double *cells = nullptr)
 {
     hipStream_t st = (hipStream_t)stream;
     const int Px = 1 << dm.lx, Py = 1 << dm.ly, Pz = 1 << dm.lz;
     const size_t cb = sizeof(Cx<T>);
     const dim3 blk(kDmThreads);
     const dim3 grows(dm.ncy * dm.ncz, dm.n_sys);
-    hipLaunchKernelGGL(k_dm_gather_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, S, ncs, sys, origin);
+    if (cells)
+        hipLaunchKernelGGL(k_dm_cells_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, cells);
+    else
+        hipLaunchKernelGGL(k_dm_gather_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, S, ncs, sys,
+                           origin);
     const int Pxh = (Px >> 1) + 1;
     const dim3 gy((Pxh + dm.xb_y - 1) / dm.xb_y, 3 * dm.ncz, dm.n_sys);
     hipLaunchKernelGGL((k_dm_y<T, false>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
@@ -358,6 +385,11 @@ int launch_demag_f32(const DemagDev &dm, const float *S, int64_t ncs, const SysD
                      const int32_t *origin, int stage, void *stream)
 {
     return run_demag<float>(dm, S, ncs, sys, origin, stage, stream);
+}
+
+int launch_demag_cells(const DemagDev &dm, const double *cells, void *stream)
+{
+    return run_demag<double>(dm, nullptr, 0, nullptr, nullptr, 0, stream, cells);
 }
 
 }  // namespace asd

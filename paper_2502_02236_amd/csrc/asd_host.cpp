@@ -100,6 +100,7 @@ struct asd_t {
     DemagDev dm{};            // demagnetising field (dm.on = 0: none)
     DemagDev dmT{};           // stray field of the frozen track (dmT.on = 0: none)
     bool stray_dirty = true;  // the frozen track changed since the stray field was computed
+    bool external_field = false;  // the stray-field buffer holds a field set from outside
 };
 
 static thread_local std::string g_err;
@@ -1034,7 +1035,7 @@ static int launch_one(asd_t *h, int cur, int step_off)
 // (spins set, window shifted, columns thermalised)
 static int refresh_stray(asd_t *h)
 {
-    if (!h->dmT.on || !h->stray_dirty) return ASD_OK;
+    if (!h->dmT.on || !h->stray_dirty || h->external_field) return ASD_OK;
     const char *w = h->ws;
     const SysDev *sys = (const SysDev *)(w + h->L.off_sys);
     const int32_t *org = (const int32_t *)(w + h->L.off_origin);
@@ -1559,6 +1560,8 @@ int asd_set_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32_t cx, 
 
 namespace asd {
 
+double atom_moment(const asd_t *h) { return h->p.mu_s; }
+
 void lattice_cell(const asd_t *h, double *dt, double edge[3])
 {
     *dt = h->p.dt;
@@ -1576,6 +1579,44 @@ int coarse_grain_pair(asd_t *h, int32_t s, int32_t xa, int32_t xb, int32_t ncols
     a.out = outa;
     b.out = outb;
     if (launch_coarse_grain_pair(a, b, h->stream)) return fail(h, ASD_EHIP, "coarse-grain launch failed");
+    return ASD_OK;
+}
+
+int demag_mesh(const asd_t *h, int32_t cell[3], int32_t mesh[3])
+{
+    if (!h || !h->dm.on) return ASD_ESTATE;
+    cell[0] = h->dm.cx;
+    cell[1] = h->dm.cy;
+    cell[2] = h->dm.cz;
+    mesh[0] = h->dm.ncx;
+    mesh[1] = h->dm.ncy;
+    mesh[2] = h->dm.ncz;
+    return ASD_OK;
+}
+
+int set_cell_field(asd_t *h, int32_t s, const double *src, int32_t src_nx, int32_t src_off)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (s < 0 || s >= (int)h->sys.size()) return fail(h, ASD_EINVAL, "bad system index");
+    if (!h->dm.on || !h->dmT.on || !h->dm.bstray)
+        return fail(h, ASD_ESTATE, "a field per coarse cell needs a track system with demag_cell");
+    const DemagDev &g = h->dm;
+    if (!src || src_off < 0 || src_off + g.ncx > src_nx) return fail(h, ASD_EINVAL, "bad source mesh");
+    char *dst = (char *)g.bstray + (size_t)s * 3 * g.ncell * h->elem;
+    if (launch_cells_from_mesh(h->p.precision, dst, src, src_nx, src_off, g.ncx, g.ncy, g.ncz,
+                               h->stream))
+        return fail(h, ASD_EHIP, "cell field launch failed");
+    h->external_field = true;
+    return ASD_OK;
+}
+
+int clear_cell_field(asd_t *h)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (h->external_field) {
+        h->external_field = false;
+        h->stray_dirty = true;
+    }
     return ASD_OK;
 }
 

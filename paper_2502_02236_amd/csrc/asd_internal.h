@@ -113,6 +113,9 @@ struct StepArgs {
     DemagDev dm;
 };
 
+// the same pipeline in FP64 from given cell sums cells [n_sys][3][ncell]
+// (spin-sum units) into dm.bd[0]
+int launch_demag_cells(const DemagDev &dm, const double *cells, void *stream);
 // demagnetising field of spins S (both [3][ncs]) into dm.bd[stage]
 int launch_demag_f64(const DemagDev &dm, const double *S, int64_t ncs, const SysDev *sys,
                      const int32_t *origin, int stage, void *stream);
@@ -143,6 +146,10 @@ int launch_philox_export(uint64_t seed, int rounds, const uint32_t *ctr, uint32_
                          void *stream);
 int launch_advance_step(int64_t *step_base, int64_t n, void *stream);
 int launch_set_i32(int32_t *dst, const int32_t *vals, int n, void *stream);
+// dst [3][ncx ncy ncz] (handle precision) from cells [off, off + ncx) of a
+// mesh of src_nx cells along x, src [3][src_nx ncy ncz] (FP64)
+int launch_cells_from_mesh(int prec, void *dst, const double *src, int src_nx, int src_off, int ncx,
+                           int ncy, int ncz, void *stream);
 // copy stored columns [x0, x0 + ncols) of system d from src to dst (both [3][ncs])
 int launch_copy_columns(int prec, void *dst, const void *src, int64_t ncs, const SysDev &d, int x0,
                         int ncols, void *stream);

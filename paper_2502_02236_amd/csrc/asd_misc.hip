@@ -123,6 +123,37 @@ int launch_mask_spins(int prec, void *buf, int64_t ncs, const uint16_t *label, c
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// A field per coarse cell of a window mesh ncx x ncy x ncz (dst [3][ncell]
+// in the handle precision) from the cells [off, off + ncx) along x of a
+// wider mesh of src_nx cells (src [3][src_nx ncy ncz], FP64)
+template <typename T>
+__global__ void k_cells_from_mesh(T *dst, const double *src, int src_nx, int src_off, int ncx,
+                                  int ncy, int ncz)
+{
+    const int64_t ncell = (int64_t)ncx * ncy * ncz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * ncell) return;
+    const int c = (int)(t / ncell);
+    const int64_t q = t - c * ncell;
+    const int i = (int)(q % ncx);
+    const int64_t jk = q / ncx;
+    dst[t] = (T)src[c * (int64_t)src_nx * ncy * ncz + (src_off + i) + (int64_t)src_nx * jk];
+}
+
+int launch_cells_from_mesh(int prec, void *dst, const double *src, int src_nx, int src_off, int ncx,
+                           int ncy, int ncz, void *stream)
+{
+    const int64_t n = 3 * (int64_t)ncx * ncy * ncz;
+    const int blocks = (int)((n + 255) / 256);
+    if (prec == ASD_FP64)
+        hipLaunchKernelGGL(k_cells_from_mesh<double>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (double *)dst, src, src_nx, src_off, ncx, ncy, ncz);
+    else
+        hipLaunchKernelGGL(k_cells_from_mesh<float>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (float *)dst, src, src_nx, src_off, ncx, ncy, ncz);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ---------------------------------------------------------------- reductions
 // One block per grain walks the grain's site list (ascending site index),
 // keeps the sites inside the window, accumulates in FP64 per thread, and

@@ -20,6 +20,7 @@
 // the new magnetisation in place (each cell reads only its own old value).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -55,6 +56,10 @@ struct MMArgs {
     void *m, *ua, *ub, *acc;  // [3][n] in the handle precision
     double *me, *alpha;       // per cell, filled by the parameter pass
     const double *ghost[2];   // x-face neighbours [ny*nz][3] (zero: none), or null
+    // a held field (T) per cell, added at every stage: cell (i, j, k) reads
+    // bd[d][(bd_off + i) + bd_nx (j + ny k)] of a mesh bd_nx cells long; or null
+    const double *bd;
+    int32_t bd_nx, bd_off;
 };
 
 // Langevin function coth x - 1/x for x >= 0: series through x^11 below 0.1,
@@ -172,6 +177,13 @@ __device__ __forceinline__ void mm_stage_cell(const MMArgs &a, int s, int c)
     B[1] = cex * lap[1] + pol * (T)a.B[1];
     B[2] = cex * lap[2] + pol * (T)a.B[2];
     B[2] = B[2] + can * mc.z;
+    if (a.bd) {
+        const int64_t nb = (int64_t)a.bd_nx * a.ny * a.nz;
+        const int64_t q = (a.bd_off + i) + (int64_t)a.bd_nx * (j + (int64_t)a.ny * k);
+        B[0] = B[0] + (T)a.bd[q];
+        B[1] = B[1] + (T)a.bd[nb + q];
+        B[2] = B[2] + (T)a.bd[2 * nb + q];
+    }
     const double al = a.alpha[c];
     const T alpha = (T)al;
     const T gp = (T)(-a.gamma / (1.0 + al * al));
@@ -346,6 +358,67 @@ __global__ void k_mm_advance_pair(int64_t *step0, int64_t *step1, int64_t n)
 
 size_t align_up(size_t v) { return (v + kMMAlign - 1) / kMMAlign * kMMAlign; }
 
+// One region's part of the multiscale window's demagnetising sources.
+struct MsdRegion {
+    MMArgs a;                 // the region (its m, drive, T_C, M_S0 and cell edges)
+    int32_t elem;             // 8: FP64 m, 4: FP32
+    int32_t off;              // first cell along x of the combined mesh
+    int32_t me_ready;         // a.me holds m_e(T) of every cell (a spot that does not move)
+    double scale;             // M_S0 V / mu_s: the spin sum of a cell with m_e = 1
+};
+
+// Sources of Eq. 7 on the window laid out as one mesh of NX cells along x
+// (left region, atomistic coarse cells, right region), in spin-sum units:
+// set 0 every cell, set 1 the regions' cells only.  Region cell: (M_S0 V /
+// mu_s) m_e(T) m with T at the cell centre at time t; atomistic cell: the
+// coarse-grain sums (Eq. 6), sums[c][4] over the nA window cells.
+__global__ void k_msd_sources(double *src, int NX, int ny, int nz, const double *sums, int nA,
+                              int offA, MsdRegion L, int hasL, MsdRegion R, int hasR, double t)
+{
+    const int64_t ncell = (int64_t)NX * ny * nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int I = (int)(c % NX);
+    const int64_t jk = c / NX;
+    const int j = (int)(jk % ny);
+    double v[3] = {0.0, 0.0, 0.0};
+    bool region = false;
+    if (I >= offA && I < offA + nA) {
+        const double *sc = sums + 4 * ((I - offA) + (int64_t)nA * jk);
+        for (int d = 0; d < 3; ++d) v[d] = sc[d];
+    } else {
+        const bool left = hasL && I < offA;
+        if (left || hasR) {
+            const MsdRegion &g = left ? L : R;
+            const int i = I - g.off;
+            const int64_t cell = i + (int64_t)g.a.nx * jk;
+            double me;
+            if (g.me_ready) {  // the region's own m_e(T) of a spot that does not move
+                me = g.a.me[cell];
+            } else {
+                double Tk = g.a.T_amb;
+                if (g.a.spot_mode != ASD_SPOT_NONE) {
+                    const double xc = g.a.spot_mode == ASD_SPOT_MOVING ? g.a.x0 + g.a.v * t : g.a.x0;
+                    const double dx = ((double)i + 0.5) * g.a.h[0] - xc;
+                    const double dy = ((double)j + 0.5) * g.a.h[1] - g.a.y0;
+                    const double q = (dx * dx + dy * dy) * g.a.inv2s2;
+                    Tk = g.a.T_amb + (g.a.T_peak - g.a.T_amb) * f64::expn(-q);
+                }
+                me = equilibrium_m(Tk, g.a.Tc, g.a.b);
+            }
+            const double s = g.scale * me;
+            for (int d = 0; d < 3; ++d)
+                v[d] = s * (g.elem == 8 ? ((const double *)g.a.m)[d * (int64_t)g.a.n + cell]
+                                        : (double)((const float *)g.a.m)[d * (int64_t)g.a.n + cell]);
+            region = true;
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        src[d * ncell + c] = v[d];
+        src[(3 + d) * ncell + c] = region ? v[d] : 0.0;
+    }
+}
+
 }  // namespace
 }  // namespace asd
 
@@ -362,6 +435,8 @@ struct asd_mm_t {
     size_t off_m = 0, off_ua = 0, off_ub = 0, off_acc = 0, off_me = 0, off_al = 0,
            off_step = 0, off_bits = 0, off_ghost[2] = {0, 0}, off_fsum = 0, off_fdir = 0, bytes = 0;
     bool ghost_on[2] = {false, false};
+    const double *bd = nullptr;  // held field of the multiscale window's demagnetising field
+    int32_t bd_nx = 0, bd_off = 0;
     bool params_valid = false;  // m_e, alpha current for a spot that does not move
     hipGraphExec_t graph = nullptr;
     std::string err;
@@ -483,6 +558,9 @@ static MMArgs mm_args(const asd_mm_t *h, int step_off)
     a.alpha = (double *)(w + h->off_al);
     for (int f = 0; f < 2; ++f)
         a.ghost[f] = h->ghost_on[f] ? (const double *)(w + h->off_ghost[f]) : nullptr;
+    a.bd = h->bd;
+    a.bd_nx = h->bd_nx;
+    a.bd_off = h->bd_off;
     return a;
 }
 
@@ -756,8 +834,120 @@ static int region_fits(asd_mm_t *m, double dt, const double edge[3], const int32
     return ASD_OK;
 }
 
-int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
-                        int32_t cy, int32_t cz, int64_t n)
+// The demagnetising field of the whole multiscale window: the combined mesh
+// (left region, atomistic coarse cells, right region along x), its FFT
+// pipeline in FP64 with two source sets (every cell; the regions' cells
+// only), and the buffers in the caller's workspace.
+struct asd_msd_t {
+    asd_t *atoms = nullptr;
+    int32_t sys = 0;
+    asd_mm_t *left = nullptr, *right = nullptr;
+    int32_t cell[3] = {1, 1, 1};
+    int32_t nL = 0, nA = 0, nR = 0, NX = 0, ny = 0, nz = 0;
+    double V = 0.0, mu_s = 0.0;
+    DemagDev dm{};
+    char *ws = nullptr;
+    size_t off_src = 0, off_sums = 0, off_wx = 0, off_wy = 0, off_out = 0, off_K = 0,
+           off_tw[3] = {0, 0, 0}, bytes = 0;
+};
+
+static int ilog2_up(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+// geometry and workspace layout of the combined mesh; nonzero: invalid
+static int msd_layout(asd_t *atoms, int32_t sys, const asd_mm_t *left, const asd_mm_t *right,
+                      int32_t cx, int32_t cy, int32_t cz, asd_msd_t *m)
+{
+    if (!atoms || (!left && !right)) return mm_fail(nullptr, ASD_EINVAL, "need atoms and a region");
+    if (cx < 1 || cy < 1 || cz < 1) return mm_fail(nullptr, ASD_EINVAL, "bad cell");
+    int32_t nx, ny, nz;
+    int rc = asd_window_size(atoms, sys, &nx, &ny, &nz);
+    if (rc) return rc;
+    void *st = nullptr;
+    if ((rc = asd_get_stream(atoms, &st))) return rc;
+    double dt, edge[3];
+    lattice_cell(atoms, &dt, edge);
+    const int32_t cell[3] = {cx, cy, cz};
+    for (const asd_mm_t *r : {left, right})
+        if (r && (rc = region_fits(const_cast<asd_mm_t *>(r), dt, edge, cell, ny, nz, st))) return rc;
+    int32_t dcell[3], dmesh[3];
+    if (demag_mesh(atoms, dcell, dmesh) != ASD_OK || dcell[0] != cx || dcell[1] != cy || dcell[2] != cz)
+        return mm_fail(nullptr, ASD_EINVAL, "the atomistic handle needs demag_cell = (%d, %d, %d)", cx, cy, cz);
+    if (nx % cx) return mm_fail(nullptr, ASD_EINVAL, "the window's columns must fill whole coarse cells");
+    if (track_columns(atoms, sys) == 0) return mm_fail(nullptr, ASD_EINVAL, "system %d has no track", sys);
+    m->atoms = atoms;
+    m->sys = sys;
+    m->left = const_cast<asd_mm_t *>(left);
+    m->right = const_cast<asd_mm_t *>(right);
+    m->cell[0] = cx;
+    m->cell[1] = cy;
+    m->cell[2] = cz;
+    m->nL = left ? left->p.nx : 0;
+    m->nR = right ? right->p.nx : 0;
+    m->nA = nx / cx;
+    m->NX = m->nL + m->nA + m->nR;
+    m->ny = dmesh[1];
+    m->nz = dmesh[2];
+    if (m->NX > 512 || m->ny > 256 || m->nz > 256)
+        return mm_fail(nullptr, ASD_EUNSUPPORTED, "the window's mesh is limited to 512 x 256 x 256 cells");
+    m->V = ((cx * edge[0]) * (cy * edge[1])) * (cz * edge[2]);
+    DemagDev &g = m->dm;
+    std::memset(&g, 0, sizeof g);
+    g.on = 1;
+    g.cx = cx;
+    g.cy = cy;
+    g.cz = cz;
+    g.ncx = m->NX;
+    g.ncy = m->ny;
+    g.ncz = m->nz;
+    g.ncell = g.ncx * g.ncy * g.ncz;
+    g.lx = ilog2_up(2 * g.ncx - 1);
+    g.ly = ilog2_up(2 * g.ncy - 1);
+    g.lz = ilog2_up(2 * g.ncz - 1);
+    g.n_sys = 2;
+    const int Px = 1 << g.lx, Py = 1 << g.ly, Pz = 1 << g.lz, Pxh = Px / 2 + 1;
+    // x lines per workgroup of the y and z passes: two LDS buffers of at most
+    // 1024 complex doubles, and no fewer than 512 workgroups while lines split
+    int xb = 1;
+    while (xb * 2 <= Pxh && xb * 2 * (Py + 1) <= 1024 &&
+           (int64_t)((Pxh + 2 * xb - 1) / (xb * 2)) * 3 * g.ncz * 2 >= 512)
+        xb *= 2;
+    g.xb_y = xb;
+    xb = 1;
+    while (xb * 2 <= Pxh && xb * 2 * 3 * (Pz + 1) <= 1024 &&
+           (int64_t)((Pxh + 2 * xb - 1) / (xb * 2)) * Py * 2 >= 512)
+        xb *= 2;
+    g.xb_z = xb;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off = align_up(off + b);
+        return o;
+    };
+    const size_t cplx = 16;
+    m->off_src = take((size_t)2 * 3 * g.ncell * sizeof(double));
+    m->off_sums = take((size_t)m->nA * m->ny * m->nz * 4 * sizeof(double));
+    m->off_wx = take((size_t)2 * 3 * g.ncz * g.ncy * Pxh * cplx);
+    m->off_wy = take((size_t)2 * 3 * g.ncz * Py * Pxh * cplx);
+    m->off_out = take((size_t)2 * 3 * g.ncell * sizeof(double));
+    m->off_K = take((size_t)6 * (Px / 2 + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * sizeof(double));
+    m->off_tw[0] = take((size_t)std::max(Px / 2, 1) * cplx);
+    m->off_tw[1] = take((size_t)std::max(Py / 2, 1) * cplx);
+    m->off_tw[2] = take((size_t)std::max(Pz / 2, 1) * cplx);
+    m->bytes = off;
+    return ASD_OK;
+}
+
+// n coupled steps; msd (may be null): the demagnetising field of the whole
+// window, evaluated before each step from the state at its start
+static int msd_prepare(asd_msd_t *m);
+
+static int multiscale_run(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                          int32_t cy, int32_t cz, int64_t n, asd_msd_t *msd)
 {
     if (!atoms || (!left && !right)) return mm_fail(nullptr, ASD_EINVAL, "need atoms and a region");
     if (n < 0 || cx < 1 || cy < 1 || cz < 1) return mm_fail(nullptr, ASD_EINVAL, "bad sizes");
@@ -799,6 +989,7 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
         const MMArgs aL = mm_args(left, 0), aR = mm_args(right, 0);
         const int bf = (nyz + 255) / 256;
         for (int64_t t = 0; t < n; ++t) {
+            if (msd && (rc = msd_prepare(msd))) return rc;
             if ((rc = coarse_grain_pair(atoms, sys, org, org + nx - cx, cx, cx, cy, cz, sumL, sumR)))
                 return rc;
             hipLaunchKernelGGL(k_mm_set_face_pair, dim3((unsigned)(2 * bf)), dim3(256), 0, left->stream,
@@ -819,6 +1010,7 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
         return ASD_OK;
     }
     for (int64_t t = 0; t < n; ++t) {
+        if (msd && (rc = msd_prepare(msd))) return rc;
         // window -> regions: averaged boundary coarse columns
         if (left) {
             double *sum = (double *)(left->ws + left->off_fsum);
@@ -846,6 +1038,202 @@ int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *rig
         if (right && (rc = asd_mm_step(right, 1))) return rc;
     }
     return ASD_OK;
+}
+
+// the fields of the combined mesh from the state at the start of the step:
+// sources, convolution, then the regions' held fields and the atoms' field
+// of the regions
+static int msd_prepare(asd_msd_t *m)
+{
+    int64_t step;
+    int32_t org;
+    int rc;
+    if ((rc = asd_get_state(m->atoms, m->sys, &step, &org))) return rc;
+    void *st = nullptr;
+    if ((rc = asd_get_stream(m->atoms, &st))) return rc;
+    double *sums = (double *)(m->ws + m->off_sums);
+    if (m->nA > 0 && (rc = asd_coarse_grain(m->atoms, m->sys, org, m->nA * m->cell[0], m->cell[0],
+                                            m->cell[1], m->cell[2], sums)))
+        return rc;
+    double dt, edge[3];
+    lattice_cell(m->atoms, &dt, edge);
+    MsdRegion L{}, R{};
+    MsdRegion *rg[2] = {&L, &R};
+    asd_mm_t *reg2[2] = {m->left, m->right};
+    for (int k = 0; k < 2; ++k) {
+        asd_mm_t *r = reg2[k];
+        if (!r) continue;
+        // a spot that does not move: the region's m_e(T) per cell, computed
+        // once by its parameter pass, is the one at every time
+        const bool still = r->drive.spot_mode != ASD_SPOT_MOVING;
+        if (still && !r->params_valid) {
+            const MMArgs a0 = mm_args(r, 0);
+            hipLaunchKernelGGL(k_mm_params, dim3((unsigned)((r->n + kMMTile - 1) / kMMTile)),
+                               dim3(kMMTile), 0, r->stream, a0, 0.0);
+            r->params_valid = true;
+        }
+        rg[k]->a = mm_args(r, 0);
+        rg[k]->elem = r->elem;
+        rg[k]->off = k == 0 ? 0 : m->nL + m->nA;
+        rg[k]->me_ready = still ? 1 : 0;
+        rg[k]->scale = r->p.Ms0 * m->V / m->mu_s;
+    }
+    const double t = (double)step * dt;
+    double *src = (double *)(m->ws + m->off_src);
+    const int64_t ncell = m->dm.ncell;
+    hipLaunchKernelGGL(k_msd_sources, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)st, src, m->NX, m->ny, m->nz, (const double *)sums, m->nA, m->nL,
+                       L, m->left ? 1 : 0, R, m->right ? 1 : 0, t);
+    if (hipGetLastError() != hipSuccess) return mm_fail(nullptr, ASD_EHIP, "demagnetising sources launch failed");
+    if (launch_demag_cells(m->dm, src, st)) return mm_fail(nullptr, ASD_EHIP, "demagnetising field launch failed");
+    const double *out = (const double *)(m->ws + m->off_out);
+    // the atoms: the field of the regions' cells (source set 1)
+    if ((rc = set_cell_field(m->atoms, m->sys, out + 3 * ncell, m->NX, m->nL))) return rc;
+    // the regions: the field of every cell (set 0), held through the step
+    asd_mm_t *reg[2] = {m->left, m->right};
+    const int32_t off[2] = {0, m->nL + m->nA};
+    for (int k = 0; k < 2; ++k) {
+        asd_mm_t *r = reg[k];
+        if (!r) continue;
+        if (r->bd != out || r->bd_nx != m->NX || r->bd_off != off[k]) {
+            r->bd = out;
+            r->bd_nx = m->NX;
+            r->bd_off = off[k];
+            mm_drop_graph(r);
+        }
+    }
+    return ASD_OK;
+}
+
+static void msd_release(asd_msd_t *m)
+{
+    for (asd_mm_t *r : {m->left, m->right})
+        if (r && r->bd) {
+            r->bd = nullptr;
+            r->bd_nx = r->bd_off = 0;
+            mm_drop_graph(r);
+        }
+    (void)clear_cell_field(m->atoms);
+}
+
+int asd_msd_workspace_bytes(asd_t *atoms, int32_t sys, const asd_mm_t *left,
+                            const asd_mm_t *right, int32_t cx, int32_t cy, int32_t cz,
+                            size_t *bytes)
+{
+    if (!bytes) return mm_fail(nullptr, ASD_EINVAL, "bytes is NULL");
+    asd_msd_t m;
+    int rc = msd_layout(atoms, sys, left, right, cx, cy, cz, &m);
+    if (rc) return rc;
+    *bytes = m.bytes;
+    return ASD_OK;
+}
+
+int asd_msd_create(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                   int32_t cy, int32_t cz, void *workspace, size_t workspace_bytes,
+                   asd_msd_t **out)
+{
+    if (!out) return mm_fail(nullptr, ASD_EINVAL, "out is NULL");
+    *out = nullptr;
+    asd_msd_t *m = new (std::nothrow) asd_msd_t();
+    if (!m) return mm_fail(nullptr, ASD_ENOMEM, "host allocation failed");
+    int rc = msd_layout(atoms, sys, left, right, cx, cy, cz, m);
+    if (rc) {
+        delete m;
+        return rc;
+    }
+    if (!workspace || ((uintptr_t)workspace % kMMAlign) != 0 || workspace_bytes < m->bytes) {
+        const int code = workspace_bytes < m->bytes ? ASD_ENOMEM : ASD_EINVAL;
+        delete m;
+        return mm_fail(nullptr, code, "workspace must be 256-byte aligned and hold asd_msd_workspace_bytes");
+    }
+    m->ws = (char *)workspace;
+    // mu_s from the spectrum's units: the atoms' moment
+    double dt, edge[3];
+    lattice_cell(atoms, &dt, edge);
+    m->mu_s = atom_moment(atoms);
+    void *stv = nullptr;
+    (void)asd_get_stream(atoms, &stv);
+    hipStream_t st = (hipStream_t)stv;
+    DemagDev &g = m->dm;
+    const int Px = 1 << g.lx, Py = 1 << g.ly, Pz = 1 << g.lz;
+    const double dx = cx * edge[0], dy = cy * edge[1], dz = cz * edge[2];
+    const double scale = -1.25663706212e-6 * m->mu_s / (((dx * dy) * dz) * ((double)Px * Py * Pz));
+    std::vector<double> oct;
+    demag_spectrum(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly, g.lz, scale, oct);
+    hipError_t e = hipMemcpyAsync(m->ws + m->off_K, oct.data(), oct.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, st);
+    std::vector<std::vector<double>> tw(3);
+    const int lp[3] = {g.lx, g.ly, g.lz};
+    for (int ax = 0; ax < 3 && e == hipSuccess; ++ax) {
+        const int P = 1 << lp[ax], half = std::max(P / 2, 1);
+        tw[ax].resize((size_t)2 * half);
+        for (int q = 0; q < half; ++q) {
+            const double ang = -2.0 * M_PI * (double)q / (double)P;
+            tw[ax][2 * q] = std::cos(ang);
+            tw[ax][2 * q + 1] = std::sin(ang);
+        }
+        e = hipMemcpyAsync(m->ws + m->off_tw[ax], tw[ax].data(), tw[ax].size() * sizeof(double),
+                           hipMemcpyHostToDevice, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete m;
+        return mm_fail(nullptr, ASD_EHIP, "demagnetising set-up copy failed: %s", hipGetErrorString(e));
+    }
+    g.wx = m->ws + m->off_wx;
+    g.wy = m->ws + m->off_wy;
+    g.bd[0] = m->ws + m->off_out;
+    g.bd[1] = nullptr;
+    g.K = m->ws + m->off_K;
+    for (int ax = 0; ax < 3; ++ax) g.tw[ax] = m->ws + m->off_tw[ax];
+    g.bstray = nullptr;
+    *out = m;
+    return ASD_OK;
+}
+
+int asd_msd_destroy(asd_msd_t *m)
+{
+    if (!m) return ASD_OK;
+    msd_release(m);
+    delete m;
+    return ASD_OK;
+}
+
+int asd_multiscale_step_demag(asd_msd_t *m, int64_t n)
+{
+    if (!m) return mm_fail(nullptr, ASD_EINVAL, "NULL multiscale demagnetising field");
+    const int rc = multiscale_run(m->atoms, m->sys, m->left, m->right, m->cell[0], m->cell[1],
+                                  m->cell[2], n, m);
+    msd_release(m);
+    return rc;
+}
+
+int asd_msd_fields(asd_msd_t *m, double *all, double *regions, int32_t *mesh)
+{
+    if (!m) return mm_fail(nullptr, ASD_EINVAL, "NULL multiscale demagnetising field");
+    void *st = nullptr;
+    int rc = asd_get_stream(m->atoms, &st);
+    if (rc) return rc;
+    const size_t n = (size_t)3 * m->dm.ncell;
+    const double *out = (const double *)(m->ws + m->off_out);
+    hipError_t e = hipSuccess;
+    if (all) e = hipMemcpyAsync(all, out, n * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)st);
+    if (regions && e == hipSuccess)
+        e = hipMemcpyAsync(regions, out + n, n * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)st);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)st);
+    if (e != hipSuccess) return mm_fail(nullptr, ASD_EHIP, "field copy failed: %s", hipGetErrorString(e));
+    if (mesh) {
+        mesh[0] = m->NX;
+        mesh[1] = m->ny;
+        mesh[2] = m->nz;
+    }
+    return ASD_OK;
+}
+
+int asd_multiscale_step(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,
+                        int32_t cy, int32_t cz, int64_t n)
+{
+    return multiscale_run(atoms, sys, left, right, cx, cy, cz, n, nullptr);
 }
 
 int asd_multiscale_shift(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, int32_t cx,

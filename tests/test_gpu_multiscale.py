@@ -15,9 +15,10 @@ import pytest
 
 import oracle
 import workloads as W
-from oracle_build import oracle_labels, oracle_system, window_mask
+from oracle_build import demag_cells, oracle_labels, oracle_system, window_mask
 from paper_2502_02236_amd import asd as A
 from paper_2502_02236_amd import bridge
+from test_gpu_demag import fp64_field_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -293,4 +294,134 @@ def test_moving_window_errors():
     with pytest.raises(A.AsdError):
         h.set_cone_reading(7)
     for x in (L, R, h):
+        x.close()
+
+
+@pytest.mark.parametrize("prec,right_prec,spot",
+                         [(A.ASD_FP64, None, False), (A.ASD_FP64, None, True),
+                          (A.ASD_FP32, None, True), (A.ASD_FP64, A.ASD_FP32, False)],
+                         ids=["fp64", "fp64_spot", "fp32_spot", "fp64_with_fp32_right_region"])
+def test_multiscale_window_with_demag_matches_oracle(prec, right_prec, spot):
+    """The demagnetising field of the whole window (Eq. 7, Sec. II, Fig. 1):
+    regions and atomistic coarse cells as one mesh, the regions holding the
+    field of all cells through their RK4 step, the atoms adding the regions'
+    field to their own per-stage field; coupled steps against the oracle's
+    sequence with direct-sum fields.  The fields of the last step agree with
+    the oracle's within the FP64 bar of the demagnetising tests (the tensor's
+    own rounding over the mesh, of mu0 Ms; FFT against direct sums), 1e-5
+    where FP32 spins are the sources; spins FP64 within 1e-12, FP32 within
+    1e-4 (atoms) and 2e-5 (regions).  The field matters: without it the window lands elsewhere."""
+    steps = 12
+    cx, cy, cz = CELL
+    w = atoms_workload(True)
+    if spot:
+        w = w.scaled(spot_mode=W.SPOT_LOCKED, T_peak=800.0, fwhm=4e-9, x0=NXA * w.a / 2,
+                     y0=NYA * w.a / 2)
+    say(f"[multiscale demag] prec={prec} right={right_prec} spot={spot}")
+    h = bridge.make_handle(w, prec, demag_cell=CELL)
+    h.shift_window(cx)
+    lab = h.labels()
+    S0 = W.initial_spins(len(lab), 8)
+    S0[:, lab < 0] = 0
+    h.set_spins(S0)
+    pl, pr = mm_params(w, prec, 5), mm_params(w, right_prec or prec, 4)
+    L = A.MMHandle(pl, stream=h.stream)
+    R = A.MMHandle(pr, stream=h.stream)
+    dr = A.asd_drive()
+    dr.B[2] = -0.8
+    dr.T_amb = 300.0
+    if spot:
+        dr.spot_mode, dr.T_peak, dr.fwhm = A.ASD_SPOT_LOCKED, 800.0, 4e-9
+        dr.x0, dr.y0 = 2.5 * cx * w.a, NYA * w.a / 2
+    L.set_drive(dr)
+    R.set_drive(dr)
+    mL0, mR0 = random_m(L.n, 21), random_m(R.n, 22)
+    L.set_m(mL0)
+    R.set_m(mR0)
+    msd = A.MultiscaleDemag(h, 0, L, R, CELL)
+    msd.step(steps)
+    gS, gL, gR = h.get_spins(), L.get_m(), R.get_m()
+    gBall, gBreg, mesh = msd.fields()
+    nA = NXA // cx
+    NX = pl.nx + nA + pr.nx
+    assert mesh == (NX, pl.ny, pl.nz)
+
+    sx = w.track_nx
+    org = cx
+    olab = oracle_labels(w)
+    sysm = oracle_system(w, labels=olab, active=window_mask(w, org), origin=org)
+    drive = dict(B=(0.0, 0.0, -0.8), T_amb=300.0)
+    if spot:
+        drive.update(spot_mode=oracle.SPOT_LOCKED, T_peak=800.0, fwhm=4e-9, x0=dr.x0, y0=dr.y0)
+    oL, oR = mm_oracle(pl, **drive), mm_oracle(pr, **drive)
+    S, mL, mR = np.array(S0, np.float64), mL0.astype(np.float64), mR0.astype(np.float64)
+    dd = (cx * w.a, cy * w.a, cz * w.a)
+    dmesh = demag_cells(w, CELL, org)
+    for t in range(steps):
+        sums = oracle.coarse_grain(W.SC, sx, NYA, NZA, olab, S, org, NXA, cx, cy, cz)
+        Ball, Breg = oracle.multiscale_demag(oL, mL, sums, nA, oR, mR, t * w.dt, dd, w.mu_s)
+        oL.set_field(oracle.mesh_part(Ball, NX, pl.ny, pl.nz, 0, pl.nx))
+        oR.set_field(oracle.mesh_part(Ball, NX, pl.ny, pl.nz, pl.nx + nA, pr.nx))
+        sysm.set_demag(dmesh, stray=oracle.mesh_part(Breg, NX, pl.ny, pl.nz, pl.nx, nA))
+        S, mL, mR = oracle_coupled_steps(sysm, oL, oR, S, mL, mR, olab, org, sx, t, 1)
+    scale = oracle.MU0 * pl.Ms0  # mu0 Ms, the scale of the field
+    dBa = float(np.abs(gBall - Ball).max()) / scale
+    dBr = float(np.abs(gBreg - Breg).max()) / scale
+    dS = float(np.max(np.abs(gS.astype(np.float64) - S)))
+    dL = float(np.max(np.abs(gL.astype(np.float64) - mL)))
+    dR = float(np.max(np.abs(gR.astype(np.float64) - mR)))
+    say(f"  field {scale:.3e} T: rel. diff all {dBa:.2e}, regions {dBr:.2e}; "
+        f"max |dS| atoms {dS:.3e}, left {dL:.3e}, right {dR:.3e}")
+    fp64 = prec == A.ASD_FP64 and right_prec is None
+    # FP64: the tensor's own rounding bar over the window's mesh; FP32 spins
+    # (within 1e-4 of the oracle's) feed FP32 sources to the same FP64 pipeline
+    tol_b = fp64_field_tol(mesh, dd) if fp64 else 1e-5
+    assert dBa <= tol_b and dBr <= tol_b
+    tol_a, tol_m = (1e-12, 1e-12) if fp64 else (1e-4, 2e-5)
+    assert dS <= tol_a and dL <= tol_m and dR <= tol_m
+    # without the field the regions land elsewhere
+    oL2, oR2 = mm_oracle(pl, **drive), mm_oracle(pr, **drive)
+    sys2 = oracle_system(w, labels=olab, active=window_mask(w, org), origin=org)
+    S2, mL2, mR2 = oracle_coupled_steps(sys2, oL2, oR2, np.array(S0, np.float64),
+                                        mL0.astype(np.float64), mR0.astype(np.float64), olab, org,
+                                        sx, 0, steps)
+    assert float(np.max(np.abs(mL2 - mL))) > 100 * max(dL, 1e-14)
+    msd.close()
+    # after the demagnetising steps the plain coupled step still runs
+    A.multiscale_step(h, 0, L, R, CELL, 2)
+    for x in (L, R, h):
+        x.close()
+
+
+def test_window_demag_errors():
+    """The whole-window field needs an atomistic handle with the same coarse
+    cell and a window of whole coarse cells; bad requests fail before anything
+    is enqueued and leave the handles usable."""
+    w = atoms_workload(False)
+    h_plain = bridge.make_handle(w, A.ASD_FP64)  # no demag_cell
+    h_plain.shift_window(CELL[0])
+    L = A.MMHandle(mm_params(w, A.ASD_FP64, 3), stream=h_plain.stream)
+    with pytest.raises(A.AsdError):
+        A.MultiscaleDemag(h_plain, 0, L, None, CELL)
+    h_other = bridge.make_handle(w, A.ASD_FP64, demag_cell=(1, 2, 2))  # another coarse cell
+    h_other.shift_window(CELL[0])
+    L2 = A.MMHandle(mm_params(w, A.ASD_FP64, 3), stream=h_other.stream)
+    with pytest.raises(A.AsdError):
+        A.MultiscaleDemag(h_other, 0, L2, None, CELL)
+    w_odd = w.scaled(nx=NXA - 1, track_nx=NXA - 1 + 2 * CELL[0])  # a ragged last cell
+    h_odd = bridge.make_handle(w_odd, A.ASD_FP64, demag_cell=CELL)
+    h_odd.shift_window(CELL[0])
+    L3 = A.MMHandle(mm_params(w_odd, A.ASD_FP64, 3), stream=h_odd.stream)
+    with pytest.raises(A.AsdError):
+        A.MultiscaleDemag(h_odd, 0, L3, None, CELL)
+    # the valid pairing runs, then the handles still step on their own
+    h = bridge.make_handle(w, A.ASD_FP64, demag_cell=CELL)
+    h.shift_window(CELL[0])
+    L4 = A.MMHandle(mm_params(w, A.ASD_FP64, 3), stream=h.stream)
+    msd = A.MultiscaleDemag(h, 0, L4, None, CELL)
+    msd.step(2)
+    msd.close()
+    h.step(2)
+    L4.step(2)
+    for x in (L, L2, L3, L4, h_plain, h_other, h_odd, h):
         x.close()
