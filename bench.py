@@ -59,9 +59,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--workload", choices=["slab", "l10", "cylinders", "track", "transfer",
-                                           "demag", "mc", "mm", "multiscale"], default="track")
+                                           "demag", "track_demag", "mc", "mm", "multiscale"],
+                    default="track")
     ap.add_argument("--demag-cell", type=int, nargs=3, default=[4, 4, 3],
-                    help="coarse cell of the demag workload, in lattice cells")
+                    help="coarse cell of the demag and track_demag workloads, in lattice cells")
     ap.add_argument("--window-demag", action="store_true",
                     help="multiscale workload: add the demagnetising field of the whole window "
                          "(regions and atoms as one mesh)")
@@ -134,7 +135,7 @@ def bytes_per_site(precision: str, workload: str, kernel_name: str) -> int:
     the L1_0 two-pass kernels read the neighbour table)."""
     e = 8 if precision == "fp64" else 4
     b = 2 * 3 * e
-    if workload == "track":
+    if workload in ("track", "track_demag"):
         b += 2
     if workload == "l10" and not kernel_name.startswith("k_fused"):
         b += 4 * 18
@@ -222,7 +223,7 @@ def build_workload(name, prec, graph_steps, demag_cell=(0, 0, 0)):
         labs = [c.labels for c in cyl]
         window = [np.ones(len(l), bool) for l in labs]
         extra["moments_every"] = 10
-    else:  # track
+    else:  # track (track_demag: with the window's demagnetising field and the track's stray field)
         n_seeds = 16
         w = W.c5_track_window()
         ins = []
@@ -231,7 +232,9 @@ def build_workload(name, prec, graph_steps, demag_cell=(0, 0, 0)):
             seeds = W.voronoi_seeds(wk)
             ku = W.grain_ku(len(seeds), w.ku, w.ku_spread, wk.seed)
             ins.append(bridge.SystemInputs(wk, seeds=seeds, ku_grain=ku))
-        h = A.Handle(bridge.params_for(w, prec, graph_steps=graph_steps), [i.desc for i in ins])
+        cell = tuple(demag_cell) if name == "track_demag" else (0, 0, 0)
+        h = A.Handle(bridge.params_for(w, prec, graph_steps=graph_steps, demag_cell=cell),
+                     [i.desc for i in ins])
         dr, bits = bridge.drive_for(w)
         h.set_drive(dr)
         h._inputs = (ins, bits)
@@ -787,27 +790,20 @@ def main():
     g = segment_steps(args.steps) if args.graph_steps < 0 else args.graph_steps
     r = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, g)
     demag = None
-    if args.workload == "demag":
-        # the same two-pass variant without the field: the difference is the
-        # time of the two demagnetising-field evaluations of each step
-        r0 = gpu_run(args, args.precision, "plain", args.steps, args.warmup, g,
-                     workload="slab", tile=r["tile"])
-        per_eval = (r["t"] - r0["t"]) / (2 * r["steps"])
+    if args.workload in ("demag", "track_demag"):
+        # the same workload without the field, on the fastest kernel (the
+        # fused step): the cost of the field is the ratio of the two steps
+        base = "slab" if args.workload == "demag" else "track"
+        r0 = gpu_run(args, args.precision, "auto", args.steps, args.warmup, g, workload=base)
         cx, cy, cz = args.demag_cell
         w = r["w"]
         mesh = (-(-w.nx // cx), -(-w.ny // cy), -(-w.nz // cz))
-        e = 4 if args.precision == "fp32" else 8
-        # algorithmic bytes of one evaluation: the window spins read once and
-        # the field per coarse cell written once
-        dbytes = 3 * e * r["n_sites"] + 3 * e * mesh[0] * mesh[1] * mesh[2]
-        ach = dbytes / per_eval / 1e9
+        t1, t0 = r["t"] / r["steps"], r0["t"] / r0["steps"]
         demag = {"cell": [cx, cy, cz], "mesh": list(mesh),
                  "padded_fft": [1 << (2 * n - 1 - 1).bit_length() if n > 1 else 1 for n in mesh],
-                 "us_per_evaluation": 1e6 * per_eval, "evaluations_per_step": 2,
-                 "step_without_demag_ms": 1e3 * r0["t"] / r0["steps"],
-                 "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                              "algorithmic_bytes_per_evaluation": dbytes}}
+                 "evaluations_per_step": 2, "kernel": r["kname"], "step_ms": 1e3 * t1,
+                 "step_without_demag_ms": 1e3 * t0, "kernel_without_demag": r0["kname"],
+                 "ratio_to_step_without_demag": t1 / t0}
     if args.copy_calibration:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
@@ -834,7 +830,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": r["w"].name + ("_x16seeds" if args.workload == "track" else ""),
+        "config": {"workload": r["w"].name + ("_x16seeds" if args.workload in ("track", "track_demag")
+                                              else ""),
                    "lattice": "l10" if args.workload == "l10" else "sc",
                    "sites": r["n_sites"],
                    "magnetic_sites": r["n_mag"], "dt_fs": 1.0, "precision": args.precision,
@@ -850,7 +847,7 @@ def main():
     }
     if demag is not None:
         out["metric"] = "atomistic spin-updates/s (spins x Heun steps) with the demagnetising field"
-        out["config"]["workload"] = f"{r['w'].name}+demag{cx}x{cy}x{cz}"
+        out["config"]["workload"] += f"+demag{cx}x{cy}x{cz}"
         out["demag"] = demag
     if not args.no_extras and args.workload == "track" and args.precision == "fp32":
         # the same step beside the headline: the plain FP64 two-pass kernels and the

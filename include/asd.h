@@ -358,7 +358,12 @@ int asd_autotune(asd_t *h, const char *cache_path);
  * varies per grain and some stored column crosses grains (labels varying
  * along z), or when the handle adds the demagnetising field (a whole-mesh
  * convolution between the two Heun stages); the two-pass kernels take every
- * system.  Drops captured graphs. */
+ * system.  Two-pass tiles: 0 recomputes f(S) and the thermal field in the
+ * corrector, 1 stores them from the predictor, 2 (the default with the
+ * demagnetising field; ASD_EUNSUPPORTED without it or for coarse cells wider
+ * than 64 lattice cells) works on whole coarse cells and forms their spin
+ * sums (Eq. 6) as it writes the spins, so that within one asd_step call only
+ * the first field evaluation reads the spins.  Drops captured graphs. */
 int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile);
 int asd_get_variant(asd_t *h, int32_t *kernel, int32_t *tile);
 /* Number of tile variants of a kernel family for this handle's lattice and

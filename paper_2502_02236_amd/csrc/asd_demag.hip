@@ -113,6 +113,13 @@ __device__ Cx<T> *fft_lines(Cx<T> *x, Cx<T> *y, int nl, int lp, int ls,
     return x;
 }
 
+// position of component c, plane k, row j, column kx of system s in wx
+__device__ __forceinline__ int64_t wx_at(const DemagDev &dm, int s, int c, int k, int j, int kx,
+                                         int Pxh)
+{
+    return ((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx;
+}
+
 template <typename T>
 __device__ __forceinline__ Cx<T> *lds_base()
 {
@@ -185,14 +192,14 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T
     const int Pxh = (Px >> 1) + 1;
     for (int q = threadIdx.x; q < 3 * Pxh; q += blockDim.x) {
         const int c = q / Pxh, kx = q - c * Pxh;
-        out[((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx] = r[c * Px + kx];
+        out[wx_at(dm, s, c, k, j, kx, Pxh)] = r[c * Px + kx];
     }
 }
 
-// --- 1': the same from given cell sums: src [S][3][ncell] (FP64, cells x
+// --- 1': the same from given cell sums: src [S][3][ncell] (cells x
 // fastest, in units of the spin sums of a coarse cell); FFT along x
-template <typename T>
-__global__ __launch_bounds__(kDmThreads) void k_dm_cells_x(DemagDev dm, const double *__restrict__ src)
+template <typename T, typename U>
+__global__ __launch_bounds__(kDmThreads) void k_dm_cells_x(DemagDev dm, const U *__restrict__ src)
 {
     const int Px = 1 << dm.lx;
     const int j = blockIdx.x % dm.ncy, k = blockIdx.x / dm.ncy, s = blockIdx.y;
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_cells_x(DemagDev dm, const do
     const int Pxh = (Px >> 1) + 1;
     for (int q = threadIdx.x; q < 3 * Pxh; q += blockDim.x) {
         const int c = q / Pxh, kx = q - c * Pxh;
-        out[((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx] = r[c * Px + kx];
+        out[wx_at(dm, s, c, k, j, kx, Pxh)] = r[c * Px + kx];
     }
 }
 
@@ -317,11 +324,10 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage,
     const int Pxh = (Px >> 1) + 1;
     for (int q = threadIdx.x; q < 3 * Px; q += blockDim.x) {
         const int c = q >> dm.lx, kx = q & (Px - 1);
-        const int64_t row = ((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh;
         if (kx < Pxh) {
-            x[q] = in[row + kx];
+            x[q] = in[wx_at(dm, s, c, k, j, kx, Pxh)];
         } else {  // X(Px - k) = conj X(k)
-            const Cx<T> v = in[row + (Px - kx)];
+            const Cx<T> v = in[wx_at(dm, s, c, k, j, Px - kx, Pxh)];
             x[q] = Cx<T>{v.re, -v.im};
         }
     }
@@ -349,9 +355,9 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage,
     }
 }
 
-template <typename T>
+template <typename T, typename U = double>
 int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
-                 const int32_t *origin, int stage, void *stream, const double *cells = nullptr)
+                 const int32_t *origin, int stage, void *stream, const U *cells = nullptr)
 {
     hipStream_t st = (hipStream_t)stream;
     const int Px = 1 << dm.lx, Py = 1 << dm.ly, Pz = 1 << dm.lz;
@@ -359,7 +365,7 @@ int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
     const dim3 blk(kDmThreads);
     const dim3 grows(dm.ncy * dm.ncz, dm.n_sys);
     if (cells)
-        hipLaunchKernelGGL(k_dm_cells_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, cells);
+        hipLaunchKernelGGL((k_dm_cells_x<T, U>), grows, blk, 2 * 3 * Px * cb, st, dm, cells);
     else
         hipLaunchKernelGGL(k_dm_gather_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, S, ncs, sys,
                            origin);
@@ -390,6 +396,16 @@ int launch_demag_f32(const DemagDev &dm, const float *S, int64_t ncs, const SysD
 int launch_demag_cells(const DemagDev &dm, const double *cells, void *stream)
 {
     return run_demag<double>(dm, nullptr, 0, nullptr, nullptr, 0, stream, cells);
+}
+
+int launch_demag_sums_f64(const DemagDev &dm, const double *sums, int stage, void *stream)
+{
+    return run_demag<double, double>(dm, nullptr, 0, nullptr, nullptr, stage, stream, sums);
+}
+
+int launch_demag_sums_f32(const DemagDev &dm, const float *sums, int stage, void *stream)
+{
+    return run_demag<float, float>(dm, nullptr, 0, nullptr, nullptr, stage, stream, sums);
 }
 
 }  // namespace asd

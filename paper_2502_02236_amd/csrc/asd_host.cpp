@@ -67,6 +67,7 @@ struct Layout {
     // demagnetising field (when asd_params.demag_cell is set)
     DemagDev dm{};            // geometry; pointers filled at create
     size_t off_dwx = 0, off_dwy = 0, off_dbd[2] = {0, 0}, off_dK = 0, off_dtw[3] = {0, 0, 0};
+    size_t off_dcs[2] = {0, 0};  // cell sums of the cell-row kernels
     DemagDev dmT{};           // stray field of the frozen track (track systems only)
     size_t off_twx = 0, off_twy = 0, off_tK = 0, off_ttw = 0, off_tstray = 0;
     size_t bytes = 0;
@@ -448,6 +449,9 @@ static const char *demag_geometry(const asd_params *p, const asd_system_desc *sy
     g->fd_cx = host_fastdiv((uint32_t)c[0]);
     g->fd_cy = host_fastdiv((uint32_t)c[1]);
     g->fd_cz = host_fastdiv((uint32_t)c[2]);
+    // cell-row kernels: whole cells across the 64 lanes of a wavefront
+    g->cr_cells = c[0] <= 64 ? 64 / c[0] : 0;
+    g->cr_segs = g->cr_cells ? (g->ncx + g->cr_cells - 1) / g->cr_cells : 0;
     return nullptr;
 }
 
@@ -516,6 +520,7 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         L.off_dwx = take((size_t)n_sys * 3 * g.ncz * g.ncy * Pxh * cplx);
         L.off_dwy = take((size_t)n_sys * 3 * g.ncz * Py * Pxh * cplx);
         for (int b = 0; b < 2; ++b) L.off_dbd[b] = take((size_t)n_sys * 3 * g.ncell * elem);
+        for (int b = 0; b < 2; ++b) L.off_dcs[b] = take((size_t)n_sys * 3 * g.ncell * elem);
         L.off_dK = take(6 * (Px / 2 + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * elem);
         L.off_dtw[0] = take(std::max<size_t>(Px / 2, 1) * cplx);
         L.off_dtw[1] = take(std::max<size_t>(Py / 2, 1) * cplx);
@@ -621,6 +626,7 @@ static void drop_graphs(asd_t *h)
 }
 
 static const char *fused_unsupported(const asd_t *h);
+static const char *cell_rows_unsupported(const asd_t *h);
 
 int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, void *workspace,
                size_t workspace_bytes, void *stream, asd_t **out)
@@ -810,6 +816,8 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
         g.wy = w + L.off_dwy;
         g.bd[0] = w + L.off_dbd[0];
         g.bd[1] = w + L.off_dbd[1];
+        g.cs[0] = w + L.off_dcs[0];
+        g.cs[1] = w + L.off_dcs[1];
         g.K = w + L.off_dK;
         for (int ax = 0; ax < 3; ++ax) g.tw[ax] = w + L.off_dtw[ax];
         if (L.dmT.on) {
@@ -843,6 +851,7 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
             t.tw[2] = g.tw[2];
             t.bstray = w + L.off_tstray;
             t.bd[0] = t.bd[1] = nullptr;
+            t.cs[0] = t.cs[1] = nullptr;
             h->dmT = t;
             g.bstray = t.bstray;  // the window's field includes the track's
             HIP_OK(h, hipStreamSynchronize(st));
@@ -872,6 +881,9 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
             return ASD_EUNSUPPORTED;
         }
     }
+    // with the demagnetising field the two-pass kernels default to the
+    // cell-row variant, which forms the cell sums as it writes the spins
+    if (h->kernel == ASD_KERNEL_PLAIN && !cell_rows_unsupported(h)) h->tile_cfg = kCellRowVariant;
     *out = h;
     return ASD_OK;
 }
@@ -1742,6 +1754,14 @@ static const char *fused_unsupported(const asd_t *h)
     return nullptr;
 }
 
+// reason the cell-row kernels (two-pass variant 2) cannot serve this handle, or NULL
+static const char *cell_rows_unsupported(const asd_t *h)
+{
+    if (!h->dm.on) return "the cell-row kernels serve handles with the demagnetising field";
+    if (h->dm.cr_cells < 1) return "the cell-row kernels need coarse cells of at most 64 lattice cells along x";
+    return nullptr;
+}
+
 // fill the fused tile map for variant v and upload it with the descriptors
 static int setup_fused_tiles(asd_t *h, int v)
 {
@@ -1774,6 +1794,10 @@ int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile)
                          ? kPlainVariants
                          : fused_count(h->p.lattice == ASD_L10, h->p.precision == ASD_FP64);
     if (tile < 0 || tile >= nvar) return fail(h, ASD_EINVAL, "variant out of range");
+    if (kernel == ASD_KERNEL_PLAIN && tile == kCellRowVariant) {
+        const char *why = cell_rows_unsupported(h);
+        if (why) return fail(h, ASD_EUNSUPPORTED, "%s", why);
+    }
     if (kernel == ASD_KERNEL_FUSED) {
         const char *why = fused_unsupported(h);
         if (why) return fail(h, ASD_EUNSUPPORTED, "%s", why);
@@ -1825,6 +1849,8 @@ int asd_variant_name(asd_t *h, char *buf, size_t len)
                      zper ? "true" : "false");
     } else if (h->tile_cfg == 1) {
         snprintf(tmp, sizeof tmp, "k_plain_predictor<%s, true>+k_stash_corrector<%s>", T, T);
+    } else if (h->tile_cfg == kCellRowVariant) {
+        snprintf(tmp, sizeof tmp, "k_cell_step<%s, false>+k_cell_step<%s, true>", T, T);
     } else {
         snprintf(tmp, sizeof tmp, "k_plain_predictor<%s, false>+k_plain_corrector<%s>", T, T);
     }
@@ -1847,8 +1873,11 @@ static std::string tune_key(const asd_t *h)
         const FusedVariant f = fused_pick(l10, fp64, v);
         for (int x : {f.txe, f.waves, f.rows, f.lz}) tab = (tab ^ (uint32_t)x) * 16777619u;
     }
-    snprintf(buf, sizeof buf, "lat%d_prec%d_%dx%dx%d_n%zu_w%lld_t%08x", h->p.lattice, h->p.precision,
-             d.nx, d.ny, d.nz, h->sys.size(), (long long)sites, tab);
+    int len = snprintf(buf, sizeof buf, "lat%d_prec%d_%dx%dx%d_n%zu_w%lld_t%08x", h->p.lattice,
+                       h->p.precision, d.nx, d.ny, d.nz, h->sys.size(), (long long)sites, tab);
+    // the demagnetising field changes the candidates and their cost
+    if (h->dm.on && len > 0 && len < (int)sizeof buf)
+        snprintf(buf + len, sizeof buf - len, "_dm%dx%dx%d", h->dm.cx, h->dm.cy, h->dm.cz);
     return buf;
 }
 
@@ -1952,7 +1981,8 @@ int asd_autotune(asd_t *h, const char *cache_path)
         int kernel, tile;
     };
     std::vector<Cand> cands;
-    for (int v = 0; v < kPlainVariants; ++v) cands.push_back({ASD_KERNEL_PLAIN, v});
+    for (int v = 0; v < kPlainVariants; ++v)
+        if (v != kCellRowVariant || !cell_rows_unsupported(h)) cands.push_back({ASD_KERNEL_PLAIN, v});
     if (!fused_unsupported(h))
         for (int v = 0; v < fused_count(h->p.lattice == ASD_L10, h->p.precision == ASD_FP64); ++v)
             cands.push_back({ASD_KERNEL_FUSED, v});

@@ -82,6 +82,12 @@ struct DemagDev {
     void *wx;                 // complex [S][3][ncz][ncy][Px/2+1] (Hermitian half in x)
     void *wy;                 // complex [S][3][ncz][Py][Px/2+1]
     void *bd[2];              // field (T) per coarse cell, [S][3][ncell], one per Heun stage
+    // cell-row step kernels (two-pass variant 2): the spin sums of every
+    // coarse cell (T, [S][3][ncell]) as the kernels write the spins, [0] of
+    // S' (predictor), [1] of the next spins (corrector); a workgroup takes
+    // cr_cells cells along x of one layer (j, k), cr_segs workgroups per layer
+    void *cs[2];
+    int32_t cr_cells, cr_segs;
     const void *K;            // tensor spectrum, octant [6][Py/2+1][Px/2+1][Pz/2+1]
     const void *tw[3];        // twiddles exp(-2 pi i t / P), t < P / 2, per axis
 };
@@ -116,6 +122,18 @@ struct StepArgs {
 // the same pipeline in FP64 from given cell sums cells [n_sys][3][ncell]
 // (spin-sum units) into dm.bd[0]
 int launch_demag_cells(const DemagDev &dm, const double *cells, void *stream);
+// the same in the handle's precision from cell sums in that precision into
+// dm.bd[stage]
+int launch_demag_sums_f64(const DemagDev &dm, const double *sums, int stage, void *stream);
+int launch_demag_sums_f32(const DemagDev &dm, const float *sums, int stage, void *stream);
+inline int launch_demag_sums(const DemagDev &dm, const double *sums, int stage, void *stream)
+{
+    return launch_demag_sums_f64(dm, sums, stage, stream);
+}
+inline int launch_demag_sums(const DemagDev &dm, const float *sums, int stage, void *stream)
+{
+    return launch_demag_sums_f32(dm, sums, stage, stream);
+}
 // demagnetising field of spins S (both [3][ncs]) into dm.bd[stage]
 int launch_demag_f64(const DemagDev &dm, const double *S, int64_t ncs, const SysDev *sys,
                      const int32_t *origin, int stage, void *stream);

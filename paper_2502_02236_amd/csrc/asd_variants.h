@@ -4,8 +4,11 @@
 namespace asd {
 
 // Two-pass kernel variants: 0 recomputes f(S) and the thermal field in the
-// corrector; 1 stashes them from the predictor.
-constexpr int kPlainVariants = 2;
+// corrector; 1 stashes them from the predictor; 2 (handles with the
+// demagnetising field only) recomputes them in kernels that take whole
+// coarse cells and form the cells' spin sums for the next field evaluation.
+constexpr int kPlainVariants = 3;
+constexpr int kCellRowVariant = 2;
 
 // Fused SC kernel variant: TXE lanes across x (64, 32 or 16), WAVES
 // wavefronts, R column slots per lane, z planes per tile LZ (0: all).

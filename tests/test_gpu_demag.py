@@ -78,8 +78,7 @@ FIELD_CASES = [
     ("sc_one_cell", sc_slab(nx=8, ny=6, nz=3), (8, 6, 3), 1),
     ("l10_3x3x2", l10_slab(), (3, 3, 2), 2),
     ("track_window_5x4x5", track(), (5, 4, 5), 2),
-    # meshes 5 x 4 x ncz: the FP32 z pass sums directly up to 16 planes
-    # (register blocks of 4, 8, 12, 16), FFTs beyond
+    # meshes 5 x 4 x ncz: z transforms of 16, 32 and 64 points
     ("sc_ncz7", sc_slab(nx=10, ny=8, nz=7), (2, 2, 1), 1),
     ("sc_ncz11", sc_slab(nx=10, ny=8, nz=11), (2, 2, 1), 1),
     ("sc_ncz15", sc_slab(nx=10, ny=8, nz=15), (2, 2, 1), 1),
@@ -179,15 +178,19 @@ STEP_CASES = [
     ("sc_fp32", sc_slab(), (4, 4, 2), 2, A.ASD_FP32),
     ("l10_fp64", l10_slab(), (3, 3, 2), 1, A.ASD_FP64),
     ("l10_fp32", l10_slab(), (3, 3, 3), 1, A.ASD_FP32),
+    # 20 planes of cells (z transforms of 64 points)
+    ("sc_fp64_ncz20", sc_slab(nz=20), (4, 4, 1), 1, A.ASD_FP64),
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["recompute", "stash"])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["recompute", "stash", "cellrows"])
 @pytest.mark.parametrize("name,w,cell,n_sys,prec", STEP_CASES, ids=[c[0] for c in STEP_CASES])
 def test_heun_with_demag_matches_oracle(name, w, cell, n_sys, prec, variant):
+    """Variant 2 forms the cell sums in the step kernels: with graph segments of
+    ten steps, nine of every ten field evaluations start from those sums."""
     steps = 40
     say(f"[demag heun] {name} cell={cell} variant={variant} steps={steps}")
-    h = bridge.make_handle(w, prec, n_systems=n_sys, demag_cell=cell)
+    h = bridge.make_handle(w, prec, n_systems=n_sys, demag_cell=cell, graph_steps=10)
     h.set_variant(A.ASD_KERNEL_PLAIN, variant)
     lab = h.labels()
     S0 = [random_state(w, lab, 21 + s) for s in range(n_sys)]
@@ -209,10 +212,11 @@ def test_heun_with_demag_matches_oracle(name, w, cell, n_sys, prec, variant):
     h.close()
 
 
+@pytest.mark.parametrize("variant", [0, 2], ids=["recompute", "cellrows"])
 @pytest.mark.parametrize("prec,cell", [(A.ASD_FP64, (5, 4, 5)), (A.ASD_FP32, (5, 4, 5)),
                                        (A.ASD_FP64, (4, 3, 2)), (A.ASD_FP32, (7, 6, 3))],
                          ids=["fp64_5x4x5", "fp32_5x4x5", "fp64_4x3x2", "fp32_7x6x3_ragged"])
-def test_track_with_demag_and_shifts(prec, cell):
+def test_track_with_demag_and_shifts(prec, cell, variant):
     """Moving window: the demagnetising mesh moves with the window and the frozen
     track's stray field is recomputed after every shift; graph-captured segments
     (the demag kernels are plain launches, no memset nodes) replayed."""
@@ -220,6 +224,7 @@ def test_track_with_demag_and_shifts(prec, cell):
     shifts = [(10, 1), (20, 2)]
     steps = 40
     h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10)
+    h.set_variant(A.ASD_KERNEL_PLAIN, variant)
     lab = h.labels()
     S0 = random_state(w, lab, 5)
     h.set_spins(S0)
@@ -245,6 +250,31 @@ def test_track_with_demag_and_shifts(prec, cell):
     say(f"[demag track] prec={prec} cell={cell} max |dS| = {err:.3e}")
     assert err <= SPIN_TOL[prec]
     h.close()
+
+
+@pytest.mark.parametrize("prec", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
+def test_cell_rows_match_two_pass_over_100_steps(prec):
+    """The cell-row kernels against the two-pass kernels that sum the spins in
+    the field pass, 100 steps from the same state: three workgroups per layer
+    of cells along x (the last one ragged), ragged cells along y and z, graph
+    segments of ten steps and a tail of plain launches.  The per-site
+    arithmetic is the same; only the order of the cell sums differs."""
+    w = sc_slab(nx=150, ny=13, nz=5)
+    cell = (2, 3, 2)
+    out = {}
+    for variant in (0, 2):
+        h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10)
+        h.set_variant(A.ASD_KERNEL_PLAIN, variant)
+        S0 = random_state(w, h.labels(), 77)
+        h.set_spins(S0)
+        h.step(95)
+        h.step(5)
+        out[variant] = h.get_spins().astype(np.float64)
+        h.close()
+    err = float(np.max(np.abs(out[2] - out[0])))
+    bar = 1e-12 if prec == A.ASD_FP64 else 1e-4
+    say(f"[cell rows vs two-pass] prec={prec}: max |dS| after 100 steps = {err:.3e} (bar {bar:.0e})")
+    assert err <= bar
 
 
 def test_track_stray_field_at_the_largest_track():
@@ -283,9 +313,10 @@ def test_demag_error_paths():
     with pytest.raises(A.AsdError) as e:
         bridge.make_handle(w, A.ASD_FP32, kernel=A.ASD_KERNEL_FUSED, demag_cell=(2, 2, 2))
     assert e.value.code == A.ASD_EUNSUPPORTED
-    # AUTO falls back to the two-pass kernels
+    # AUTO falls back to the two-pass kernels, the cell-row variant by default
     h = bridge.make_handle(w, A.ASD_FP32, kernel=A.ASD_KERNEL_AUTO, demag_cell=(2, 2, 2))
-    assert h.variant()[0] == A.ASD_KERNEL_PLAIN
+    assert h.variant() == (A.ASD_KERNEL_PLAIN, 2)
+    assert h.variant_name().startswith("k_cell_step")
     with pytest.raises(A.AsdError) as e:
         h.set_variant(A.ASD_KERNEL_FUSED, 0)
     assert e.value.code == A.ASD_EUNSUPPORTED
@@ -294,6 +325,16 @@ def test_demag_error_paths():
     with pytest.raises(A.AsdError) as e:
         h.demag_field()
     assert e.value.code == A.ASD_ESTATE
+    # the cell-row kernels need the field, and cells at most 64 lattice cells wide
+    with pytest.raises(A.AsdError) as e:
+        h.set_variant(A.ASD_KERNEL_PLAIN, 2)
+    assert e.value.code == A.ASD_EUNSUPPORTED
+    h.close()
+    h = bridge.make_handle(w.scaled(nx=130), A.ASD_FP32, demag_cell=(65, 2, 2))
+    assert h.variant() == (A.ASD_KERNEL_PLAIN, 0)
+    with pytest.raises(A.AsdError) as e:
+        h.set_variant(A.ASD_KERNEL_PLAIN, 2)
+    assert e.value.code == A.ASD_EUNSUPPORTED
     h.close()
     # systems of different window sizes cannot share the mesh
     ins = [bridge.SystemInputs(w), bridge.SystemInputs(w.scaled(nx=w.nx - 1))]
