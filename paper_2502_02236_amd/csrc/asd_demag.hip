@@ -117,7 +117,8 @@ __device__ Cx<T> *fft_lines(Cx<T> *x, Cx<T> *y, int nl, int lp, int ls,
 __device__ __forceinline__ int64_t wx_at(const DemagDev &dm, int s, int c, int k, int j, int kx,
                                          int Pxh)
 {
-    return ((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx;
+    return dm.yzf ? ((((int64_t)s * Pxh + kx) * 3 + c) * dm.ncz + k) * dm.ncy + j
+                  : ((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx;
 }
 
 template <typename T>
@@ -196,18 +197,26 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_gather_x(DemagDev dm, const T
     }
 }
 
-// --- 1': the same from given cell sums: src [S][3][ncell] (cells x
-// fastest, in units of the spin sums of a coarse cell); FFT along x
+// --- 1': the same from given cell sums: src [S][3][ns][ncell] (cells x
+// fastest, in units of the spin sums of a coarse cell; ns partial sums per
+// cell, 1 when dm.ns is 0); FFT along x
 template <typename T, typename U>
 __global__ __launch_bounds__(kDmThreads) void k_dm_cells_x(DemagDev dm, const U *__restrict__ src)
 {
     const int Px = 1 << dm.lx;
     const int j = blockIdx.x % dm.ncy, k = blockIdx.x / dm.ncy, s = blockIdx.y;
     Cx<T> *x = lds_base<T>(), *y = x + 3 * Px;
+    const int ns = max(dm.ns, 1);  // partial sums per cell, added in slot order
     for (int q = threadIdx.x; q < 3 * Px; q += blockDim.x) {
         const int c = q >> dm.lx, i = q & (Px - 1);
         const int64_t cell = i + (int64_t)dm.ncx * (j + (int64_t)dm.ncy * k);
-        x[q] = Cx<T>{i < dm.ncx ? (T)src[((int64_t)s * 3 + c) * dm.ncell + cell] : T(0), T(0)};
+        T v = T(0);
+        if (i < dm.ncx) {
+            const U *p = src + ((int64_t)s * 3 + c) * ns * dm.ncell + cell;
+            v = (T)p[0];
+            for (int sl = 1; sl < ns; ++sl) v = v + (T)p[(int64_t)sl * dm.ncell];
+        }
+        x[q] = Cx<T>{v, T(0)};
     }
     __syncthreads();
     const Cx<T> *r = fft_lines<T, false>(x, y, 3, dm.lx, Px, (const Cx<T> *)dm.tw[0]);
@@ -312,6 +321,96 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
     }
 }
 
+// --- 2-4 in one workgroup per (kx, system) when yzf: the 3 NCZ rows of
+// column kx (kx-major in wx) into LDS; FFT along y; per ky the field planes
+// as direct sums over the source planes with the tensor transformed along x
+// and y only, so the convolution along z needs neither padding nor
+// transforms; inverse FFT along y; the ncy rows back.  Lanes: four groups of
+// Py, group q computing the planes q, q + 4, ... (wavefront-uniform, so the
+// unrolled sums need no divergent branches).
+constexpr int kDmYzThreads = 512;
+
+template <typename T, int NCZ, int Q0>
+__device__ __forceinline__ void yz_column(const T *__restrict__ kt, int oy, T sy, const Cx<T> *r,
+                                          Cx<T> *o, int ls, int ky)
+{
+    constexpr int Q = 4;
+    // tensor along z at offsets 0 .. NCZ-1 (kt + (comp NCZ + d) oy); xy and
+    // yz are odd in ky, xz and yz odd in dz and imaginary (stored as such)
+    T nxx[NCZ], nyy[NCZ], nzz[NCZ], nxy[NCZ], txz[NCZ], tyz[NCZ];
+#pragma unroll
+    for (int d = 0; d < NCZ; ++d) {
+        nxx[d] = kt[(0 * NCZ + d) * (int64_t)oy];
+        nyy[d] = kt[(1 * NCZ + d) * (int64_t)oy];
+        nzz[d] = kt[(2 * NCZ + d) * (int64_t)oy];
+        nxy[d] = sy * kt[(3 * NCZ + d) * (int64_t)oy];
+        txz[d] = kt[(4 * NCZ + d) * (int64_t)oy];
+        tyz[d] = sy * kt[(5 * NCZ + d) * (int64_t)oy];
+    }
+#pragma unroll
+    for (int z = Q0; z < NCZ; z += Q) {
+        T hxr = T(0), hxi = T(0), hyr = T(0), hyi = T(0), hzr = T(0), hzi = T(0);
+#pragma unroll
+        for (int zs = 0; zs < NCZ; ++zs) {
+            const int d = z - zs, ad = d < 0 ? -d : d;
+            const T sg = d < 0 ? T(-1) : T(1);
+            const Cx<T> mx = r[(0 * NCZ + zs) * ls + ky], my = r[(1 * NCZ + zs) * ls + ky],
+                        mz = r[(2 * NCZ + zs) * ls + ky];
+            const T Nxx = nxx[ad], Nyy = nyy[ad], Nzz = nzz[ad], Nxy = nxy[ad];
+            const T Txz = sg * txz[ad], Tyz = sg * tyz[ad];
+            // H += N M with N_xz = i Txz, N_yz = i Tyz
+            hxr = hxr + ((Nxx * mx.re + Nxy * my.re) - Txz * mz.im);
+            hxi = hxi + ((Nxx * mx.im + Nxy * my.im) + Txz * mz.re);
+            hyr = hyr + ((Nxy * mx.re + Nyy * my.re) - Tyz * mz.im);
+            hyi = hyi + ((Nxy * mx.im + Nyy * my.im) + Tyz * mz.re);
+            hzr = hzr + ((Nzz * mz.re - Txz * mx.im) - Tyz * my.im);
+            hzi = hzi + ((Nzz * mz.im + Txz * mx.re) + Tyz * my.re);
+        }
+        o[(0 * NCZ + z) * ls + ky] = Cx<T>{hxr, hxi};
+        o[(1 * NCZ + z) * ls + ky] = Cx<T>{hyr, hyi};
+        o[(2 * NCZ + z) * ls + ky] = Cx<T>{hzr, hzi};
+    }
+}
+
+template <typename T, int NCZ>
+__global__ __launch_bounds__(kDmYzThreads) void k_dm_yz(DemagDev dm)
+{
+    constexpr int Q = 4, nl = 3 * NCZ;
+    const int Px = 1 << dm.lx, Py = 1 << dm.ly;
+    const int Pxh = (Px >> 1) + 1;
+    const int kx = blockIdx.x, s = blockIdx.y;
+    const int ncy = dm.ncy, ls = Py + 1;
+    Cx<T> *bx = lds_base<T>(), *by = bx + nl * ls;
+    Cx<T> *w = (Cx<T> *)dm.wx + ((int64_t)s * Pxh + kx) * nl * ncy;
+    for (int q = threadIdx.x; q < nl * Py; q += blockDim.x) {
+        const int line = q >> dm.ly, yy = q & (Py - 1);
+        bx[line * ls + yy] = yy < ncy ? w[line * ncy + yy] : Cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    Cx<T> *r = fft_lines<T, false>(bx, by, nl, dm.ly, ls, (const Cx<T> *)dm.tw[1]);
+    Cx<T> *o = r == bx ? by : bx;
+    const int oy = (Py >> 1) + 1;
+    const T *kt0 = (const T *)dm.K + (int64_t)kx * 6 * NCZ * oy;
+    for (int t = threadIdx.x; t < Py * Q; t += blockDim.x) {
+        const int q = t >> dm.ly, ky = t & (Py - 1);
+        const int kyr = ky <= (Py >> 1) ? ky : Py - ky;
+        const T sy = ky <= (Py >> 1) ? T(1) : T(-1);
+        const T *kt = kt0 + kyr;
+        switch (q) {
+        case 0: yz_column<T, NCZ, 0>(kt, oy, sy, r, o, ls, ky); break;
+        case 1: yz_column<T, NCZ, 1>(kt, oy, sy, r, o, ls, ky); break;
+        case 2: yz_column<T, NCZ, 2>(kt, oy, sy, r, o, ls, ky); break;
+        default: yz_column<T, NCZ, 3>(kt, oy, sy, r, o, ls, ky); break;
+        }
+    }
+    __syncthreads();
+    const Cx<T> *h = fft_lines<T, true>(o, r, nl, dm.ly, ls, (const Cx<T> *)dm.tw[1]);
+    for (int q = threadIdx.x; q < nl * ncy; q += blockDim.x) {
+        const int line = q / ncy, yy = q - line * ncy;
+        w[line * ncy + yy] = h[line * ls + yy];
+    }
+}
+
 // --- 5: inverse FFT along x of one (y, z) row, the field of its ncx cells
 template <typename T>
 __global__ __launch_bounds__(kDmThreads) void k_dm_x_out(DemagDev dm, int stage,
@@ -370,16 +469,37 @@ int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
         hipLaunchKernelGGL(k_dm_gather_x<T>, grows, blk, 2 * 3 * Px * cb, st, dm, S, ncs, sys,
                            origin);
     const int Pxh = (Px >> 1) + 1;
-    const dim3 gy((Pxh + dm.xb_y - 1) / dm.xb_y, 3 * dm.ncz, dm.n_sys);
-    hipLaunchKernelGGL((k_dm_y<T, false>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
-    const dim3 gz((Pxh + dm.xb_z - 1) / dm.xb_z, Py, dm.n_sys);
-    hipLaunchKernelGGL(k_dm_z<T>, gz, blk, 2 * 3 * dm.xb_z * (Pz + 1) * cb, st, dm);
-    hipLaunchKernelGGL((k_dm_y<T, true>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
+    if (dm.yzf) {
+        const dim3 g(Pxh, dm.n_sys), b(kDmYzThreads);
+        const size_t lds = demag_yz_lds_bytes(dm, (int)sizeof(T));
+#define ASD_YZ(N)                                                                                  \
+    case N: hipLaunchKernelGGL((k_dm_yz<T, N>), g, b, lds, st, dm); break;
+        switch (dm.ncz) {
+            ASD_YZ(1) ASD_YZ(2) ASD_YZ(3) ASD_YZ(4) ASD_YZ(5) ASD_YZ(6) ASD_YZ(7) ASD_YZ(8)
+            ASD_YZ(9) ASD_YZ(10) ASD_YZ(11) ASD_YZ(12) ASD_YZ(13) ASD_YZ(14) ASD_YZ(15) ASD_YZ(16)
+        default: return -1;
+        }
+#undef ASD_YZ
+    } else {
+        const dim3 gy((Pxh + dm.xb_y - 1) / dm.xb_y, 3 * dm.ncz, dm.n_sys);
+        hipLaunchKernelGGL((k_dm_y<T, false>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
+        const dim3 gz((Pxh + dm.xb_z - 1) / dm.xb_z, Py, dm.n_sys);
+        hipLaunchKernelGGL(k_dm_z<T>, gz, blk, 2 * 3 * dm.xb_z * (Pz + 1) * cb, st, dm);
+        hipLaunchKernelGGL((k_dm_y<T, true>), gy, blk, 2 * dm.xb_y * (Py + 1) * cb, st, dm);
+    }
     hipLaunchKernelGGL(k_dm_x_out<T>, grows, blk, 2 * 3 * Px * cb, st, dm, stage, origin);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
+
+size_t demag_yz_lds_bytes(const DemagDev &dm, int elem)
+{
+    // the unrolled sums keep their operands in registers: up to 16 planes
+    // (12 in FP64)
+    if (dm.ncz > (elem == 8 ? 12 : 16)) return 0;
+    return (size_t)2 * 3 * dm.ncz * ((size_t)(1 << dm.ly) + 1) * 2 * elem;
+}
 
 int launch_demag_f64(const DemagDev &dm, const double *S, int64_t ncs, const SysDev *sys,
                      const int32_t *origin, int stage, void *stream)

@@ -76,6 +76,55 @@ void fft1(std::complex<double> *a, int l, size_t st)
 
 }  // namespace
 
+namespace {
+
+// the auxiliary-function table of tensor component comp (xx yy zz xy xz yz)
+// over cell offsets 0..nc (a stencil reaches one beyond nc - 1)
+Table component_table(int comp, int ncx, int ncy, int ncz, double dx, double dy, double dz)
+{
+    Table t{ncx, ncy, ncz, std::vector<double>((size_t)(ncx + 1) * (ncy + 1) * (ncz + 1))};
+    for (int k = 0; k <= ncz; ++k)
+        for (int j = 0; j <= ncy; ++j)
+            for (int i = 0; i <= ncx; ++i) {
+                const double X = i * dx, Y = j * dy, Z = k * dz;
+                double v = 0.0;
+                switch (comp) {
+                case 0: v = aux_f(X, Y, Z); break;  // xx: f(x, y, z)
+                case 1: v = aux_f(Y, X, Z); break;  // yy: f(y, x, z)
+                case 2: v = aux_f(Z, Y, X); break;  // zz: f(z, y, x)
+                case 3: v = aux_g(X, Y, Z); break;  // xy: g(x, y, z)
+                case 4: v = aux_g(X, Z, Y); break;  // xz: g(x, z, y)
+                default: v = aux_g(Y, Z, X); break; // yz: g(y, z, x)
+                }
+                t.v[((size_t)k * (ncy + 1) + j) * (ncx + 1) + i] = v;
+            }
+    return t;
+}
+
+// axes in which each component is odd: xy -> (x, y), xz -> (x, z), yz -> (y, z)
+const bool kOdd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+
+// component comp of the tensor between cells displaced by (I, J, K) cells,
+// times 4 pi V: the second difference along each axis of the table
+double tensor_element(const Table &t, int comp, int I, int J, int K)
+{
+    double acc = 0.0;
+    for (int ez = -1; ez <= 1; ++ez)
+        for (int ey = -1; ey <= 1; ++ey)
+            for (int ex = -1; ex <= 1; ++ex) {
+                const int ii = I + ex, jj = J + ey, kk = K + ez;
+                double sg = 1.0;
+                if (kOdd[comp][0] && ii < 0) sg = -sg;
+                if (kOdd[comp][1] && jj < 0) sg = -sg;
+                if (kOdd[comp][2] && kk < 0) sg = -sg;
+                const double w = (ex ? -1.0 : 2.0) * (ey ? -1.0 : 2.0) * (ez ? -1.0 : 2.0);
+                acc += w * sg * t.at(std::abs(ii), std::abs(jj), std::abs(kk));
+            }
+    return acc;
+}
+
+}  // namespace
+
 // Spectrum of the six tensor components on the zero-padded mesh (padded
 // sizes 2^lx x 2^ly x 2^lz), times `scale`, kept on the octant kx <= Px/2,
 // ky <= Py/2, kz <= Pz/2: [6][Py/2+1][Px/2+1][Pz/2+1] (xx yy zz xy xz yz;
@@ -88,51 +137,17 @@ void demag_spectrum(int ncx, int ncy, int ncz, double dx, double dy, double dz, 
     const int Px = 1 << lx, Py = 1 << ly, Pz = 1 << lz;
     const int ox = Px / 2 + 1, oy = Py / 2 + 1, oz = Pz / 2 + 1;
     octant.assign((size_t)6 * ox * oy * oz, 0.0);
-    // tables over offsets 0..nc (a stencil reaches one beyond nc - 1)
-    auto tab = [&](int comp) {
-        Table t{ncx, ncy, ncz, std::vector<double>((size_t)(ncx + 1) * (ncy + 1) * (ncz + 1))};
-        for (int k = 0; k <= ncz; ++k)
-            for (int j = 0; j <= ncy; ++j)
-                for (int i = 0; i <= ncx; ++i) {
-                    const double X = i * dx, Y = j * dy, Z = k * dz;
-                    double v = 0.0;
-                    switch (comp) {
-                    case 0: v = aux_f(X, Y, Z); break;  // xx: f(x, y, z)
-                    case 1: v = aux_f(Y, X, Z); break;  // yy: f(y, x, z)
-                    case 2: v = aux_f(Z, Y, X); break;  // zz: f(z, y, x)
-                    case 3: v = aux_g(X, Y, Z); break;  // xy: g(x, y, z)
-                    case 4: v = aux_g(X, Z, Y); break;  // xz: g(x, z, y)
-                    default: v = aux_g(Y, Z, X); break; // yz: g(y, z, x)
-                    }
-                    t.v[((size_t)k * (ncy + 1) + j) * (ncx + 1) + i] = v;
-                }
-        return t;
-    };
-    // axes in which each component is odd: xy -> (x, y), xz -> (x, z), yz -> (y, z)
-    const bool odd[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
     const double inv4piV = 1.0 / (4.0 * M_PI * dx * dy * dz);
     std::vector<std::complex<double>> a((size_t)Px * Py * Pz);
     for (int comp = 0; comp < 6; ++comp) {
-        const Table t = tab(comp);
+        const Table t = component_table(comp, ncx, ncy, ncz, dx, dy, dz);
         std::fill(a.begin(), a.end(), std::complex<double>(0.0, 0.0));
         for (int K = -(ncz - 1); K <= ncz - 1; ++K)
             for (int J = -(ncy - 1); J <= ncy - 1; ++J)
                 for (int I = -(ncx - 1); I <= ncx - 1; ++I) {
-                    double acc = 0.0;
-                    for (int ez = -1; ez <= 1; ++ez)
-                        for (int ey = -1; ey <= 1; ++ey)
-                            for (int ex = -1; ex <= 1; ++ex) {
-                                const int ii = I + ex, jj = J + ey, kk = K + ez;
-                                double sg = 1.0;
-                                if (odd[comp][0] && ii < 0) sg = -sg;
-                                if (odd[comp][1] && jj < 0) sg = -sg;
-                                if (odd[comp][2] && kk < 0) sg = -sg;
-                                const double w = (ex ? -1.0 : 2.0) * (ey ? -1.0 : 2.0) * (ez ? -1.0 : 2.0);
-                                acc += w * sg * t.at(std::abs(ii), std::abs(jj), std::abs(kk));
-                            }
                     const size_t ix = (size_t)((I + Px) % Px), iy = (size_t)((J + Py) % Py),
                                  iz = (size_t)((K + Pz) % Pz);
-                    a[(iz * Py + iy) * Px + ix] = acc * inv4piV * scale;
+                    a[(iz * Py + iy) * Px + ix] = tensor_element(t, comp, I, J, K) * inv4piV * scale;
                 }
         for (size_t r = 0; r < (size_t)Py * Pz; ++r) fft1(a.data() + r * Px, lx, 1);
         for (size_t z = 0; z < (size_t)Pz; ++z)
@@ -143,6 +158,42 @@ void demag_spectrum(int ncx, int ncy, int ncz, double dx, double dy, double dz, 
                 for (int kx = 0; kx < ox; ++kx)
                     octant[(((size_t)comp * oy + ky) * ox + kx) * oz + kz] =
                         a[((size_t)(kz % Pz) * Py + (ky % Py)) * Px + (kx % Px)].real();
+    }
+}
+
+// The same tensor transformed along x and y only, at the plane offsets
+// dz = 0 .. ncz-1: [Px/2+1][6][ncz][Py/2+1] (ky fastest, the order in which
+// neighbouring lanes of the y-z pass read it), times `scale`.
+// Along x and y the components are real and even or odd in each wavenumber
+// as above; xx, yy, zz and xy are real, xz and yz (odd along one in-plane
+// axis) imaginary, stored as their imaginary part.  Along z, xz and yz are
+// odd in dz, the others even.
+void demag_mixed(int ncx, int ncy, int ncz, double dx, double dy, double dz, int lx, int ly,
+                 double scale, std::vector<double> &table)
+{
+    const int Px = 1 << lx, Py = 1 << ly;
+    const int ox = Px / 2 + 1, oy = Py / 2 + 1;
+    table.assign((size_t)6 * ox * oy * ncz, 0.0);
+    const double inv4piV = 1.0 / (4.0 * M_PI * dx * dy * dz);
+    std::vector<std::complex<double>> a((size_t)Px * Py);
+    for (int comp = 0; comp < 6; ++comp) {
+        const Table t = component_table(comp, ncx, ncy, ncz, dx, dy, dz);
+        for (int K = 0; K < ncz; ++K) {
+            std::fill(a.begin(), a.end(), std::complex<double>(0.0, 0.0));
+            for (int J = -(ncy - 1); J <= ncy - 1; ++J)
+                for (int I = -(ncx - 1); I <= ncx - 1; ++I) {
+                    const size_t ix = (size_t)((I + Px) % Px), iy = (size_t)((J + Py) % Py);
+                    a[iy * Px + ix] = tensor_element(t, comp, I, J, K) * inv4piV * scale;
+                }
+            for (size_t r = 0; r < (size_t)Py; ++r) fft1(a.data() + r * Px, lx, 1);
+            for (size_t x = 0; x < (size_t)Px; ++x) fft1(a.data() + x, ly, Px);
+            const bool imag = comp >= 4;
+            for (int ky = 0; ky < oy; ++ky)
+                for (int kx = 0; kx < ox; ++kx) {
+                    const std::complex<double> v = a[(size_t)(ky % Py) * Px + (kx % Px)];
+                    table[(((size_t)kx * 6 + comp) * ncz + K) * oy + ky] = imag ? v.imag() : v.real();
+                }
+        }
     }
 }
 

@@ -67,7 +67,8 @@ struct Layout {
     // demagnetising field (when asd_params.demag_cell is set)
     DemagDev dm{};            // geometry; pointers filled at create
     size_t off_dwx = 0, off_dwy = 0, off_dbd[2] = {0, 0}, off_dK = 0, off_dtw[3] = {0, 0, 0};
-    size_t off_dcs[2] = {0, 0};  // cell sums of the cell-row kernels
+    size_t off_dcs[2] = {0, 0};  // cell sums of the cell-row and fused stage kernels
+    size_t dcs_bytes = 0;
     DemagDev dmT{};           // stray field of the frozen track (track systems only)
     size_t off_twx = 0, off_twy = 0, off_tK = 0, off_ttw = 0, off_tstray = 0;
     size_t bytes = 0;
@@ -382,6 +383,20 @@ static void fused_tiles_of(const asd_params *p, const asd_system_desc *d, int ti
     if (tz) *tz = (d->nz + len - 1) / len;
 }
 
+// partial-sum slots of the fused stage kernels of SC variant v: how many
+// tiles one coarse cell can meet along x, y and z
+static void stage_slots(const asd_params *p, const asd_system_desc *d, const int32_t *cell, int v,
+                        int *nsx, int *nsy, int *ns)
+{
+    int bx, by, fx, fy, fz, len;
+    fused_tile_interior(p->precision == ASD_FP64, v, &bx, &by, false);
+    fused_tiles_of(p, d, v, &fx, &fy, &fz, &len);
+    *nsx = (cell[0] - 1) / bx + 2;
+    *nsy = (cell[1] - 1) / by + 2;
+    const int nsz = fz > 1 ? (cell[2] - 1) / len + 2 : 1;
+    *ns = *nsx * *nsy * nsz;
+}
+
 static FastDivH host_fastdiv(uint32_t d)
 {
     FastDivH f;
@@ -520,7 +535,17 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         L.off_dwx = take((size_t)n_sys * 3 * g.ncz * g.ncy * Pxh * cplx);
         L.off_dwy = take((size_t)n_sys * 3 * g.ncz * Py * Pxh * cplx);
         for (int b = 0; b < 2; ++b) L.off_dbd[b] = take((size_t)n_sys * 3 * g.ncell * elem);
-        for (int b = 0; b < 2; ++b) L.off_dcs[b] = take((size_t)n_sys * 3 * g.ncell * elem);
+        // cell sums: one slot (cell-row kernels) or the fused stage kernels' partial slots
+        int ns_max = 1;
+        if (p->lattice == ASD_SC)
+            for (int v = 0; v < fused_count(false, p->precision == ASD_FP64); ++v) {
+                int nsx, nsy, ns;
+                stage_slots(p, &sys[0], p->demag_cell, v, &nsx, &nsy, &ns);
+                ns_max = std::max(ns_max, ns);
+            }
+        for (int b = 0; b < 2; ++b)
+            L.off_dcs[b] = take((size_t)n_sys * 3 * ns_max * g.ncell * elem);
+        L.dcs_bytes = (size_t)n_sys * 3 * ns_max * g.ncell * elem;
         L.off_dK = take(6 * (Px / 2 + 1) * (Py / 2 + 1) * (Pz / 2 + 1) * elem);
         L.off_dtw[0] = take(std::max<size_t>(Px / 2, 1) * cplx);
         L.off_dtw[1] = take(std::max<size_t>(Py / 2, 1) * cplx);
@@ -785,9 +810,23 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
         const double ex = p->a, ey = p->a, ez = p->lattice == ASD_SC ? p->a : p->c;
         const double dx = g.cx * ex, dy = g.cy * ey, dz = g.cz * ez;
         const int Px = 1 << g.lx, Py = 1 << g.ly, Pz = 1 << g.lz;
-        const double scale = -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)Px * Py * Pz));
+        // the one-workgroup y-z pass (direct sums along z) where its LDS fits
+        int lds_max = 0;
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) !=
+            hipSuccess)
+            lds_max = 0;
+        auto yz_fits = [&](const DemagDev &d) {
+            const size_t need = demag_yz_lds_bytes(d, h->elem);
+            return need > 0 && need <= (size_t)lds_max ? 1 : 0;
+        };
+        g.yzf = yz_fits(g);
         std::vector<double> oct;
-        demag_spectrum(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly, g.lz, scale, oct);
+        if (g.yzf)
+            demag_mixed(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly,
+                        -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)Px * Py)), oct);
+        else
+            demag_spectrum(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly, g.lz,
+                           -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)Px * Py * Pz)), oct);
         std::vector<char> buf(oct.size() * h->elem);
         for (size_t i = 0; i < oct.size(); ++i) {
             if (h->elem == 8) ((double *)buf.data())[i] = oct[i];
@@ -823,8 +862,13 @@ int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, v
         if (L.dmT.on) {
             DemagDev t = L.dmT;
             const int PxT = 1 << t.lx;
-            const double scaleT = -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)PxT * Py * Pz));
-            demag_spectrum(t.ncx, t.ncy, t.ncz, dx, dy, dz, t.lx, t.ly, t.lz, scaleT, oct);
+            t.yzf = yz_fits(t);
+            if (t.yzf)
+                demag_mixed(t.ncx, t.ncy, t.ncz, dx, dy, dz, t.lx, t.ly,
+                            -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)PxT * Py)), oct);
+            else
+                demag_spectrum(t.ncx, t.ncy, t.ncz, dx, dy, dz, t.lx, t.ly, t.lz,
+                               -kMu0 * p->mu_s / (((dx * dy) * dz) * ((double)PxT * Py * Pz)), oct);
             buf.assign(oct.size() * h->elem, 0);
             for (size_t i = 0; i < oct.size(); ++i) {
                 if (h->elem == 8) ((double *)buf.data())[i] = oct[i];
@@ -1735,9 +1779,15 @@ int asd_philox(uint64_t seed, int32_t rounds, const uint32_t *ctr, uint32_t *out
 // reason the fused kernel cannot serve this handle, or NULL
 static const char *fused_unsupported(const asd_t *h)
 {
-    if (h->dm.on)
-        return "the demagnetising field is a whole-mesh convolution between the two Heun "
-               "stages; the fused kernels run both stages in one launch";
+    if (h->dm.on) {
+        // the step runs as the predictor and corrector stages of the SC kernel
+        if (h->p.lattice != ASD_SC)
+            return "the demagnetising field needs the convolution between the two Heun stages; "
+                   "the fused L1_0 kernel runs both stages in one launch";
+        for (const HostSys &hs : h->sys)
+            if (hs.desc.bc_z != ASD_BC_OPEN)
+                return "the fused stage kernels for the demagnetising field march open z only";
+    }
     const int64_t elem = h->p.precision == ASD_FP64 ? 8 : 4;
     for (const HostSys &hs : h->sys) {
         if (hs.desc.bc_z != ASD_BC_OPEN && hs.desc.bc_z != ASD_BC_PERIODIC)
@@ -1782,6 +1832,16 @@ static int setup_fused_tiles(asd_t *h, int v)
     h->n_ftiles = (int)map.size();
     HIP_OK(h, hipMemcpyAsync(h->ws + h->L.off_ftile, map.data(), map.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, h->stream));
+    if (h->dm.on) {
+        // partial-sum slots of the stage kernels; slots no tile writes stay zero
+        int nsx, nsy, ns;
+        stage_slots(&h->p, &h->sys[0].desc, h->p.demag_cell, v, &nsx, &nsy, &ns);
+        h->dm.nsx = nsx;
+        h->dm.nsy = nsy;
+        h->dm.ns = ns;
+        for (int b = 0; b < 2; ++b)
+            HIP_OK(h, hipMemsetAsync(h->ws + h->L.off_dcs[b], 0, h->L.dcs_bytes, h->stream));
+    }
     return upload_sysdev(h);
 }
 
@@ -1803,6 +1863,8 @@ int asd_set_variant(asd_t *h, int32_t kernel, int32_t tile)
         if (why) return fail(h, ASD_EUNSUPPORTED, "%s", why);
         int rc = setup_fused_tiles(h, tile);
         if (rc) return rc;
+    } else if (h->dm.on) {
+        h->dm.ns = h->dm.nsx = h->dm.nsy = 1;  // the cell-row kernels write whole sums
     }
     h->kernel = kernel;
     h->tile_cfg = tile;

@@ -67,6 +67,10 @@ struct DemagDev {
     int32_t ncell;            // ncx * ncy * ncz
     int32_t lx, ly, lz;       // log2 of the padded sizes Px, Py, Pz
     int32_t xb_y, xb_z;       // x lines per workgroup in the y and z passes
+    int32_t yzf;              // 1: the y and z passes as one workgroup per (kx,
+                              // system) with direct sums along z (ncz <= 16): wx
+                              // kx-major [S][Px/2+1][3][ncz][ncy], K the tensor
+                              // transformed along x and y only (demag_mixed)
     int32_t n_sys;
     FastDivH fd_cx, fd_cy, fd_cz;
     // stray field of a frozen track: the same pipeline on a mesh that
@@ -79,16 +83,24 @@ struct DemagDev {
     int32_t ncell_win;        // track mesh: cells of the window mesh
     void *bstray;             // window mesh: added to the result when not null;
                               // track mesh: the output [S][3][ncell_win]
-    void *wx;                 // complex [S][3][ncz][ncy][Px/2+1] (Hermitian half in x)
+    void *wx;                 // complex [S][3][ncz][ncy][Px/2+1] (Hermitian half in x;
+                              // kx-major with yzf)
     void *wy;                 // complex [S][3][ncz][Py][Px/2+1]
     void *bd[2];              // field (T) per coarse cell, [S][3][ncell], one per Heun stage
     // cell-row step kernels (two-pass variant 2): the spin sums of every
     // coarse cell (T, [S][3][ncell]) as the kernels write the spins, [0] of
     // S' (predictor), [1] of the next spins (corrector); a workgroup takes
     // cr_cells cells along x of one layer (j, k), cr_segs workgroups per layer
+    // The fused stage kernels write partial sums per tile instead: slot
+    // (sz nsy + sy) nsx + sx of [S][3][ns][ncell] holds the part of a cell in
+    // the tile that is (sx, sy, sz) tiles past the first tile the cell meets
+    // (ns = nsx nsy nsz); the field pass adds the ns slots in order.  The
+    // cell-row kernels use one slot.
     void *cs[2];
     int32_t cr_cells, cr_segs;
+    int32_t ns, nsx, nsy;
     const void *K;            // tensor spectrum, octant [6][Py/2+1][Px/2+1][Pz/2+1]
+                              // (yzf: [Px/2+1][6][ncz][Py/2+1], see demag_mixed)
     const void *tw[3];        // twiddles exp(-2 pi i t / P), t < P / 2, per axis
 };
 
@@ -152,6 +164,12 @@ inline int launch_demag(const DemagDev &dm, const float *S, int64_t ncs, const S
 // host set-up (asd_demag_tensor.cpp): tensor spectrum octant, times scale
 void demag_spectrum(int ncx, int ncy, int ncz, double dx, double dy, double dz, int lx, int ly,
                     int lz, double scale, std::vector<double> &octant);
+// the tensor transformed along x and y only, at plane offsets 0 .. ncz-1
+void demag_mixed(int ncx, int ncy, int ncz, double dx, double dy, double dz, int lx, int ly,
+                 double scale, std::vector<double> &table);
+// dynamic LDS bytes of the one-workgroup y-z pass (0: ncz above 16); the
+// pass runs where this fits the device
+size_t demag_yz_lds_bytes(const DemagDev &dm, int elem);
 
 // launchers (asd_step_f64.hip / asd_step_f32.hip)
 int launch_plain_step_f64(const StepArgs<double> &a, int n_blocks, void *stream);

@@ -1157,9 +1157,21 @@ int asd_msd_create(asd_t *atoms, int32_t sys, asd_mm_t *left, asd_mm_t *right, i
     DemagDev &g = m->dm;
     const int Px = 1 << g.lx, Py = 1 << g.ly, Pz = 1 << g.lz;
     const double dx = cx * edge[0], dy = cy * edge[1], dz = cz * edge[2];
-    const double scale = -1.25663706212e-6 * m->mu_s / (((dx * dy) * dz) * ((double)Px * Py * Pz));
+    // the one-workgroup y-z pass (direct sums along z) where its LDS fits
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds_max = 0;
+    const size_t need = demag_yz_lds_bytes(g, (int)sizeof(double));
+    g.yzf = need > 0 && need <= (size_t)lds_max ? 1 : 0;
     std::vector<double> oct;
-    demag_spectrum(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly, g.lz, scale, oct);
+    if (g.yzf)
+        demag_mixed(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly,
+                    -1.25663706212e-6 * m->mu_s / (((dx * dy) * dz) * ((double)Px * Py)), oct);
+    else
+        demag_spectrum(g.ncx, g.ncy, g.ncz, dx, dy, dz, g.lx, g.ly, g.lz,
+                       -1.25663706212e-6 * m->mu_s / (((dx * dy) * dz) * ((double)Px * Py * Pz)),
+                       oct);
     hipError_t e = hipMemcpyAsync(m->ws + m->off_K, oct.data(), oct.size() * sizeof(double),
                                   hipMemcpyHostToDevice, st);
     std::vector<std::vector<double>> tw(3);

@@ -212,19 +212,21 @@ def test_heun_with_demag_matches_oracle(name, w, cell, n_sys, prec, variant):
     h.close()
 
 
-@pytest.mark.parametrize("variant", [0, 2], ids=["recompute", "cellrows"])
+@pytest.mark.parametrize("kernel,variant", [(A.ASD_KERNEL_PLAIN, 0), (A.ASD_KERNEL_PLAIN, 2),
+                                            (A.ASD_KERNEL_FUSED, 0)],
+                         ids=["recompute", "cellrows", "fused_stages"])
 @pytest.mark.parametrize("prec,cell", [(A.ASD_FP64, (5, 4, 5)), (A.ASD_FP32, (5, 4, 5)),
                                        (A.ASD_FP64, (4, 3, 2)), (A.ASD_FP32, (7, 6, 3))],
                          ids=["fp64_5x4x5", "fp32_5x4x5", "fp64_4x3x2", "fp32_7x6x3_ragged"])
-def test_track_with_demag_and_shifts(prec, cell, variant):
+def test_track_with_demag_and_shifts(prec, cell, kernel, variant):
     """Moving window: the demagnetising mesh moves with the window and the frozen
     track's stray field is recomputed after every shift; graph-captured segments
     (the demag kernels are plain launches, no memset nodes) replayed."""
     w = track()
     shifts = [(10, 1), (20, 2)]
     steps = 40
-    h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10)
-    h.set_variant(A.ASD_KERNEL_PLAIN, variant)
+    h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10, kernel=kernel)
+    h.set_variant(kernel, variant)
     lab = h.labels()
     S0 = random_state(w, lab, 5)
     h.set_spins(S0)
@@ -277,6 +279,73 @@ def test_cell_rows_match_two_pass_over_100_steps(prec):
     assert err <= bar
 
 
+# (name, workload, coarse cell, precision, fused variants): tiles narrower than
+# a cell (14 interior columns), z chunks of 8 and 11 planes cutting layers of
+# cells, one chunk, and the widest tiles
+FUSED_STAGE_CASES = [
+    ("sc_fp64_chunks", sc_slab(nz=20), (4, 3, 3), A.ASD_FP64, [0, 1, 5]),
+    ("sc_fp32_chunks", sc_slab(nz=20), (4, 3, 3), A.ASD_FP32, [0, 2, 12, 14]),
+    ("sc_fp32_2sys", sc_slab(), (5, 4, 2), A.ASD_FP32, [0, 9]),
+    ("sc_fp32_wide_cells", sc_slab(nx=70), (20, 7, 7), A.ASD_FP32, [2, 14]),
+]
+
+
+@pytest.mark.parametrize("name,w,cell,prec,variants", FUSED_STAGE_CASES,
+                         ids=[c[0] for c in FUSED_STAGE_CASES])
+def test_fused_stages_with_demag_match_oracle(name, w, cell, prec, variants):
+    """The fused kernel as predictor and corrector stages with the field between
+    them: each stage adds its field at the site's cell and writes per-tile parts
+    of the cell sums for the next evaluation.  Graph segments of ten steps: nine
+    of every ten evaluations start from those parts."""
+    steps = 30
+    n_sys = 2 if "2sys" in name else 1
+    dn, dd, dcell = demag_cells(w, cell)
+    refs = []
+    S0 = None
+    for v in variants:
+        h = bridge.make_handle(w, prec, n_systems=n_sys, demag_cell=cell, graph_steps=10,
+                               kernel=A.ASD_KERNEL_FUSED)
+        h.set_variant(A.ASD_KERNEL_FUSED, v)
+        lab = h.labels()
+        if S0 is None:
+            S0 = [random_state(w, lab, 31 + s) for s in range(n_sys)]
+            for s in range(n_sys):
+                sysm = oracle_system(w, labels=oracle_labels(w), sys_id=s)
+                sysm.set_demag((dn, dd, dcell))
+                refs.append(sysm.heun(S0[s], 0, steps))
+        for s in range(n_sys):
+            h.set_spins(S0[s], s)
+        h.step(steps)
+        for s in range(n_sys):
+            err = float(np.max(np.abs(h.get_spins(s).astype(np.float64) - refs[s])))
+            say(f"[fused stages] {name} variant {v} ({h.variant_name()}) system {s}: "
+                f"max |dS| = {err:.3e}")
+            assert err <= SPIN_TOL[prec], (name, v, s, err)
+        h.close()
+
+
+@pytest.mark.parametrize("prec", [A.ASD_FP64, A.ASD_FP32], ids=["fp64", "fp32"])
+def test_fused_stages_match_two_pass_over_100_steps(prec):
+    """The fused stage kernels against the two-pass kernels over 100 steps from
+    the same state (FP64 within 1e-12)."""
+    w = sc_slab(nx=150, ny=13, nz=9)
+    cell = (2, 3, 2)
+    out = {}
+    for kernel, variant in ((A.ASD_KERNEL_PLAIN, 0), (A.ASD_KERNEL_FUSED, 0)):
+        h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10, kernel=kernel)
+        h.set_variant(kernel, variant)
+        S0 = random_state(w, h.labels(), 78)
+        h.set_spins(S0)
+        h.step(95)
+        h.step(5)
+        out[kernel] = h.get_spins().astype(np.float64)
+        h.close()
+    err = float(np.max(np.abs(out[A.ASD_KERNEL_FUSED] - out[A.ASD_KERNEL_PLAIN])))
+    bar = 1e-12 if prec == A.ASD_FP64 else 1e-4
+    say(f"[fused stages vs two-pass] prec={prec}: max |dS| after 100 steps = {err:.3e}")
+    assert err <= bar
+
+
 def test_track_stray_field_at_the_largest_track():
     """The track mesh at its limit: 254 coarse columns along the stored track."""
     w = track(track_nx=254 * 2, nx=40, ny=6, nz=2, grains=False)
@@ -310,16 +379,22 @@ def test_demag_error_paths():
     with pytest.raises(A.AsdError) as e:
         bridge.make_handle(w.scaled(nx=600), A.ASD_FP32, demag_cell=(2, 1, 1))
     assert e.value.code == A.ASD_EUNSUPPORTED
-    with pytest.raises(A.AsdError) as e:
-        bridge.make_handle(w, A.ASD_FP32, kernel=A.ASD_KERNEL_FUSED, demag_cell=(2, 2, 2))
-    assert e.value.code == A.ASD_EUNSUPPORTED
-    # AUTO falls back to the two-pass kernels, the cell-row variant by default
+    # the fused stage kernels: SC with open z; L1_0 and periodic z take the two-pass kernels
+    for wl in (l10_slab(), w.scaled(bc=(0, 0, 1))):
+        with pytest.raises(A.AsdError) as e:
+            bridge.make_handle(wl, A.ASD_FP32, kernel=A.ASD_KERNEL_FUSED, demag_cell=(2, 2, 2))
+        assert e.value.code == A.ASD_EUNSUPPORTED
+        h = bridge.make_handle(wl, A.ASD_FP32, kernel=A.ASD_KERNEL_AUTO, demag_cell=(2, 2, 2))
+        assert h.variant() == (A.ASD_KERNEL_PLAIN, 2)
+        assert h.variant_name().startswith("k_cell_step")
+        with pytest.raises(A.AsdError) as e:
+            h.set_variant(A.ASD_KERNEL_FUSED, 0)
+        assert e.value.code == A.ASD_EUNSUPPORTED
+        h.close()
     h = bridge.make_handle(w, A.ASD_FP32, kernel=A.ASD_KERNEL_AUTO, demag_cell=(2, 2, 2))
-    assert h.variant() == (A.ASD_KERNEL_PLAIN, 2)
+    assert h.variant() == (A.ASD_KERNEL_FUSED, 0)
+    h.set_variant(A.ASD_KERNEL_PLAIN, 2)
     assert h.variant_name().startswith("k_cell_step")
-    with pytest.raises(A.AsdError) as e:
-        h.set_variant(A.ASD_KERNEL_FUSED, 0)
-    assert e.value.code == A.ASD_EUNSUPPORTED
     h.close()
     h = bridge.make_handle(w, A.ASD_FP32)
     with pytest.raises(A.AsdError) as e:
