@@ -21,6 +21,8 @@
 // per stage; the padded sizes are powers of two.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "asd.h"
 #include "asd_device.h"
 #include "asd_internal.h"
@@ -331,10 +333,17 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
 constexpr int kDmYzThreads = 512;
 
 template <typename T, int NCZ, int Q0>
-__device__ __forceinline__ void yz_column(const T *__restrict__ kt, int oy, T sy, const Cx<T> *r,
-                                          Cx<T> *o, int ls, int ky)
+__device__ __forceinline__ void yz_column(const T *__restrict__ kt, int oy, T sy,
+                                          const Cx<T> *__restrict__ r, Cx<T> *__restrict__ o,
+                                          int ls, int ky)
 {
     constexpr int Q = 4;
+    // the sources of this ky (3 NCZ values) once
+    Cx<T> m[3][NCZ];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int zs = 0; zs < NCZ; ++zs) m[c][zs] = r[(c * NCZ + zs) * ls + ky];
     // tensor along z at offsets 0 .. NCZ-1 (kt + (comp NCZ + d) oy); xy and
     // yz are odd in ky, xz and yz odd in dz and imaginary (stored as such)
     T nxx[NCZ], nyy[NCZ], nzz[NCZ], nxy[NCZ], txz[NCZ], tyz[NCZ];
@@ -354,8 +363,7 @@ __device__ __forceinline__ void yz_column(const T *__restrict__ kt, int oy, T sy
         for (int zs = 0; zs < NCZ; ++zs) {
             const int d = z - zs, ad = d < 0 ? -d : d;
             const T sg = d < 0 ? T(-1) : T(1);
-            const Cx<T> mx = r[(0 * NCZ + zs) * ls + ky], my = r[(1 * NCZ + zs) * ls + ky],
-                        mz = r[(2 * NCZ + zs) * ls + ky];
+            const Cx<T> mx = m[0][zs], my = m[1][zs], mz = m[2][zs];
             const T Nxx = nxx[ad], Nyy = nyy[ad], Nzz = nzz[ad], Nxy = nxy[ad];
             const T Txz = sg * txz[ad], Tyz = sg * tyz[ad];
             // H += N M with N_xz = i Txz, N_yz = i Tyz
@@ -380,14 +388,16 @@ __global__ __launch_bounds__(kDmYzThreads) void k_dm_yz(DemagDev dm)
     const int Pxh = (Px >> 1) + 1;
     const int kx = blockIdx.x, s = blockIdx.y;
     const int ncy = dm.ncy, ls = Py + 1;
-    Cx<T> *bx = lds_base<T>(), *by = bx + nl * ls;
+    Cx<T> *bx = lds_base<T>(), *by = bx + nl * ls, *twy = by + nl * ls;
     Cx<T> *w = (Cx<T> *)dm.wx + ((int64_t)s * Pxh + kx) * nl * ncy;
     for (int q = threadIdx.x; q < nl * Py; q += blockDim.x) {
         const int line = q >> dm.ly, yy = q & (Py - 1);
         bx[line * ls + yy] = yy < ncy ? w[line * ncy + yy] : Cx<T>{T(0), T(0)};
     }
+    // the twiddles of the y transforms in LDS
+    for (int q = threadIdx.x; q < max(Py >> 1, 1); q += blockDim.x) twy[q] = ((const Cx<T> *)dm.tw[1])[q];
     __syncthreads();
-    Cx<T> *r = fft_lines<T, false>(bx, by, nl, dm.ly, ls, (const Cx<T> *)dm.tw[1]);
+    Cx<T> *r = fft_lines<T, false>(bx, by, nl, dm.ly, ls, twy);
     Cx<T> *o = r == bx ? by : bx;
     const int oy = (Py >> 1) + 1;
     const T *kt0 = (const T *)dm.K + (int64_t)kx * 6 * NCZ * oy;
@@ -404,7 +414,7 @@ __global__ __launch_bounds__(kDmYzThreads) void k_dm_yz(DemagDev dm)
         }
     }
     __syncthreads();
-    const Cx<T> *h = fft_lines<T, true>(o, r, nl, dm.ly, ls, (const Cx<T> *)dm.tw[1]);
+    const Cx<T> *h = fft_lines<T, true>(o, r, nl, dm.ly, ls, twy);
     for (int q = threadIdx.x; q < nl * ncy; q += blockDim.x) {
         const int line = q / ncy, yy = q - line * ncy;
         w[line * ncy + yy] = h[line * ls + yy];
@@ -498,7 +508,9 @@ size_t demag_yz_lds_bytes(const DemagDev &dm, int elem)
     // the unrolled sums keep their operands in registers: up to 16 planes
     // (12 in FP64)
     if (dm.ncz > (elem == 8 ? 12 : 16)) return 0;
-    return (size_t)2 * 3 * dm.ncz * ((size_t)(1 << dm.ly) + 1) * 2 * elem;
+    // two line buffers and the y twiddles
+    return ((size_t)2 * 3 * dm.ncz * ((size_t)(1 << dm.ly) + 1) + std::max((1 << dm.ly) / 2, 1)) *
+           2 * elem;
 }
 
 int launch_demag_f64(const DemagDev &dm, const double *S, int64_t ncs, const SysDev *sys,
