@@ -119,8 +119,7 @@ __device__ Cx<T> *fft_lines(Cx<T> *x, Cx<T> *y, int nl, int lp, int ls,
 __device__ __forceinline__ int64_t wx_at(const DemagDev &dm, int s, int c, int k, int j, int kx,
                                          int Pxh)
 {
-    return dm.yzf ? ((((int64_t)s * Pxh + kx) * 3 + c) * dm.ncz + k) * dm.ncy + j
-                  : ((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx;
+    return ((((int64_t)s * 3 + c) * dm.ncz + k) * dm.ncy + j) * Pxh + kx;
 }
 
 template <typename T>
@@ -324,7 +323,7 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
 }
 
 // --- 2-4 in one workgroup per (kx, system) when yzf: the 3 NCZ rows of
-// column kx (kx-major in wx) into LDS; FFT along y; per ky the field planes
+// column kx into LDS; FFT along y; per ky the field planes
 // as direct sums over the source planes with the tensor transformed along x
 // and y only, so the convolution along z needs neither padding nor
 // transforms; inverse FFT along y; the ncy rows back.  Lanes: four groups of
@@ -386,13 +385,20 @@ __global__ __launch_bounds__(kDmYzThreads) void k_dm_yz(DemagDev dm)
     constexpr int Q = 4, nl = 3 * NCZ;
     const int Px = 1 << dm.lx, Py = 1 << dm.ly;
     const int Pxh = (Px >> 1) + 1;
-    const int kx = blockIdx.x, s = blockIdx.y;
+    // blocks go round-robin over the eight XCDs: give each XCD a contiguous
+    // range of columns, so that the neighbouring columns that share the
+    // cache lines of wx are read through the same L2
+    const int nb = Pxh * dm.n_sys, per = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= nb) return;
+    const int kx = tile % Pxh, s = tile / Pxh;
     const int ncy = dm.ncy, ls = Py + 1;
     Cx<T> *bx = lds_base<T>(), *by = bx + nl * ls, *twy = by + nl * ls;
-    Cx<T> *w = (Cx<T> *)dm.wx + ((int64_t)s * Pxh + kx) * nl * ncy;
+    // line (c, z) row y of column kx at ((s 3 ncz + line) ncy + y) Pxh + kx
+    Cx<T> *w = (Cx<T> *)dm.wx + (int64_t)s * nl * ncy * Pxh + kx;
     for (int q = threadIdx.x; q < nl * Py; q += blockDim.x) {
         const int line = q >> dm.ly, yy = q & (Py - 1);
-        bx[line * ls + yy] = yy < ncy ? w[line * ncy + yy] : Cx<T>{T(0), T(0)};
+        bx[line * ls + yy] = yy < ncy ? w[((int64_t)line * ncy + yy) * Pxh] : Cx<T>{T(0), T(0)};
     }
     // the twiddles of the y transforms in LDS
     for (int q = threadIdx.x; q < max(Py >> 1, 1); q += blockDim.x) twy[q] = ((const Cx<T> *)dm.tw[1])[q];
@@ -417,7 +423,7 @@ __global__ __launch_bounds__(kDmYzThreads) void k_dm_yz(DemagDev dm)
     const Cx<T> *h = fft_lines<T, true>(o, r, nl, dm.ly, ls, twy);
     for (int q = threadIdx.x; q < nl * ncy; q += blockDim.x) {
         const int line = q / ncy, yy = q - line * ncy;
-        w[line * ncy + yy] = h[line * ls + yy];
+        w[((int64_t)line * ncy + yy) * Pxh] = h[line * ls + yy];
     }
 }
 
@@ -480,7 +486,7 @@ int run_demag(const DemagDev &dm, const T *S, int64_t ncs, const SysDev *sys,
                            origin);
     const int Pxh = (Px >> 1) + 1;
     if (dm.yzf) {
-        const dim3 g(Pxh, dm.n_sys), b(kDmYzThreads);
+        const dim3 g((Pxh * dm.n_sys + 7) / 8 * 8), b(kDmYzThreads);
         const size_t lds = demag_yz_lds_bytes(dm, (int)sizeof(T));
 #define ASD_YZ(N)                                                                                  \
     case N: hipLaunchKernelGGL((k_dm_yz<T, N>), g, b, lds, st, dm); break;

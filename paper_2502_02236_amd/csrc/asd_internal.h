@@ -68,9 +68,9 @@ struct DemagDev {
     int32_t lx, ly, lz;       // log2 of the padded sizes Px, Py, Pz
     int32_t xb_y, xb_z;       // x lines per workgroup in the y and z passes
     int32_t yzf;              // 1: the y and z passes as one workgroup per (kx,
-                              // system) with direct sums along z (ncz <= 16): wx
-                              // kx-major [S][Px/2+1][3][ncz][ncy], K the tensor
-                              // transformed along x and y only (demag_mixed)
+                              // system) with direct sums along z (ncz <= 16), K
+                              // the tensor transformed along x and y only
+                              // (demag_mixed)
     int32_t n_sys;
     FastDivH fd_cx, fd_cy, fd_cz;
     // stray field of a frozen track: the same pipeline on a mesh that
@@ -83,8 +83,7 @@ struct DemagDev {
     int32_t ncell_win;        // track mesh: cells of the window mesh
     void *bstray;             // window mesh: added to the result when not null;
                               // track mesh: the output [S][3][ncell_win]
-    void *wx;                 // complex [S][3][ncz][ncy][Px/2+1] (Hermitian half in x;
-                              // kx-major with yzf)
+    void *wx;                 // complex [S][3][ncz][ncy][Px/2+1] (Hermitian half in x)
     void *wy;                 // complex [S][3][ncz][Py][Px/2+1]
     void *bd[2];              // field (T) per coarse cell, [S][3][ncell], one per Heun stage
     // cell-row step kernels (two-pass variant 2): the spin sums of every
