@@ -1906,8 +1906,11 @@ int asd_variant_name(asd_t *h, char *buf, size_t len)
             if (hs.desc.bc_z == ASD_BC_PERIODIC) zper = true;
         if (l10)
             snprintf(tmp, sizeof tmp, "k_fused_l10<%s, %d, %d, %d>", T, f.txe, f.waves, f.rows);
+        else if (h->dm.on)  // the predictor and corrector stages (open z only)
+            snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d, false, 1>+k_fused_sc<%s, %d, %d, %d, false, 2>",
+                     T, f.txe, f.waves, f.rows, T, f.txe, f.waves, f.rows);
         else
-            snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d, %s>", T, f.txe, f.waves, f.rows,
+            snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d, %s, 0>", T, f.txe, f.waves, f.rows,
                      zper ? "true" : "false");
     } else if (h->tile_cfg == 1) {
         snprintf(tmp, sizeof tmp, "k_plain_predictor<%s, true>+k_stash_corrector<%s>", T, T);
