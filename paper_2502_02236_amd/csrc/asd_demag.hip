@@ -331,56 +331,68 @@ __global__ __launch_bounds__(kDmThreads) void k_dm_z(DemagDev dm)
 // unrolled sums need no divergent branches).
 constexpr int kDmYzThreads = 512;
 
+// one output component of the planes z = Q0, Q0 + 4, ... of one ky:
+// H_c(z) = sum_zs [A(z - zs) Mx + B(z - zs) My + C(z - zs) Mz] with the three
+// tensor components of row c (A, B, C; IA/IB/IC: the component is the
+// imaginary one, odd in dz)
+template <typename T, int NCZ, int Q0, bool IA, bool IB, bool IC>
+__device__ __forceinline__ void yz_row(const T *__restrict__ ka, const T *__restrict__ kb,
+                                       const T *__restrict__ kc, T sa, T sb, T sc, int oy,
+                                       const Cx<T> (&m)[3][NCZ], Cx<T> *__restrict__ o, int ls,
+                                       int ky, int c)
+{
+    constexpr int Q = 4;
+    T ta[NCZ], tb[NCZ], tc[NCZ];
+#pragma unroll
+    for (int d = 0; d < NCZ; ++d) {
+        ta[d] = sa * ka[d * (int64_t)oy];
+        tb[d] = sb * kb[d * (int64_t)oy];
+        tc[d] = sc * kc[d * (int64_t)oy];
+    }
+#pragma unroll
+    for (int z = Q0; z < NCZ; z += Q) {
+        T hr = T(0), hi = T(0);
+#pragma unroll
+        for (int zs = 0; zs < NCZ; ++zs) {
+            const int d = z - zs, ad = d < 0 ? -d : d;
+            const T sg = d < 0 ? T(-1) : T(1);
+            // a real component adds t m; an imaginary one (i t, odd in dz) adds i sg t m
+            const T A = IA ? sg * ta[ad] : ta[ad], Bv = IB ? sg * tb[ad] : tb[ad],
+                    Cv = IC ? sg * tc[ad] : tc[ad];
+            hr = hr + ((IA ? -A * m[0][zs].im : A * m[0][zs].re) +
+                       (IB ? -Bv * m[1][zs].im : Bv * m[1][zs].re)) +
+                 (IC ? -Cv * m[2][zs].im : Cv * m[2][zs].re);
+            hi = hi + ((IA ? A * m[0][zs].re : A * m[0][zs].im) +
+                       (IB ? Bv * m[1][zs].re : Bv * m[1][zs].im)) +
+                 (IC ? Cv * m[2][zs].re : Cv * m[2][zs].im);
+        }
+        o[(c * NCZ + z) * ls + ky] = Cx<T>{hr, hi};
+    }
+}
+
+// the three output components of one ky (tensor at kt + (comp NCZ + d) oy;
+// xy and yz odd in ky, xz and yz imaginary and odd in dz)
 template <typename T, int NCZ, int Q0>
 __device__ __forceinline__ void yz_column(const T *__restrict__ kt, int oy, T sy,
                                           const Cx<T> *__restrict__ r, Cx<T> *__restrict__ o,
                                           int ls, int ky)
 {
-    constexpr int Q = 4;
     // the sources of this ky (3 NCZ values) once
     Cx<T> m[3][NCZ];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int zs = 0; zs < NCZ; ++zs) m[c][zs] = r[(c * NCZ + zs) * ls + ky];
-    // tensor along z at offsets 0 .. NCZ-1 (kt + (comp NCZ + d) oy); xy and
-    // yz are odd in ky, xz and yz odd in dz and imaginary (stored as such)
-    T nxx[NCZ], nyy[NCZ], nzz[NCZ], nxy[NCZ], txz[NCZ], tyz[NCZ];
-#pragma unroll
-    for (int d = 0; d < NCZ; ++d) {
-        nxx[d] = kt[(0 * NCZ + d) * (int64_t)oy];
-        nyy[d] = kt[(1 * NCZ + d) * (int64_t)oy];
-        nzz[d] = kt[(2 * NCZ + d) * (int64_t)oy];
-        nxy[d] = sy * kt[(3 * NCZ + d) * (int64_t)oy];
-        txz[d] = kt[(4 * NCZ + d) * (int64_t)oy];
-        tyz[d] = sy * kt[(5 * NCZ + d) * (int64_t)oy];
-    }
-#pragma unroll
-    for (int z = Q0; z < NCZ; z += Q) {
-        T hxr = T(0), hxi = T(0), hyr = T(0), hyi = T(0), hzr = T(0), hzi = T(0);
-#pragma unroll
-        for (int zs = 0; zs < NCZ; ++zs) {
-            const int d = z - zs, ad = d < 0 ? -d : d;
-            const T sg = d < 0 ? T(-1) : T(1);
-            const Cx<T> mx = m[0][zs], my = m[1][zs], mz = m[2][zs];
-            const T Nxx = nxx[ad], Nyy = nyy[ad], Nzz = nzz[ad], Nxy = nxy[ad];
-            const T Txz = sg * txz[ad], Tyz = sg * tyz[ad];
-            // H += N M with N_xz = i Txz, N_yz = i Tyz
-            hxr = hxr + ((Nxx * mx.re + Nxy * my.re) - Txz * mz.im);
-            hxi = hxi + ((Nxx * mx.im + Nxy * my.im) + Txz * mz.re);
-            hyr = hyr + ((Nxy * mx.re + Nyy * my.re) - Tyz * mz.im);
-            hyi = hyi + ((Nxy * mx.im + Nyy * my.im) + Tyz * mz.re);
-            hzr = hzr + ((Nzz * mz.re - Txz * mx.im) - Tyz * my.im);
-            hzi = hzi + ((Nzz * mz.im + Txz * mx.re) + Tyz * my.re);
-        }
-        o[(0 * NCZ + z) * ls + ky] = Cx<T>{hxr, hxi};
-        o[(1 * NCZ + z) * ls + ky] = Cx<T>{hyr, hyi};
-        o[(2 * NCZ + z) * ls + ky] = Cx<T>{hzr, hzi};
-    }
+    const int64_t cs = (int64_t)NCZ * oy;  // component stride
+    const T *kxx = kt, *kyy = kt + cs, *kzz = kt + 2 * cs, *kxy = kt + 3 * cs, *kxz = kt + 4 * cs,
+            *kyz = kt + 5 * cs;
+    yz_row<T, NCZ, Q0, false, false, true>(kxx, kxy, kxz, T(1), sy, T(1), oy, m, o, ls, ky, 0);
+    yz_row<T, NCZ, Q0, false, false, true>(kxy, kyy, kyz, sy, T(1), sy, oy, m, o, ls, ky, 1);
+    yz_row<T, NCZ, Q0, true, true, false>(kxz, kyz, kzz, T(1), sy, T(1), oy, m, o, ls, ky, 2);
 }
 
 template <typename T, int NCZ>
-__global__ __launch_bounds__(kDmYzThreads) void k_dm_yz(DemagDev dm)
+__global__ __launch_bounds__(kDmYzThreads, sizeof(T) == 4 && NCZ <= 11 ? 4 : 2) void k_dm_yz(DemagDev dm)
 {
     constexpr int Q = 4, nl = 3 * NCZ;
     const int Px = 1 << dm.lx, Py = 1 << dm.ly;
