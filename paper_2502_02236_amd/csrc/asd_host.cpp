@@ -369,12 +369,19 @@ static int grain_count_of(const asd_params *p, const asd_system_desc *d)
     return 1;
 }
 
+// tiles of fused variant tile_cfg along x, y, z (and the z chunk length);
+// stage: the stage kernels of the step with the demagnetising field, whose
+// whole extended tile is interior
 static void fused_tiles_of(const asd_params *p, const asd_system_desc *d, int tile_cfg, int *tx,
-                           int *ty, int *tz = nullptr, int *lz = nullptr)
+                           int *ty, int *tz = nullptr, int *lz = nullptr, bool stage = false)
 {
     int bx, by;
     const bool l10 = p->lattice == ASD_L10;
     fused_tile_interior(p->precision == ASD_FP64, tile_cfg, &bx, &by, l10);
+    if (stage) {
+        bx += 2;
+        by += 2;
+    }
     *tx = (d->nx + bx - 1) / bx;
     *ty = (d->ny + by - 1) / by;
     const FusedVariant f = fused_pick(l10, p->precision == ASD_FP64, tile_cfg);
@@ -390,7 +397,9 @@ static void stage_slots(const asd_params *p, const asd_system_desc *d, const int
 {
     int bx, by, fx, fy, fz, len;
     fused_tile_interior(p->precision == ASD_FP64, v, &bx, &by, false);
-    fused_tiles_of(p, d, v, &fx, &fy, &fz, &len);
+    bx += 2;  // the stage kernels' tiles have no halo
+    by += 2;
+    fused_tiles_of(p, d, v, &fx, &fy, &fz, &len, true);
     *nsx = (cell[0] - 1) / bx + 2;
     *nsy = (cell[1] - 1) / by + 2;
     const int nsz = fz > 1 ? (cell[2] - 1) / len + 2 : 1;
@@ -1818,7 +1827,7 @@ static int setup_fused_tiles(asd_t *h, int v)
     std::vector<int32_t> map;
     for (size_t s = 0; s < h->sys.size(); ++s) {
         int fx, fy, fz, lz;
-        fused_tiles_of(&h->p, &h->sys[s].desc, v, &fx, &fy, &fz, &lz);
+        fused_tiles_of(&h->p, &h->sys[s].desc, v, &fx, &fy, &fz, &lz, h->dm.on != 0);
         SysDev &d = h->dev[s];
         d.ftile_base = (int32_t)map.size();
         d.ftiles_x = fx;
