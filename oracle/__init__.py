@@ -69,6 +69,7 @@ class OrcSystem(C.Structure):
         ("T_peak", C.c_double), ("fwhm", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
         ("v", C.c_double), ("seed", C.c_uint64), ("rounds", C.c_int),
         ("dn", C.c_int * 3), ("dd", C.c_double * 3), ("dcell", i32p), ("bstray", f64p),
+        ("demag_once", C.c_int),
     ]
 
 
@@ -269,12 +270,15 @@ class System:
         self._s = s
         self.set_demag(demag)
 
-    def set_demag(self, demag, stray=None):
+    def set_demag(self, demag, stray=None, once=False):
         """demag = (dn, dd, dcell): coarse mesh (cells along x, y, z), cell
         edges (m) and the coarse cell of every site (-1 = none); None = off.
         stray: float[3, ncell] field (T) of sources outside the evolving sites,
-        added to every cell's demagnetising field (None = none)."""
+        added to every cell's demagnetising field (None = none).  once: the
+        field evaluated once per step from the step's starting spins and held
+        through both Heun stages (else at both stages)."""
         s = self._s
+        s.demag_once = 1 if once else 0
         self.bstray = None if stray is None else np.ascontiguousarray(stray, np.float64).reshape(-1)
         s.bstray = _ptr(self.bstray, f64p)
         if demag is None:

@@ -583,8 +583,9 @@ int orc_heun_steps(const orc_system *s, double *Sx, double *Sy, double *Sz, int6
             Px[i] = P[0]; Py[i] = P[1]; Pz[i] = P[2];
             f0[3 * i + 0] = f[0]; f0[3 * i + 1] = f[1]; f0[3 * i + 2] = f[2];
         }
-        /* corrector with the predicted configuration and the same noise */
-        if (bd && demag_cells(s, Px, Py, Pz, bd) != 0) {
+        /* corrector with the predicted configuration and the same noise (the
+         * demagnetising field of S' too, unless it is held through the step) */
+        if (bd && !s->demag_once && demag_cells(s, Px, Py, Pz, bd) != 0) {
             free(Px); free(Py); free(Pz); free(f0); free(bth); free(bd);
             return -1;
         }

@@ -51,13 +51,18 @@ typedef struct orc_system {
     uint64_t seed;
     int rounds;
     /* demagnetising field of the evolving sites (Eq. 7 on the coarse cells
-     * of Eq. 6), evaluated at both Heun stages from that stage's spins;
-     * dcell[i] = coarse cell of site i or -1; dn[0] = 0 switches it off */
+     * of Eq. 6), evaluated at both Heun stages from that stage's spins (or
+     * once per step, demag_once); dcell[i] = coarse cell of site i or -1;
+     * dn[0] = 0 switches it off */
     int dn[3];              /* coarse mesh, cells along x, y, z */
     double dd[3];           /* coarse cell edges (m) */
     const int32_t *dcell;
     const double *bstray;   /* [3][ncell] field (T) of sources outside the
                                evolving sites, added per coarse cell; or NULL */
+    int demag_once;         /* 0: the field is evaluated at both Heun stages
+                               from that stage's spins; 1: once per step, from
+                               the step's starting spins, and held through
+                               both stages */
 } orc_system;
 
 void orc_philox4x32(int rounds, uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4]);

@@ -197,3 +197,36 @@ def test_track_stray_plus_window_field_is_whole_track_field(origin, cell):
     win = (i + i0 + nt * (j + dn[1] * k)).transpose(2, 1, 0).reshape(-1)
     np.testing.assert_allclose(own + stray, Ball[:, win], rtol=0, atol=1e-12)
     assert np.max(np.abs(stray)) > 1e-3
+
+
+def test_field_once_per_step_is_a_field_held_through_the_step():
+    """Reading in which the demagnetising field is evaluated once per step: one
+    coarse cell covering a block gives one field, B_d(S_n), at every site; held
+    through both Heun stages it must act exactly like a uniform applied field of
+    that value (polarity +1), to rounding.  A slip that re-evaluates the field
+    at S' (the other reading), drops it from a stage, or takes it from another
+    configuration, moves the spins by far more than rounding."""
+    w = W.c1_plain_sc().scaled(nx=5, ny=4, nz=3, bc=(0, 0, 0), B=(0.05, -0.02, 0.3), T_amb=300.0)
+    n = w.n_sites
+    dd = (w.nx * w.a, w.ny * w.a, w.nz * w.a)
+    rng = np.random.default_rng(11)
+    S0 = rng.normal(size=(3, n))
+    S0 /= np.linalg.norm(S0, axis=0)
+    one = ((1, 1, 1), dd, np.zeros(n, np.int32))
+    Bd = oracle.demag_field(S0, np.zeros(n, np.int32), (1, 1, 1), dd, w.mu_s)[:, 0]
+    assert np.max(np.abs(Bd)) > 1e-3  # a random state still has a net moment
+    once = oracle_system(w)
+    once.set_demag(one, once=True)
+    S_once = once.heun(S0, 0, 1)
+    held = oracle_system(w.scaled(B=tuple(np.asarray(w.B) + Bd)))
+    S_held = held.heun(S0, 0, 1)
+    assert np.max(np.abs(S_once - S_held)) < 1e-13
+    each = oracle_system(w)
+    each.set_demag(one)
+    S_each = each.heun(S0, 0, 1)
+    assert np.max(np.abs(S_each - S_once)) > 1e3 * np.max(np.abs(S_once - S_held))
+    # several steps: the held field is re-evaluated at the start of each step
+    S2 = once.heun(S0, 0, 2)
+    Bd1 = oracle.demag_field(S_once, np.zeros(n, np.int32), (1, 1, 1), dd, w.mu_s)[:, 0]
+    S2_held = oracle_system(w.scaled(B=tuple(np.asarray(w.B) + Bd1))).heun(S_held, 1, 1)
+    assert np.max(np.abs(S2 - S2_held)) < 1e-12
