@@ -63,6 +63,9 @@ def parse():
                     default="track")
     ap.add_argument("--demag-cell", type=int, nargs=3, default=[4, 4, 3],
                     help="coarse cell of the demag and track_demag workloads, in lattice cells")
+    ap.add_argument("--demag-once", action="store_true",
+                    help="demag and track_demag workloads: the field evaluated once per step and "
+                         "held through both Heun stages (default: at both stages)")
     ap.add_argument("--window-demag", action="store_true",
                     help="multiscale workload: add the demagnetising field of the whole window "
                          "(regions and atoms as one mesh)")
@@ -308,6 +311,8 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps, workl
     tile = args.tile if tile is None else tile
     w, h, S0s, n_mag, n_sites, extra = build_workload(workload, prec, graph_steps,
                                                       args.demag_cell)
+    if workload in ("demag", "track_demag") and args.demag_once:
+        h.set_demag_reading(A.ASD_DEMAG_ONCE)
     if kern == A.ASD_KERNEL_AUTO:
         os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
         cache = (os.path.join(ROOT, "_build", "asd_tune_fresh.json") if args.retune
@@ -801,7 +806,10 @@ def main():
         t1, t0 = r["t"] / r["steps"], r0["t"] / r0["steps"]
         demag = {"cell": [cx, cy, cz], "mesh": list(mesh),
                  "padded_fft": [1 << (2 * n - 1 - 1).bit_length() if n > 1 else 1 for n in mesh],
-                 "evaluations_per_step": 2, "kernel": r["kname"], "step_ms": 1e3 * t1,
+                 "reading": "once per step, held through both stages" if args.demag_once
+                 else "at both Heun stages",
+                 "evaluations_per_step": 1 if args.demag_once else 2, "kernel": r["kname"],
+                 "step_ms": 1e3 * t1,
                  "step_without_demag_ms": 1e3 * t0, "kernel_without_demag": r0["kname"],
                  "ratio_to_step_without_demag": t1 / t0}
     if args.copy_calibration:

@@ -335,6 +335,18 @@ int asd_get_stream(asd_t *h, void **stream);
  * ASD_ESTATE when the handle was created without demag_cell. */
 int asd_demag_field(asd_t *h, double *per_cell, int32_t *mesh);
 
+/* When the demagnetising field is evaluated within a Heun step (Sec. II: the
+ * field of the window is refreshed every iteration).  ASD_DEMAG_EACH_STAGE
+ * (default): at both stages, from that stage's spins (S, then S').
+ * ASD_DEMAG_ONCE: once per step from the step's starting spins S, and the
+ * same field in both stages (an iteration read as a whole time step); the
+ * fused kernel then runs the step in one launch.  ASD_EINVAL for another
+ * value, ASD_ESTATE for a handle without demag_cell.  Drops captured
+ * graphs. */
+#define ASD_DEMAG_EACH_STAGE 0
+#define ASD_DEMAG_ONCE 1
+int asd_set_demag_reading(asd_t *h, int32_t reading);
+
 /* Step counter of the handle and window origin (in lattice columns) of
  * system sys, from the host copies (no synchronisation). */
 int asd_get_state(asd_t *h, int32_t sys, int64_t *step, int32_t *origin);

@@ -23,6 +23,7 @@ ASD_BC_OPEN, ASD_BC_PERIODIC, ASD_BC_TRACK = 0, 1, 2
 ASD_SPOT_NONE, ASD_SPOT_MOVING, ASD_SPOT_LOCKED = 0, 1, 2
 ASD_KERNEL_AUTO, ASD_KERNEL_PLAIN, ASD_KERNEL_FUSED = 0, 1, 2
 ASD_CONE_PRINTED, ASD_CONE_CAP = 0, 1
+ASD_DEMAG_EACH_STAGE, ASD_DEMAG_ONCE = 0, 1
 
 SYMBOLS = [
     "asd_workspace_bytes", "asd_create", "asd_destroy", "asd_set_field_temperature",
@@ -38,7 +39,7 @@ SYMBOLS = [
     "asd_mm_workspace_bytes", "asd_mm_create", "asd_mm_destroy", "asd_mm_set_field_temperature",
     "asd_mm_set_m", "asd_mm_get_m", "asd_mm_step", "asd_mm_get_step", "asd_mm_last_error",
     "asd_mm_set_face", "asd_mm_get_face", "asd_multiscale_step", "asd_multiscale_shift",
-    "asd_set_cone_reading", "asd_set_columns", "asd_msd_workspace_bytes", "asd_msd_create",
+    "asd_set_cone_reading", "asd_set_demag_reading", "asd_set_columns", "asd_msd_workspace_bytes", "asd_msd_create",
     "asd_msd_destroy", "asd_multiscale_step_demag", "asd_msd_fields",
     "asd_window_size", "asd_get_stream",
 ]
@@ -146,6 +147,7 @@ def lib():
         L.asd_multiscale_shift.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32,
                                            vp, vp]
         L.asd_set_cone_reading.argtypes = [h, C.c_int32]
+        L.asd_set_demag_reading.argtypes = [h, C.c_int32]
         L.asd_msd_workspace_bytes.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32,
                                               P(C.c_size_t)]
         L.asd_msd_create.argtypes = [h, C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp,
@@ -384,6 +386,11 @@ class Handle:
     def set_cone_reading(self, reading: int):
         """ASD_CONE_PRINTED (default) or ASD_CONE_CAP for the inverse transfer."""
         _check(lib().asd_set_cone_reading(self.h, reading), self.h)
+
+    def set_demag_reading(self, reading: int):
+        """ASD_DEMAG_EACH_STAGE (default): the demagnetising field at both Heun
+        stages; ASD_DEMAG_ONCE: once per step, held through both stages."""
+        _check(lib().asd_set_demag_reading(self.h, reading), self.h)
 
     def mc_sweep(self, n: int):
         """n Metropolis sweeps at each system's ambient temperature."""

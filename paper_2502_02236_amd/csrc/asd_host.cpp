@@ -390,16 +390,19 @@ static void fused_tiles_of(const asd_params *p, const asd_system_desc *d, int ti
     if (tz) *tz = (d->nz + len - 1) / len;
 }
 
-// partial-sum slots of the fused stage kernels of SC variant v: how many
-// tiles one coarse cell can meet along x, y and z
+// partial-sum slots of the fused kernels with the demagnetising field, SC
+// variant v (stage: the halo-free stage kernels, else the one-launch step):
+// how many tiles one coarse cell can meet along x, y and z
 static void stage_slots(const asd_params *p, const asd_system_desc *d, const int32_t *cell, int v,
-                        int *nsx, int *nsy, int *ns)
+                        int *nsx, int *nsy, int *ns, bool stage = true)
 {
     int bx, by, fx, fy, fz, len;
     fused_tile_interior(p->precision == ASD_FP64, v, &bx, &by, false);
-    bx += 2;  // the stage kernels' tiles have no halo
-    by += 2;
-    fused_tiles_of(p, d, v, &fx, &fy, &fz, &len, true);
+    if (stage) {  // the stage kernels' tiles have no halo
+        bx += 2;
+        by += 2;
+    }
+    fused_tiles_of(p, d, v, &fx, &fy, &fz, &len, stage);
     *nsx = (cell[0] - 1) / bx + 2;
     *nsy = (cell[1] - 1) / by + 2;
     const int nsz = fz > 1 ? (cell[2] - 1) / len + 2 : 1;
@@ -547,11 +550,12 @@ static Layout make_layout(const asd_params *p, const asd_system_desc *sys, int n
         // cell sums: one slot (cell-row kernels) or the fused stage kernels' partial slots
         int ns_max = 1;
         if (p->lattice == ASD_SC)
-            for (int v = 0; v < fused_count(false, p->precision == ASD_FP64); ++v) {
-                int nsx, nsy, ns;
-                stage_slots(p, &sys[0], p->demag_cell, v, &nsx, &nsy, &ns);
-                ns_max = std::max(ns_max, ns);
-            }
+            for (int v = 0; v < fused_count(false, p->precision == ASD_FP64); ++v)
+                for (bool stage : {true, false}) {
+                    int nsx, nsy, ns;
+                    stage_slots(p, &sys[0], p->demag_cell, v, &nsx, &nsy, &ns, stage);
+                    ns_max = std::max(ns_max, ns);
+                }
         for (int b = 0; b < 2; ++b)
             L.off_dcs[b] = take((size_t)n_sys * 3 * ns_max * g.ncell * elem);
         L.dcs_bytes = (size_t)n_sys * 3 * ns_max * g.ncell * elem;
@@ -661,6 +665,7 @@ static void drop_graphs(asd_t *h)
 
 static const char *fused_unsupported(const asd_t *h);
 static const char *cell_rows_unsupported(const asd_t *h);
+static int setup_fused_tiles(asd_t *h, int v);
 
 int asd_create(const asd_params *p, const asd_system_desc *sys, int32_t n_sys, void *workspace,
                size_t workspace_bytes, void *stream, asd_t **out)
@@ -1553,6 +1558,19 @@ int asd_thermalise_columns(asd_t *h, int32_t s, int32_t x0, int32_t ncols, int32
     return ASD_OK;
 }
 
+int asd_set_demag_reading(asd_t *h, int32_t reading)
+{
+    if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
+    if (reading != ASD_DEMAG_EACH_STAGE && reading != ASD_DEMAG_ONCE)
+        return fail(h, ASD_EINVAL, "reading must be ASD_DEMAG_EACH_STAGE or ASD_DEMAG_ONCE");
+    if (!h->dm.on) return fail(h, ASD_ESTATE, "the handle has no demagnetising field");
+    h->dm.once = reading == ASD_DEMAG_ONCE ? 1 : 0;
+    drop_graphs(h);
+    // the fused kernels' tiles and partial-sum slots depend on the reading
+    if (h->kernel == ASD_KERNEL_FUSED) return setup_fused_tiles(h, h->tile_cfg);
+    return ASD_OK;
+}
+
 int asd_set_cone_reading(asd_t *h, int32_t reading)
 {
     if (!h) return fail(nullptr, ASD_EINVAL, "NULL handle");
@@ -1827,7 +1845,7 @@ static int setup_fused_tiles(asd_t *h, int v)
     std::vector<int32_t> map;
     for (size_t s = 0; s < h->sys.size(); ++s) {
         int fx, fy, fz, lz;
-        fused_tiles_of(&h->p, &h->sys[s].desc, v, &fx, &fy, &fz, &lz, h->dm.on != 0);
+        fused_tiles_of(&h->p, &h->sys[s].desc, v, &fx, &fy, &fz, &lz, h->dm.on && !h->dm.once);
         SysDev &d = h->dev[s];
         d.ftile_base = (int32_t)map.size();
         d.ftiles_x = fx;
@@ -1844,7 +1862,7 @@ static int setup_fused_tiles(asd_t *h, int v)
     if (h->dm.on) {
         // partial-sum slots of the stage kernels; slots no tile writes stay zero
         int nsx, nsy, ns;
-        stage_slots(&h->p, &h->sys[0].desc, h->p.demag_cell, v, &nsx, &nsy, &ns);
+        stage_slots(&h->p, &h->sys[0].desc, h->p.demag_cell, v, &nsx, &nsy, &ns, !h->dm.once);
         h->dm.nsx = nsx;
         h->dm.nsy = nsy;
         h->dm.ns = ns;
@@ -1915,6 +1933,9 @@ int asd_variant_name(asd_t *h, char *buf, size_t len)
             if (hs.desc.bc_z == ASD_BC_PERIODIC) zper = true;
         if (l10)
             snprintf(tmp, sizeof tmp, "k_fused_l10<%s, %d, %d, %d>", T, f.txe, f.waves, f.rows);
+        else if (h->dm.on && h->dm.once)  // one launch, the field of S held (open z only)
+            snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d, false, 3>", T, f.txe, f.waves,
+                     f.rows);
         else if (h->dm.on)  // the predictor and corrector stages (open z only)
             snprintf(tmp, sizeof tmp, "k_fused_sc<%s, %d, %d, %d, false, 1>+k_fused_sc<%s, %d, %d, %d, false, 2>",
                      T, f.txe, f.waves, f.rows, T, f.txe, f.waves, f.rows);
@@ -1951,7 +1972,8 @@ static std::string tune_key(const asd_t *h)
                        h->p.precision, d.nx, d.ny, d.nz, h->sys.size(), (long long)sites, tab);
     // the demagnetising field changes the candidates and their cost
     if (h->dm.on && len > 0 && len < (int)sizeof buf)
-        snprintf(buf + len, sizeof buf - len, "_dm%dx%dx%d", h->dm.cx, h->dm.cy, h->dm.cz);
+        snprintf(buf + len, sizeof buf - len, "_dm%dx%dx%d%s", h->dm.cx, h->dm.cy, h->dm.cz,
+                 h->dm.once ? "_once" : "");
     return buf;
 }
 

@@ -98,6 +98,7 @@ struct DemagDev {
     void *cs[2];
     int32_t cr_cells, cr_segs;
     int32_t ns, nsx, nsy;
+    int32_t once;             // 1: the field of S only, held through both stages
     const void *K;            // tensor spectrum, octant [6][Py/2+1][Px/2+1][Pz/2+1]
                               // (yzf: [Px/2+1][6][ncz][Py/2+1], see demag_mixed)
     const void *tw[3];        // twiddles exp(-2 pi i t / P), t < P / 2, per axis

@@ -212,13 +212,15 @@ def test_heun_with_demag_matches_oracle(name, w, cell, n_sys, prec, variant):
     h.close()
 
 
-@pytest.mark.parametrize("kernel,variant", [(A.ASD_KERNEL_PLAIN, 0), (A.ASD_KERNEL_PLAIN, 2),
-                                            (A.ASD_KERNEL_FUSED, 0)],
-                         ids=["recompute", "cellrows", "fused_stages"])
+@pytest.mark.parametrize("kernel,variant,once", [(A.ASD_KERNEL_PLAIN, 0, False),
+                                                 (A.ASD_KERNEL_PLAIN, 2, False),
+                                                 (A.ASD_KERNEL_FUSED, 0, False),
+                                                 (A.ASD_KERNEL_FUSED, 0, True)],
+                         ids=["recompute", "cellrows", "fused_stages", "fused_once"])
 @pytest.mark.parametrize("prec,cell", [(A.ASD_FP64, (5, 4, 5)), (A.ASD_FP32, (5, 4, 5)),
                                        (A.ASD_FP64, (4, 3, 2)), (A.ASD_FP32, (7, 6, 3))],
                          ids=["fp64_5x4x5", "fp32_5x4x5", "fp64_4x3x2", "fp32_7x6x3_ragged"])
-def test_track_with_demag_and_shifts(prec, cell, kernel, variant):
+def test_track_with_demag_and_shifts(prec, cell, kernel, variant, once):
     """Moving window: the demagnetising mesh moves with the window and the frozen
     track's stray field is recomputed after every shift; graph-captured segments
     (the demag kernels are plain launches, no memset nodes) replayed."""
@@ -227,6 +229,8 @@ def test_track_with_demag_and_shifts(prec, cell, kernel, variant):
     steps = 40
     h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10, kernel=kernel)
     h.set_variant(kernel, variant)
+    if once:
+        h.set_demag_reading(A.ASD_DEMAG_ONCE)
     lab = h.labels()
     S0 = random_state(w, lab, 5)
     h.set_spins(S0)
@@ -242,7 +246,7 @@ def test_track_with_demag_and_shifts(prec, cell, kernel, variant):
     done = 0
     for at, cols in shifts + [(steps, 0)]:
         dn, dd, dcell = demag_cells(w, cell, origin=org)
-        sysm.set_demag((dn, dd, dcell), stray=track_stray(w, cell, org, S))
+        sysm.set_demag((dn, dd, dcell), stray=track_stray(w, cell, org, S), once=once)
         S = sysm.heun(S, done, at - done)
         done = at
         if cols:
@@ -344,6 +348,87 @@ def test_fused_stages_match_two_pass_over_100_steps(prec):
     bar = 1e-12 if prec == A.ASD_FP64 else 1e-4
     say(f"[fused stages vs two-pass] prec={prec}: max |dS| after 100 steps = {err:.3e}")
     assert err <= bar
+
+
+# the field evaluated once per step and held through both stages:
+# (name, workload, coarse cell, precision, kernel, variant)
+ONCE_CASES = [
+    ("sc_fp64_recompute", sc_slab(), (4, 4, 2), A.ASD_FP64, A.ASD_KERNEL_PLAIN, 0),
+    ("sc_fp64_cellrows", sc_slab(), (4, 4, 2), A.ASD_FP64, A.ASD_KERNEL_PLAIN, 2),
+    ("sc_fp64_fused_chunks", sc_slab(nz=20), (4, 3, 3), A.ASD_FP64, A.ASD_KERNEL_FUSED, 0),
+    ("sc_fp32_fused_wide", sc_slab(nz=20), (4, 3, 3), A.ASD_FP32, A.ASD_KERNEL_FUSED, 14),
+    ("sc_fp32_fused_narrow", sc_slab(), (5, 4, 2), A.ASD_FP32, A.ASD_KERNEL_FUSED, 2),
+    ("l10_fp64_cellrows", l10_slab(), (3, 3, 2), A.ASD_FP64, A.ASD_KERNEL_PLAIN, 2),
+]
+
+
+@pytest.mark.parametrize("name,w,cell,prec,kernel,variant", ONCE_CASES,
+                         ids=[c[0] for c in ONCE_CASES])
+def test_demag_once_per_step_matches_oracle(name, w, cell, prec, kernel, variant):
+    """ASD_DEMAG_ONCE against the oracle's held field: the fused kernel runs the
+    step in one launch with the field of S and writes the cell sums of the new
+    spins for the next step's field; graph segments of ten steps."""
+    steps = 30
+    h = bridge.make_handle(w, prec, demag_cell=cell, graph_steps=10, kernel=kernel)
+    h.set_variant(kernel, variant)
+    h.set_demag_reading(A.ASD_DEMAG_ONCE)
+    if kernel == A.ASD_KERNEL_FUSED:
+        assert h.variant_name().endswith(", 3>")
+    lab = h.labels()
+    S0 = random_state(w, lab, 61)
+    h.set_spins(S0)
+    h.step(steps)
+    dn, dd, dcell = demag_cells(w, cell)
+    sysm = oracle_system(w, labels=oracle_labels(w))
+    sysm.set_demag((dn, dd, dcell), once=True)
+    ref = sysm.heun(S0, 0, steps)
+    err = float(np.max(np.abs(h.get_spins().astype(np.float64) - ref)))
+    say(f"[demag once] {name} ({h.variant_name()}): max |dS| = {err:.3e}")
+    assert err <= SPIN_TOL[prec], (name, err)
+    # the reading matters: the field at both stages lands far outside the FP64 bar
+    if prec == A.ASD_FP64:
+        each = oracle_system(w, labels=oracle_labels(w))
+        each.set_demag((dn, dd, dcell))
+        assert float(np.max(np.abs(each.heun(S0, 0, steps) - ref))) > 100 * max(err, 1e-13)
+    h.close()
+
+
+def test_demag_once_fused_matches_two_pass_over_100_steps():
+    """FP64: the one-launch fused step with the held field against the two-pass
+    kernels with the same reading, 100 steps (within 1e-12); then back to the
+    field at both stages on the same handle."""
+    w = sc_slab(nx=150, ny=13, nz=9)
+    cell = (2, 3, 2)
+    out = {}
+    for kernel in (A.ASD_KERNEL_PLAIN, A.ASD_KERNEL_FUSED):
+        h = bridge.make_handle(w, A.ASD_FP64, demag_cell=cell, graph_steps=10, kernel=kernel)
+        h.set_variant(kernel, 0)
+        h.set_demag_reading(A.ASD_DEMAG_ONCE)
+        S0 = random_state(w, h.labels(), 79)
+        h.set_spins(S0)
+        h.step(95)
+        h.step(5)
+        out[kernel] = h.get_spins().astype(np.float64)
+        h.set_demag_reading(A.ASD_DEMAG_EACH_STAGE)
+        assert "1>+k_fused_sc" in h.variant_name() or kernel == A.ASD_KERNEL_PLAIN
+        h.close()
+    err = float(np.max(np.abs(out[A.ASD_KERNEL_FUSED] - out[A.ASD_KERNEL_PLAIN])))
+    say(f"[demag once fused vs two-pass] max |dS| after 100 steps = {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_demag_reading_errors():
+    w = sc_slab()
+    h = bridge.make_handle(w, A.ASD_FP32, demag_cell=(2, 2, 2))
+    with pytest.raises(A.AsdError) as e:
+        h.set_demag_reading(2)
+    assert e.value.code == A.ASD_EINVAL
+    h.close()
+    h = bridge.make_handle(w, A.ASD_FP32)
+    with pytest.raises(A.AsdError) as e:
+        h.set_demag_reading(A.ASD_DEMAG_ONCE)
+    assert e.value.code == A.ASD_ESTATE
+    h.close()
 
 
 def test_track_stray_field_at_the_largest_track():
