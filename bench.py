@@ -162,12 +162,19 @@ def alu_ops_per_site(precision: str, workload: str):
 
 
 def kernel_sources_hash():
+    """Hash of the step kernels' source code: the files the step kernels are
+    compiled from, with comments and blank space removed (a comment edit does
+    not change the kernels, so it does not retire the committed counters)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("asd_device.h", "asd_step.inc", "asd_fused.inc", "asd_fused_l10.inc", "asd_variants.h",
               "asd_internal.h"):
-        with open(os.path.join(ROOT, "paper_2502_02236_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2502_02236_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -2,20 +2,26 @@
 // cells of Eq. 6, by zero-padded FFT convolution with the spectrum of
 // Newell's cell-averaged tensor.
 //
-// Per evaluation, for every system of the handle (grid y):
+// Per evaluation, for every system of the handle:
 //   gather_x  one workgroup per (y, z) row of coarse cells: sum the spins of
 //             each cell (non-magnetic sites hold 0), FFT the three component
-//             rows along x (zero-padded to Px)
-//   y pass    FFT along y of the ncz planes that hold data (zero-padded to Py)
-//   z pass    per (kx, ky): FFT along z, multiply by the 3x3 tensor
+//             rows along x (zero-padded to Px); or cells_x: the same from
+//             cell sums the step kernels formed
+//   yz        (ncz <= 16, 12 in FP64) one workgroup per kx column: FFT along
+//             y, the convolution along z as direct sums over the planes with
+//             the tensor transformed along x and y only, inverse FFT along y;
+//   or, for thicker meshes, three passes:
+//     y pass  FFT along y of the ncz planes that hold data (zero-padded to Py)
+//     z pass  per (kx, ky): FFT along z, multiply by the 3x3 tensor
 //             spectrum, inverse FFT along z, keep the ncz planes of the mesh
-//   y pass    inverse FFT along y, keep the ncy rows of the mesh
+//     y pass  inverse FFT along y, keep the ncy rows of the mesh
 //   x_out     inverse FFT along x, keep the ncx cells: the field per cell
 // The x transform of the real cell sums is Hermitian, X(Px - k) = conj X(k),
 // so only kx = 0 .. Px/2 (Pxh columns) is kept through the y and z passes and
 // the full row is rebuilt before the inverse x transform.
-// The spectrum carries -mu0 mu_s / (V Px Py Pz), so the result is the flux
-// density mu0 H_d in tesla from plain spin sums.  Every transform is a
+// The spectrum carries -mu0 mu_s / (V Px Py Pz) (the mixed table of the yz
+// pass -mu0 mu_s / (V Px Py)), so the result is the flux density mu0 H_d in
+// tesla from plain spin sums.  Every transform is a
 // Stockham FFT over a batch of lines held in LDS (ping-pong buffers): radix-4
 // stages, after one radix-2 stage when log2 of the length is odd, one barrier
 // per stage; the padded sizes are powers of two.
