@@ -307,7 +307,7 @@ def clock_ramp(torch, h, S0s, graph_steps, seconds=RAMP_S):
 
 
 def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps, workload=None,
-            tile=None):
+            tile=None, demag_once=None):
     import torch
     from paper_2502_02236_amd import asd as A
 
@@ -318,7 +318,8 @@ def gpu_run(args, precision_name, kernel_name, steps, warmup, graph_steps, workl
     tile = args.tile if tile is None else tile
     w, h, S0s, n_mag, n_sites, extra = build_workload(workload, prec, graph_steps,
                                                       args.demag_cell)
-    if workload in ("demag", "track_demag") and args.demag_once:
+    once = args.demag_once if demag_once is None else demag_once
+    if workload in ("demag", "track_demag") and once:
         h.set_demag_reading(A.ASD_DEMAG_ONCE)
     if kern == A.ASD_KERNEL_AUTO:
         os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
@@ -819,6 +820,14 @@ def main():
                  "step_ms": 1e3 * t1,
                  "step_without_demag_ms": 1e3 * t0, "kernel_without_demag": r0["kname"],
                  "ratio_to_step_without_demag": t1 / t0}
+        if not args.demag_once and not args.no_extras:
+            # beside it, the other reading: the field held through the step
+            r2 = gpu_run(args, args.precision, args.kernel, args.steps, args.warmup, g,
+                         demag_once=True)
+            t2 = r2["t"] / r2["steps"]
+            demag["held_field"] = {"reading": "once per step, held through both stages",
+                                   "kernel": r2["kname"], "step_ms": 1e3 * t2,
+                                   "ratio_to_step_without_demag": t2 / t0}
     if args.copy_calibration:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
