@@ -68,21 +68,28 @@ __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
 // (j / Ns) R Ns + k + r Ns; the output ends in natural order.  One radix-2
 // stage when lp is odd, radix-4 stages after it.  Returns the buffer
 // holding the result.  Callers synchronise before; every stage ends with a
-// barrier.
+// barrier.  Between stages of lines of 64 points or more, point e of a line
+// sits at e ^ ((e >> 2) & 31): the stages' strided writes (a lane's points
+// 4 Ns apart) then fall on distinct LDS banks; the first stage reads and the
+// last one writes the natural order, so callers never see the permutation.
+__device__ __forceinline__ int fft_swz(int e, bool on) { return on ? e ^ ((e >> 2) & 31) : e; }
+
 template <typename T, bool INV>
 __device__ Cx<T> *fft_lines(Cx<T> *x, Cx<T> *y, int nl, int lp, int ls,
                             const Cx<T> *__restrict__ tw)
 {
     if (lp == 0) return x;
     const int P = 1 << lp, half = P >> 1;
+    const bool sw = lp >= 6;
     int Ns = 1;
     if (lp & 1) {
+        const bool wsw = sw && lp > 1;
         for (int q = threadIdx.x; q < nl * half; q += blockDim.x) {
             const int line = q >> (lp - 1), j = q & (half - 1);
             const Cx<T> a = x[line * ls + j], b = x[line * ls + j + half];
-            Cx<T> *yd = y + line * ls + 2 * j;
-            yd[0] = Cx<T>{a.re + b.re, a.im + b.im};
-            yd[1] = Cx<T>{a.re - b.re, a.im - b.im};
+            Cx<T> *yd = y + line * ls;
+            yd[fft_swz(2 * j, wsw)] = Cx<T>{a.re + b.re, a.im + b.im};
+            yd[fft_swz(2 * j + 1, wsw)] = Cx<T>{a.re - b.re, a.im - b.im};
         }
         __syncthreads();
         Cx<T> *t = x;
@@ -94,24 +101,28 @@ __device__ Cx<T> *fft_lines(Cx<T> *x, Cx<T> *y, int nl, int lp, int ls,
     for (; Ns < P; Ns <<= 2) {
         const int lns = __ffs(Ns) - 1;
         const int tstep = lp - 2 - lns;  // log2 of P / (4 Ns)
+        const bool rsw = sw && Ns > 1, wsw = sw && 4 * Ns < P;
         for (int q = threadIdx.x; q < nl * quarter; q += blockDim.x) {
             const int line = q >> (lp - 2), j = q & (quarter - 1);
             const int k = j & (Ns - 1);
-            const Cx<T> *xs = x + line * ls + j;
-            const Cx<T> v0 = xs[0];
-            const Cx<T> v1 = cmul(xs[quarter], twiddle<T, INV>(tw, k << tstep, half));
-            const Cx<T> v2 = cmul(xs[2 * quarter], twiddle<T, INV>(tw, (2 * k) << tstep, half));
-            const Cx<T> v3 = cmul(xs[3 * quarter], twiddle<T, INV>(tw, (3 * k) << tstep, half));
+            const Cx<T> *xs = x + line * ls;
+            const Cx<T> v0 = xs[fft_swz(j, rsw)];
+            const Cx<T> v1 = cmul(xs[fft_swz(j + quarter, rsw)], twiddle<T, INV>(tw, k << tstep, half));
+            const Cx<T> v2 =
+                cmul(xs[fft_swz(j + 2 * quarter, rsw)], twiddle<T, INV>(tw, (2 * k) << tstep, half));
+            const Cx<T> v3 =
+                cmul(xs[fft_swz(j + 3 * quarter, rsw)], twiddle<T, INV>(tw, (3 * k) << tstep, half));
             const Cx<T> a0{v0.re + v2.re, v0.im + v2.im}, a1{v0.re - v2.re, v0.im - v2.im};
             const Cx<T> a2{v1.re + v3.re, v1.im + v3.im};
             const T dr = v1.re - v3.re, di = v1.im - v3.im;
             // (v1 - v3) times -i (forward) or +i (inverse)
             const Cx<T> a3 = INV ? Cx<T>{-di, dr} : Cx<T>{di, -dr};
-            Cx<T> *yd = y + line * ls + ((j >> lns) << (lns + 2)) + k;
-            yd[0] = Cx<T>{a0.re + a2.re, a0.im + a2.im};
-            yd[Ns] = Cx<T>{a1.re + a3.re, a1.im + a3.im};
-            yd[2 * Ns] = Cx<T>{a0.re - a2.re, a0.im - a2.im};
-            yd[3 * Ns] = Cx<T>{a1.re - a3.re, a1.im - a3.im};
+            Cx<T> *yd = y + line * ls;
+            const int e = ((j >> lns) << (lns + 2)) + k;
+            yd[fft_swz(e, wsw)] = Cx<T>{a0.re + a2.re, a0.im + a2.im};
+            yd[fft_swz(e + Ns, wsw)] = Cx<T>{a1.re + a3.re, a1.im + a3.im};
+            yd[fft_swz(e + 2 * Ns, wsw)] = Cx<T>{a0.re - a2.re, a0.im - a2.im};
+            yd[fft_swz(e + 3 * Ns, wsw)] = Cx<T>{a1.re - a3.re, a1.im - a3.im};
         }
         __syncthreads();
         Cx<T> *t = x;
